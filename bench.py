@@ -1,0 +1,172 @@
+"""Benchmark of the visibility simulator hot path on one MI355X.
+
+Workload (the metric's configuration): 128-antenna hexagonal array with 2
+feeds x 2 E-field axes, 50 000 point sources with power-law fluxes and
+spectral indices, 32 LSTs over 24 h x 16 channels 100-200 MHz, a dipole-like
+Jones beam on a 0.5 deg az/za grid with bicubic interpolation.  All inputs are
+seeded synthetic arrays already resident in HBM when timing starts.
+
+One step = one matvis_simulate call over every (t, nu) instance: rotation,
+horizon compaction, beam interpolation, Z formation and V = Z Z^H, i.e. every
+step of Alg. 2 for the whole batch, replayed from its captured hipGraph.
+
+metric: src * ant-pair * (t, nu) / s = n_src * n_ant (n_ant + 1) / 2 * n_t * n_nu / T.
+
+Also reported on the same JSON line:
+* roofline: the Z Z^H product kernel, timed live with HIP events around each
+  of its launches (a separate profiled pass over the same steps), algorithmic
+  flops 4 N (N + 1) K per instance (x 3 products on BF16X3) against the MFMA
+  peak of the arithmetic's dtype;
+* cpu_baseline: the FP64 direct-sum oracle on one full (t, nu) instance on the
+  host cores, and the error of the GPU result on that instance.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}  # dense MFMA, MI355X
+HBM_GBS = 8000.0
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n-src", type=int, default=None, help="shrink the workload (smoke runs only)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the simulator shards (t, nu) instances "
+              f"across GPUs with no communication, but multi-GPU runs are not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2312_09763_amd import matvis as mv
+    from paper_2312_09763_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prec = args.precision
+    wl = synth.workload(2, n_src=args.n_src)
+    log(f"workload2: n_ant={wl.n_ant} n_src={wl.n_src} n_time={wl.n_time} n_freq={wl.n_freq} precision={prec}")
+    cfg = mv.config_for(wl, prec)
+    ctx = mv.Context(cfg)
+    d = mv.device_inputs(wl, prec)
+    vis = torch.empty((wl.n_time, wl.n_freq, wl.n_ant, wl.n_ant, wl.n_feed, wl.n_feed), dtype=ctx.complex_dtype,
+                      device="cuda")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        ctx.simulate(**d, vis=vis)
+    ctx.finish()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.simulate(**d, vis=vis)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ctx.finish()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    units = wl.work_units()
+    value = units / (ms_step / 1e3)
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f} ms/step)")
+
+    # ---- live per-kernel timing for the roofline (same steps, launched directly)
+    ctx.profile(True)
+    for _ in range(args.profile_steps):
+        ctx.simulate(**d, vis=vis)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.finish()
+    _, count, _, _ = ctx.step_sky(d["lsts"], d["src_radec"])
+    counts = count.cpu().numpy().astype(np.int64)
+    N = wl.n_ant * wl.n_feed
+    K = wl.n_ax * counts  # per time
+    useful_flops_step = float(np.sum(4.0 * N * (N + 1) * K) * wl.n_freq)
+    herk_ms, herk_n = prof["herk"]
+    herk_ms_launch = herk_ms / max(herk_n, 1)
+    flops_launch = useful_flops_step * PRODUCTS[prec] * args.profile_steps / max(herk_n, 1)
+    achieved = flops_launch / (herk_ms_launch / 1e3) / 1e12
+    zform_ms, zform_n = prof["zform"]
+    z_bytes_step = float(np.sum(N * (np.ceil(wl.n_ax * counts / 64.0) * 64) * 8.0) * wl.n_freq)
+    steps_ms = {k: round(v[0] / args.profile_steps, 4) for k, v in prof.items()}
+    log("per-step device ms:", steps_ms)
+
+    # ---- CPU baseline: the FP64 oracle on one full instance, and the GPU error there
+    cpu = None
+    err = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import metrics
+        t, f = 0, 0
+        grid = wl.beam if prec == "fp64" else wl.beam.astype(np.complex64).astype(np.complex128)
+        c0 = time.perf_counter()
+        Vref = oracle.simulate(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, wl.flux, grid, wl.latitude, wl.dza,
+                               wl.daz, wl.interp, instances=[(t, f)])
+        cdt = time.perf_counter() - c0
+        sample_units = wl.n_src * wl.n_ant * (wl.n_ant + 1) / 2.0
+        cpu = {"value": sample_units / cdt, "unit": "src*ant-pair*(t,nu)/s", "cores": oracle.get_threads(),
+               "kind": "oracle",
+               "sample": f"one full (t, nu) instance (t=0, nu={wl.freqs[f] / 1e6:.1f} MHz) of the same workload, "
+                         f"all {wl.n_ant}x{wl.n_ant} antenna pairs, FP64 direct sum, {cdt:.1f} s"}
+        Vg = vis[t, f].cpu().numpy().astype(np.complex128)[None]
+        err = {"err_F": float(metrics.err_f(Vg, Vref).max()), "err_CS": float(metrics.err_cs(Vg, Vref).max()),
+               "instance": [t, f]}
+        log(f"oracle: {cdt:.1f} s on {oracle.get_threads()} threads; GPU error on that instance {err}")
+
+    out = {
+        "metric": "src*ant-pair*(t,nu)/s",
+        "value": value,
+        "unit": "src*ant-pair*(t,nu)/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3 (f32 accumulate)"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "128-antenna polarised hex array, 50000 point sources, 32 LSTs x 16 channels "
+                               "100-200 MHz, dipole Jones beam 0.5 deg grid bicubic",
+                   "n_ant": wl.n_ant, "n_feed": wl.n_feed, "n_ax": wl.n_ax, "n_src": wl.n_src,
+                   "n_time": wl.n_time, "n_freq": wl.n_freq, "precision": prec},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
+                     "kernel": "k_herk", "launch_ms": herk_ms_launch, "flops_per_launch": flops_launch,
+                     "useful_tflops": achieved / PRODUCTS[prec]},
+        "zform": {"achieved_GBps": z_bytes_step * args.profile_steps / (zform_ms / 1e3) / 1e9 if zform_ms else None,
+                  "peak_GBps": HBM_GBS},
+        "step_ms": steps_ms,
+        "cpu_baseline": cpu,
+        "error_vs_oracle": err,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

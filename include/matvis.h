@@ -1,0 +1,199 @@
+/*
+ * matvis.h -- C ABI of the MI355X (gfx950) matrix-based visibility simulator.
+ *
+ * The library evaluates the point-source RIME of arXiv:2312.09763 the way its
+ * Sec. 3.5 (Alg. 2) lays it out, for many (time, frequency) instances at once:
+ *   (i)   rotate sources to topocentric ENU with R(t) of Eq. (rotation) and cut
+ *         those at or below the horizon (U <= 0), order-preserving compaction;
+ *   (ii)  interpolate the beam (Jones terms) at the visible sources' (za, az)
+ *         on an az/za grid whose pole is the zenith (Sec. 3.4);
+ *   (iii) antenna phase exp(-2 pi i nu x_a . s / c) (the fringe factorisation
+ *         of Sec. 3.2), with FP64 range reduction of the argument;
+ *   (iv)  Z[(a,p),(n,k)] = sqrt(I_n) A_{beam(a),p,k}(n) F_a(n)  (Eq. littlez);
+ *   (v)   V = Z Z^H  (Eq. zz), lower-triangle tiles on MFMA, Hermitian fill.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers (HIP global memory) unless the
+ *     comment says host.  The caller owns every input and output buffer; the
+ *     context owns all scratch.  No pointer is kept after a call returns
+ *     except for the asynchronous use on `stream` (a hipStream_t passed as
+ *     void*, NULL = the null stream) until the stream is synchronised.
+ *   - Angles are radians, positions metres (ENU), frequencies Hz, fluxes Jy.
+ *   - Complex numbers are interleaved (re, im): complex128 = 2 doubles,
+ *     complex64 = 2 floats.
+ *   - Argument errors return MATVIS_EINVAL synchronously and leave the context
+ *     usable; HIP failures return MATVIS_EHIP; data errors found on the device
+ *     (negative or non-finite flux, non-finite antenna positions) are reported
+ *     by matvis_finish as MATVIS_EDATA (the visibilities are then undefined).
+ *     No entry point aborts, exits or throws.  matvis_last_error gives text.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef MATVIS_H
+#define MATVIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct matvis_ctx matvis_ctx;
+
+typedef enum {
+    MATVIS_OK = 0,
+    MATVIS_EINVAL = -1,       /* bad argument or shape */
+    MATVIS_ENOMEM = -2,       /* device allocation failed */
+    MATVIS_EHIP = -3,         /* a HIP runtime call failed */
+    MATVIS_EUNSUPPORTED = -4, /* valid but unsupported combination */
+    MATVIS_ESTATE = -5,       /* call not valid in the context's state */
+    MATVIS_EDATA = -6         /* invalid input values detected on the device */
+} matvis_status;
+
+/* Arithmetic of step (v), V = Z Z^H.
+ *   FP64  : complex128 beams, Z, products and output;
+ *   FP32  : complex64 beams and Z, FP32 MFMA products accumulated in FP32
+ *           over bounded source chunks, chunks combined in FP64, complex64 out;
+ *   BF16X3: Z in FP32 split into bf16 hi + lo parts, V ~ hi hi^T + hi lo^T +
+ *           lo hi^T on bf16 MFMA with FP32 accumulation, complex64 out.
+ * In every mode the rotation and the phase range reduction are FP64. */
+typedef enum { MATVIS_FP64 = 0, MATVIS_FP32 = 1, MATVIS_BF16X3 = 2 } matvis_precision;
+
+/* Step (ii): beam evaluation at the visible sources. */
+typedef enum {
+    MATVIS_BEAM_BILINEAR = 0,  /* bilinear on the az/za grid */
+    MATVIS_BEAM_BICUBIC = 1,   /* Keys cubic convolution (a = -1/2), Keys' end rows in za */
+    MATVIS_BEAM_SURROGATE = 2  /* learned Fourier-feature network (see matvis_set_surrogate) */
+} matvis_beam_mode;
+
+/* Problem geometry and capacities, fixed for the context's lifetime.
+ * Beam grid geometry: za_j = j * dza_rad for j < n_za (the last row is the
+ * horizon, (n_za - 1) * dza_rad = pi/2); az_k = k * daz_rad, periodic with
+ * n_az * daz_rad = 2 pi; az is measured from North through East. */
+typedef struct {
+    int32_t n_ant;        /* antennas (Sec. 3.5 input D) */
+    int32_t n_feed;       /* feeds per antenna, 1 or 2 (Sec. 3.1) */
+    int32_t n_ax;         /* E-field axes, 1 or 2 (Sec. 3.1) */
+    int32_t n_beam;       /* unique beams (Sec. 3.5 inputs A and a_i) */
+    int64_t max_src;      /* largest n_src a simulate call may pass */
+    int32_t max_time;     /* largest n_time */
+    int32_t max_freq;     /* largest n_freq */
+    double latitude_rad;  /* l in Eq. (rotation) */
+    int32_t precision;    /* matvis_precision */
+    int32_t beam_mode;    /* matvis_beam_mode */
+    int32_t n_za, n_az;   /* beam grid size (ignored for the surrogate) */
+    double dza_rad, daz_rad;
+    int64_t src_chunk;    /* sources per chunk (Sec. 6.4 chunking); 0 = automatic */
+    int32_t batch_time;   /* times per device batch; 0 = automatic */
+    int32_t batch_freq;   /* frequencies per device batch; 0 = automatic */
+    int32_t flags;        /* MATVIS_FLAG_* bits */
+} matvis_config;
+
+#define MATVIS_FLAG_NO_GRAPH 1 /* launch kernels directly instead of replaying a captured hipGraph */
+
+/* Create a context on the current HIP device and allocate all scratch for the
+ * capacities in *cfg.  Returns MATVIS_EINVAL for inconsistent sizes (n_feed or
+ * n_ax not in {1, 2}, non-positive counts, grid smaller than 3 x 3 or whose
+ * spacing does not span 0..pi/2 and 0..2 pi), MATVIS_ENOMEM if the device
+ * cannot hold the scratch.  *out is NULL on failure. */
+matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out);
+
+/* Simulate every (t, f) instance, Alg. 2 steps (i)-(v).
+ *   antpos    [n_ant][3] double, ENU metres (Sec. 3.5 input D).  Only
+ *             differences matter; the library centres them on their mean.
+ *   beam_idx  [n_ant] int32 in [0, n_beam) or NULL (all 0)  (input a_i).
+ *   freqs     [n_freq] double, Hz, n_freq <= max_freq.
+ *   lsts      [n_time] double, local sidereal time in radians; R(t) of
+ *             Eq. (rotation) is built on the device with hour angle H = -LST.
+ *   src_radec [2][n_src] double: row 0 right ascension, row 1 declination
+ *             (Eq. xeq is evaluated on the device).  n_src <= max_src.
+ *   src_flux  [n_freq][n_src] double, Stokes I per channel, >= 0 (input I).
+ *   beam_grid [n_beam][n_freq][n_feed][n_ax][n_za][n_az] complex, complex128
+ *             when precision is FP64 else complex64; NULL for the surrogate.
+ *   vis       [n_time][n_freq][n_ant][n_ant][n_feed][n_feed] complex,
+ *             complex128 for FP64 else complex64, fully written:
+ *             vis[t][f][a][b][p][q] = sum_n sum_k Z[(a,p),(n,k)] conj(Z[(b,q),(n,k)]),
+ *             exactly Hermitian (vis[b][a][q][p] = conj vis[a][b][p][q]).
+ *   stream    hipStream_t as void*.
+ * The call is asynchronous: it enqueues work on `stream` and returns. */
+matvis_status matvis_simulate(matvis_ctx *ctx, const double *antpos, const int32_t *beam_idx, const double *freqs,
+                              int32_t n_freq, const double *lsts, int32_t n_time, const double *src_radec,
+                              int64_t n_src, const double *src_flux, const void *beam_grid, void *vis, void *stream);
+
+/* Synchronise the last stream used and report deferred device-side errors:
+ * MATVIS_EDATA for invalid input values, MATVIS_EHIP for asynchronous HIP
+ * failures.  Clears the device error flags. */
+matvis_status matvis_finish(matvis_ctx *ctx);
+
+/* Text of the last error on this context (never NULL; "" when none).  Valid
+ * until the next call on the context. */
+const char *matvis_last_error(const matvis_ctx *ctx);
+
+/* Name of a status code. */
+const char *matvis_status_string(int32_t status);
+
+/* Release the context and all its device memory (after synchronising). */
+void matvis_destroy(matvis_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Per-step timing (the paper times each step of Alg. 2 separately, Sec. 6.1).
+ * While enabled, matvis_simulate launches its kernels directly (no graph) and
+ * brackets every launch of each step with a pair of HIP events on the
+ * caller's stream.  matvis_profile_read synchronises those events, writes the
+ * summed device time in milliseconds and the number of launches per step, in
+ * the order of enum matvis_step, and forgets them.  ms and launches are HOST
+ * arrays of MATVIS_N_STEPS entries.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+    MATVIS_STEP_SKY = 0,    /* rotation + compaction (count, scan, scatter) */
+    MATVIS_STEP_BEAM = 1,   /* beam interpolation */
+    MATVIS_STEP_ZFORM = 2,  /* phase + Z formation */
+    MATVIS_STEP_HERK = 3,   /* the Z Z^H product kernel alone */
+    MATVIS_STEP_REDUCE = 4, /* k-split reduction + Hermitian fill */
+    MATVIS_STEP_OTHER = 5,  /* input preparation and the work-list prefix */
+    MATVIS_N_STEPS = 6
+} matvis_step;
+
+matvis_status matvis_profile_enable(matvis_ctx *ctx, int32_t enable);
+matvis_status matvis_profile_read(matvis_ctx *ctx, double *ms, int64_t *launches);
+
+/* ---------------------------------------------------------------------------
+ * Step entry points: one hot-path step on caller buffers, using the context's
+ * geometry and precision.  They exist so each kernel can be checked on its
+ * own; matvis_simulate runs the same kernels.
+ * ------------------------------------------------------------------------- */
+
+/* Alg. 2 step (i) for n_time LSTs and n_src sources (n_time <= max_time,
+ * n_src <= max_src):
+ *   idx     [n_time][n_src] int32: ascending indices of sources with U > 0
+ *           (first count[t] entries of row t are defined);
+ *   count   [n_time] int32: visible sources per time;
+ *   s_hat   [n_time][3][n_src] double: (E, N, U) of the visible sources, in
+ *           the order of idx (may be NULL);
+ *   za_az   [n_time][2][n_src] double: zenith angle and azimuth of the
+ *           visible sources (may be NULL). */
+matvis_status matvis_step_sky(matvis_ctx *ctx, const double *lsts, int32_t n_time, const double *src_radec,
+                              int64_t n_src, int32_t *idx, int32_t *count, double *s_hat, double *za_az,
+                              void *stream);
+
+/* Alg. 2 step (ii) alone: beam values at n points given by zenith angle and
+ * azimuth za_az [2][n] (double), from one channel's grid slice
+ * grid [n_beam][n_feed][n_ax][n_za][n_az] (complex128 for FP64, else
+ * complex64), with the context's beam mode (bilinear or bicubic).
+ * Output A [n_beam][n_feed][n_ax][n] complex of the same width. */
+matvis_status matvis_step_interp(matvis_ctx *ctx, const double *za_az, int64_t n, const void *grid, void *A,
+                                 void *stream);
+
+/* Step (v) alone: V = Z Z^H for an [n_row][n_col] complex matrix Z with
+ * row stride ld elements (complex128 for FP64, else complex64), n_row <=
+ * n_ant * n_feed, n_col <= n_ax * max_src.  Output V [n_row][n_row] of the
+ * same complex width, fully written and Hermitian.  BF16X3 splits Z on the
+ * device before the product. */
+matvis_status matvis_step_herk(matvis_ctx *ctx, const void *Z, int32_t n_row, int64_t n_col, int64_t ld, void *V,
+                               void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MATVIS_H */

@@ -70,6 +70,9 @@ def _declare(L):
     L.orc_simulate.argtypes = [ctypes.POINTER(Geom), _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P,
                                _P, ctypes.c_int32, _P, _P, _P]
     L.orc_simulate.restype = ctypes.c_int
+    L.orc_simulate_pairs.argtypes = [ctypes.POINTER(Geom), _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P,
+                                     _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]
+    L.orc_simulate_pairs.restype = ctypes.c_int
     L.orc_simulate_given_beam.argtypes = [ctypes.POINTER(Geom), _P, _P, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_int64, _P, _P, _P, _P, _P]
     L.orc_simulate_given_beam.restype = ctypes.c_int64
@@ -175,6 +178,28 @@ def simulate(antpos, freqs, lsts, ra, dec, flux, beam_grid, latitude: float, dza
     rc = lib().orc_simulate(ctypes.byref(G), _ptr(antpos), _ptr(bi), _ptr(freqs), freqs.size, _ptr(lsts),
                             ra.size, _ptr(ra), _ptr(dec), _ptr(flux), _ptr(beam_grid), len(instances),
                             _ptr(it), _ptr(iff), _ptr(V))
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    return V
+
+
+def simulate_pairs(antpos, freqs, lsts, ra, dec, flux, beam_grid, latitude: float, dza: float, daz: float,
+                   interp_mode: str, instances: Sequence, pairs: Sequence, beam_idx=None) -> np.ndarray:
+    """Direct sum for selected antenna pairs only: V[inst][pair][p][q] (complex128)."""
+    antpos, freqs, lsts, ra, dec, flux = map(_f64, (antpos, freqs, lsts, ra, dec, flux))
+    beam_grid = _c128(beam_grid)
+    nb, nfreq, nf, nx, nza, naz = beam_grid.shape
+    na = antpos.shape[0]
+    it = _i32([i[0] for i in instances])
+    iff = _i32([i[1] for i in instances])
+    pa = _i32([p[0] for p in pairs])
+    pb = _i32([p[1] for p in pairs])
+    bi = None if beam_idx is None else _i32(beam_idx)
+    G = _geom(na, nf, nx, nb, nza, naz, dza, daz, latitude, interp_mode)
+    V = np.zeros((len(instances), len(pairs), nf, nf), dtype=np.complex128)
+    rc = lib().orc_simulate_pairs(ctypes.byref(G), _ptr(antpos), _ptr(bi), _ptr(freqs), freqs.size, _ptr(lsts),
+                                  ra.size, _ptr(ra), _ptr(dec), _ptr(flux), _ptr(beam_grid), len(instances),
+                                  _ptr(it), _ptr(iff), len(pairs), _ptr(pa), _ptr(pb), _ptr(V))
     if rc != 0:
         raise MemoryError("oracle allocation failed")
     return V

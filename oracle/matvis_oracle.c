@@ -317,6 +317,66 @@ int orc_simulate(const orc_geom *G, const double *antpos, const int32_t *beam_id
     return 0;
 }
 
+/* The direct sum of Eq. (matvisrime) for a chosen list of antenna pairs only
+ * (pair_a[j], pair_b[j]), j < n_pair: V[inst][j][p][q].  Same arithmetic as
+ * orc_simulate, for checking single entries of large problems. */
+int orc_simulate_pairs(const orc_geom *G, const double *antpos, const int32_t *beam_idx, const double *freqs,
+                       int32_t n_freq, const double *lsts, int64_t n_src, const double *ra, const double *dec,
+                       const double *flux, const cplx *beam_grid, int32_t n_inst, const int32_t *inst_t,
+                       const int32_t *inst_f, int32_t n_pair, const int32_t *pair_a, const int32_t *pair_b,
+                       cplx *V) {
+    double *xeq = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
+    double *xall = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
+    double *xvis = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
+    double *fvis = malloc(sizeof(double) * (n_src ? n_src : 1));
+    int32_t *idx = malloc(sizeof(int32_t) * (n_src ? n_src : 1));
+    int64_t plane = (int64_t)G->n_za * G->n_az;
+    int64_t per_freq = (int64_t)G->n_feed * G->n_ax * plane;
+    cplx *A = malloc(sizeof(cplx) * (size_t)G->n_beam * G->n_feed * G->n_ax * (n_src ? n_src : 1));
+    cplx *slice = malloc(sizeof(cplx) * (size_t)G->n_beam * per_freq);
+    if (!xeq || !xall || !xvis || !fvis || !idx || !A || !slice) {
+        free(xeq); free(xall); free(xvis); free(fvis); free(idx); free(A); free(slice);
+        return -1;
+    }
+    orc_xeq(n_src, ra, dec, xeq);
+    const int nf = G->n_feed, nx = G->n_ax;
+    for (int32_t i = 0; i < n_inst; i++) {
+        int t = inst_t[i], f = inst_f[i];
+        for (int b = 0; b < G->n_beam; b++)
+            memcpy(slice + b * per_freq, beam_grid + ((int64_t)b * n_freq + f) * per_freq, sizeof(cplx) * per_freq);
+        int64_t m = instance_sky(G, lsts[t], n_src, xeq, slice, idx, xall, xvis, A);
+        for (int64_t n = 0; n < m; n++) fvis[n] = flux[(int64_t)f * n_src + idx[n]];
+        double freq = freqs[f];
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int32_t j = 0; j < n_pair; j++) {
+            int a = pair_a[j], b = pair_b[j];
+            double bx = antpos[3 * a + 0] - antpos[3 * b + 0];
+            double by = antpos[3 * a + 1] - antpos[3 * b + 1];
+            double bz = antpos[3 * a + 2] - antpos[3 * b + 2];
+            int ia = beam_idx ? beam_idx[a] : 0;
+            int ib = beam_idx ? beam_idx[b] : 0;
+            for (int p = 0; p < nf; p++)
+                for (int q = 0; q < nf; q++) {
+                    cplx acc = 0.0;
+                    for (int64_t n = 0; n < m; n++) {
+                        const double *s = xvis + 3 * n;
+                        double tau = (bx * s[0] + by * s[1] + bz * s[2]) / SPEED_OF_LIGHT;
+                        double ph = -2.0 * M_PI * freq * tau;
+                        cplx fringe = cos(ph) + I * sin(ph);
+                        cplx beams = 0.0;
+                        for (int k = 0; k < nx; k++)
+                            beams += A[(((int64_t)ia * nf + p) * nx + k) * n_src + n] *
+                                     conj(A[(((int64_t)ib * nf + q) * nx + k) * n_src + n]);
+                        acc += fvis[n] * beams * fringe;
+                    }
+                    V[(((int64_t)i * n_pair + j) * nf + p) * nf + q] = acc;
+                }
+        }
+    }
+    free(xeq); free(xall); free(xvis); free(fvis); free(idx); free(A); free(slice);
+    return 0;
+}
+
 /* Same direct sum, with the beam supplied by the caller for every source
  * (A_all [n_beam][n_feed][n_ax][n_src] at this instance), e.g. an analytic
  * beam evaluated exactly.  One instance; returns the visible count. */

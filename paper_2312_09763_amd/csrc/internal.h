@@ -1,0 +1,138 @@
+// Internal declarations shared by the HIP translation units of libmatvis.
+// Everything here is gfx950 device code or host launch glue; the public
+// boundary is include/matvis.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mv {
+
+constexpr double kSpeedOfLight = 299792458.0;  // m/s
+constexpr int kColPad = 64;                    // Z columns are padded to a multiple of this (complex elements)
+constexpr int kWave = 64;                      // CDNA wavefront width
+
+enum Prec : int { P64 = 0, P32 = 1, PB3 = 2 };
+enum Interp : int { BILINEAR = 0, BICUBIC = 1 };
+
+// Device error flag bits (OR-ed into ctx->d_flags).
+enum : int { FLAG_BAD_FLUX = 1, FLAG_BAD_ANTPOS = 2, FLAG_BAD_BEAM_IDX = 4 };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Everything one batch of (t, f) instances needs to locate its data.
+// Instance i of the batch is (t, f) = (t0 + i / nfb, f0 + i % nfb); its sky
+// lives in time slot i / nfb of the sky buffers.
+struct Batch {
+    int32_t t0, f0, ntb, nfb;  // first time / frequency, and how many of each
+    int32_t n_inst;            // ntb * nfb
+};
+
+// Device-side sky buffers of one time batch and one source chunk.
+struct SkyBufs {
+    const double *xeq;  // [3][ld_xeq] unit vectors, Eq. (xeq)
+    int64_t ld_xeq;
+    const double *rot;  // [max_time][9] rotation matrices, Eq. (rotation)
+    int32_t *blk_count; // [ntb][nblk]
+    int32_t *blk_off;   // [ntb][nblk]
+    int32_t *count;     // [ntb] visible sources in the chunk
+    int32_t *idx;       // [ntb][ld_src] absolute source indices, ascending
+    double *s_hat;      // [ntb][3][ld_src] (E, N, U)
+    double *za_az;      // [ntb][2][ld_src]
+    int64_t ld_src;     // row stride of the per-time arrays (>= chunk size)
+};
+
+// ---- sky (kernels_sky.hip) -------------------------------------------------
+hipError_t launch_xeq(const double *radec, int64_t n_src, double *xeq, int64_t ld, hipStream_t s);
+hipError_t launch_rotmats(const double *lsts, int32_t n_time, double latitude, double *rot, hipStream_t s);
+hipError_t launch_prep_inputs(const double *antpos, int32_t n_ant, const int32_t *beam_idx, int32_t n_beam,
+                              const double *flux, int64_t n_flux, double *antc, int32_t *bidx, int32_t *flags,
+                              hipStream_t s);
+hipError_t launch_sky(const SkyBufs &b, int32_t t0, int32_t ntb, int64_t c0, int64_t nsrc_chunk, hipStream_t s);
+
+// ---- beam (kernels_beam.hip) -----------------------------------------------
+struct InterpArgs {
+    const void *grid;        // [n_beam][n_freq_grid][n_feed][n_ax][n_za][n_az]
+    int32_t n_freq_grid;     // channels in the grid array
+    int32_t n_beam, n_feed, n_ax, n_za, n_az;
+    double dza, daz;
+    const double *za_az;     // [nslots][2][ld_src]
+    const int32_t *count;    // [nslots] visible counts, or null -> fixed_count
+    int64_t fixed_count;
+    int64_t ld_src;
+    void *A;                 // [n_inst][n_beam][n_feed][n_ax][ld_src]
+    int64_t max_m;           // grid size along sources
+};
+hipError_t launch_interp(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s);
+
+// ---- Z formation (kernels_z.hip) -------------------------------------------
+struct ZformArgs {
+    const double *antc;      // [n_ant][3] centred ENU
+    const int32_t *bidx;     // [n_ant] sanitised beam index
+    const double *freqs;     // [n_freq]
+    const double *flux;      // [n_freq][n_src]
+    int64_t n_src;
+    const int32_t *idx;      // [nslots][ld_src]
+    const double *s_hat;     // [nslots][3][ld_src]
+    const int32_t *count;    // [nslots]
+    const void *A;           // [n_inst][n_beam][n_feed][n_ax][ld_src]
+    int64_t ld_src;
+    int32_t n_ant, n_feed, n_ax, n_beam;
+    void *Z;                 // FP64/FP32: [n_inst][n_rows_pad][ldz] complex; BF16X3: hi plane
+    void *Z_lo;              // BF16X3 lo plane, same shape (4 B per complex)
+    int64_t ldz;             // complex elements per row
+    int32_t n_rows_pad;
+    int64_t max_m;           // launch size along sources (>= padded count)
+};
+hipError_t launch_zform(int prec, const ZformArgs &a, const Batch &bt, hipStream_t s);
+// Copy a caller's dense Z [n_row][ld] into the padded scratch layout (splitting
+// for BF16X3); rows n_row..n_rows_pad-1 and columns n_col..n_col_pad-1 become zero.
+hipError_t launch_z_import(int prec, const void *Zin, int32_t n_row, int32_t n_rows_pad, int64_t n_col, int64_t ld,
+                           void *Z, void *Z_lo, int64_t ldz, int64_t n_col_pad, hipStream_t s);
+
+// ---- HERK (kernels_herk.hip) -----------------------------------------------
+struct HerkArgs {
+    const void *Z;           // as in ZformArgs
+    const void *Z_lo;
+    int64_t ldz;
+    int64_t inst_stride;     // elements between instances in Z
+    int32_t n_rows;          // N = n_ant * n_feed
+    int32_t n_rows_pad;      // multiple of the super-tile size
+    const int32_t *count;    // [nslots] visible counts (K = n_ax * count), or null -> fixed_k
+    int64_t fixed_k;
+    int32_t n_ax;
+    int32_t nfb;             // instance i uses count slot i / nfb
+    int32_t n_inst;
+    int64_t ksplit;          // complex columns per work item (multiple of 64)
+    int32_t max_splits;      // partial slots per instance
+    void *part;              // [n_inst][max_splits][n_rows_pad][n_rows_pad] complex partials
+    int32_t *work;           // [n_inst + 1] item prefix
+    int32_t grid;            // persistent grid size (multiple of 8)
+};
+int herk_super_tile(int prec);
+int herk_occupancy(int prec);  // resident workgroups per CU
+// Item prefix over the batch (k_worklist), then the persistent product kernel.
+hipError_t launch_worklist(int prec, const HerkArgs &a, hipStream_t s);
+hipError_t launch_herk(int prec, const HerkArgs &a, hipStream_t s);
+
+struct ReduceArgs {
+    const void *part;
+    int32_t n_rows, n_rows_pad, max_splits;
+    const int32_t *count;
+    int64_t fixed_k;
+    int32_t n_ax, nfb, n_inst;
+    int64_t ksplit;
+    double *vacc;            // [n_inst][n_rows][n_rows] complex128 running sums (multi-chunk)
+    int32_t first, last;     // first chunk: assign; last chunk: write the output
+    void *out;               // output base
+    int32_t out_kind;        // 0: vis layout [t][f][a][b][p][q]; 1: plain [r][c]
+    int32_t n_ant, n_feed, n_freq_total;
+    Batch bt;
+};
+hipError_t launch_reduce(int prec, const ReduceArgs &a, hipStream_t s);
+
+}  // namespace mv

@@ -1,0 +1,416 @@
+// Alg. 2 step (v): V = Z Z^H (Eq. zz) for a batch of instances with uneven
+// column counts, on MFMA.
+//
+// Real embedding.  With Z = Zr + i Zi,
+//   Re V = Zr Zr^T + Zi Zi^T,   Im V = Zi Zr^T - Zr Zi^T,
+// so each 16x16 output tile takes four real products per k-chunk (FP32 and
+// FP64: v_mfma_{f32,f64}_16x16x4, one complex element per lane), or six bf16
+// products on BF16X3 (v_mfma_f32_16x16x32_bf16: eight bf16 = four complex per
+// lane, re/im interleaved; the imaginary operand W = (im, -re) is formed in
+// registers by swapping the bf16 halves and flipping one sign bit, and
+// Z Z^H ~ hi hi^H + hi lo^H + lo hi^H).
+//
+// Work decomposition.  Output rows are padded to Np, a multiple of the
+// super-tile ST (128 on FP32/BF16X3, 64 on FP64).  A work item is
+// (instance, k-split, lower super-tile (I >= J)).  A 256-thread workgroup
+// stages the rows of I and J (only I on the diagonal) for KC = 16 complex
+// columns at a time in LDS, with the next chunk prefetched into registers;
+// its four waves own the 2 x 2 wave tiles of the super-tile (the wave above
+// the diagonal of a diagonal super-tile idles).  Each item writes its
+// partial tile to its own slot, so the later sum over k-splits runs in a
+// fixed order and the result is bitwise reproducible.
+//
+// Scheduling.  The grid is persistent (a multiple of 8 workgroups); the
+// per-instance item counts come from the device-side visible counts through
+// a prefix array built by k_worklist, so no host synchronisation is needed.
+// Workgroup b runs on XCD b % 8; consecutive items (the super-tiles of one
+// k-split, which share Z rows) are mapped to workgroups of the same XCD so
+// the shared rows hit the same L2.
+#include "internal.h"
+
+namespace mv {
+
+namespace {
+
+template <int PREC>
+struct HT;
+template <>
+struct HT<P32> {
+    static constexpr int ST = 128, WT = 64, KC = 16, EB = 8, PLANES = 1;
+};
+template <>
+struct HT<P64> {
+    static constexpr int ST = 64, WT = 32, KC = 16, EB = 16, PLANES = 1;
+};
+template <>
+struct HT<PB3> {
+    static constexpr int ST = 128, WT = 64, KC = 16, EB = 4, PLANES = 2;
+};
+
+template <int PREC>
+struct HD {
+    typedef HT<PREC> T;
+    static constexpr int ST = T::ST, WT = T::WT, KC = T::KC, EB = T::EB, PLANES = T::PLANES;
+    static constexpr int ROWB = KC * EB * PLANES;  // bytes of one staged row
+    static constexpr int RS = ROWB + 16;           // LDS row stride (16 B pad against bank conflicts)
+    static constexpr int CPR = ROWB / 16;          // 16-byte chunks per row
+    static constexpr int NLD = 2 * ST * CPR / 256; // chunks per thread per stage
+    static constexpr int LDS = 2 * ST * RS;
+    static constexpr int TI = WT / 16;             // 16x16 tiles per wave side
+};
+
+__device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// Items of instance i: ceil(K_i / ksplit) * n_st.
+__device__ inline int64_t inst_k(const int32_t *count, int64_t fixed_k, int n_ax, int nfb, int i) {
+    return count ? (int64_t)n_ax * count[i / nfb] : fixed_k;
+}
+
+__global__ void __launch_bounds__(1024) k_worklist(const int32_t *count, int64_t fixed_k, int n_ax, int nfb, int n_inst,
+                                                   int64_t ksplit, int n_st, int32_t *work) {
+    __shared__ int wtot[1024 / kWave];
+    __shared__ int carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    for (int base = 0; base < n_inst; base += 1024) {
+        int i = base + threadIdx.x;
+        int v = 0;
+        if (i < n_inst) {
+            int64_t k = inst_k(count, fixed_k, n_ax, nfb, i);
+            v = (int)((k + ksplit - 1) / ksplit) * n_st;
+        }
+        int x = v;
+        for (int d = 1; d < kWave; d <<= 1) {
+            int y = __shfl_up(x, d, kWave);
+            if (lane >= d) x += y;
+        }
+        if (lane == kWave - 1) wtot[w] = x;
+        __syncthreads();
+        if (w == 0) {
+            int t = lane < 1024 / kWave ? wtot[lane] : 0;
+            for (int d = 1; d < kWave; d <<= 1) {
+                int y = __shfl_up(t, d, kWave);
+                if (lane >= d) t += y;
+            }
+            if (lane < 1024 / kWave) wtot[lane] = t;
+        }
+        __syncthreads();
+        int carry = carry_s;
+        if (i < n_inst) work[i] = carry + (w > 0 ? wtot[w - 1] : 0) + x - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + wtot[1024 / kWave - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) work[n_inst] = carry_s;
+}
+
+// W = (im, -re) for four packed bf16 complex values.
+__device__ inline u32x4 bf16_rot(u32x4 v) {
+    u32x4 r;
+    for (int q = 0; q < 4; q++) r[q] = __builtin_amdgcn_alignbit(v[q], v[q], 16) ^ 0x80000000u;
+    return r;
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256, 2) k_herk(HerkArgs a) {
+    typedef HD<PREC> D;
+    constexpr int ST = D::ST, WT = D::WT, KC = D::KC, RS = D::RS, CPR = D::CPR, NLD = D::NLD, TI = D::TI;
+    typedef typename std::conditional<PREC == P64, f64x4, f32x4>::type Acc;
+    typedef typename std::conditional<PREC == P64, double2, float2>::type PartT;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[D::LDS];
+
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid / kWave;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int Np = a.n_rows_pad;
+    const int nb = Np / ST;
+    const int n_st = nb * (nb + 1) / 2;
+    const int total = a.work[a.n_inst];
+    const int per_xcd = a.grid / 8;
+    const int slot = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const char *zbase = (const char *)a.Z;
+    const char *zlo = (const char *)a.Z_lo;
+    const int64_t ldzb = a.ldz * D::EB;  // row stride in bytes of one plane
+
+    for (int item = slot; item < total; item += a.grid) {
+        // locate the instance: largest i with work[i] <= item
+        int lo = 0, hi = a.n_inst - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (a.work[mid] <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int inst = lo;
+        const int local = item - a.work[inst];
+        const int s = local / n_st;
+        int st = local % n_st;
+        int I = 0;
+        while (st > I) {
+            st -= I + 1;
+            I++;
+        }
+        const int J = st;
+        const bool diag = (I == J);
+        const int64_t K = inst_k(a.count, a.fixed_k, a.n_ax, a.nfb, inst);
+        const int64_t Kr = ((K + KC - 1) / KC) * KC;
+        const int64_t kb = (int64_t)s * a.ksplit;
+        const int64_t ke = kb + a.ksplit < Kr ? kb + a.ksplit : Kr;
+        const int64_t ioff = (int64_t)inst * a.inst_stride * D::EB;
+
+        Acc acc_re[TI][TI], acc_im[TI][TI];
+        for (int i = 0; i < TI; i++)
+            for (int j = 0; j < TI; j++)
+                for (int e = 0; e < 4; e++) {
+                    acc_re[i][j][e] = 0;
+                    acc_im[i][j][e] = 0;
+                }
+
+        u32x4 pre[NLD];
+        auto load = [&](int64_t k0) {
+#pragma unroll
+            for (int j = 0; j < NLD; j++) {
+                if (diag && j >= NLD / 2) break;
+                const int q = tid + 256 * j;
+                const int lr = q / CPR, c = q % CPR;
+                const int grow = lr < ST ? I * ST + lr : J * ST + (lr - ST);
+                const char *src;
+                if constexpr (D::PLANES == 2) {
+                    const int half = CPR / 2;
+                    src = (c < half ? zbase : zlo) + ioff + grow * ldzb + k0 * D::EB + (c % half) * 16;
+                } else {
+                    src = zbase + ioff + grow * ldzb + k0 * D::EB + c * 16;
+                }
+                pre[j] = *(const u32x4 *)src;
+            }
+        };
+        auto store = [&]() {
+#pragma unroll
+            for (int j = 0; j < NLD; j++) {
+                if (diag && j >= NLD / 2) break;
+                const int q = tid + 256 * j;
+                const int lr = q / CPR, c = q % CPR;
+                *(u32x4 *)(lds + lr * RS + c * 16) = pre[j];
+            }
+        };
+
+        const bool active = !(diag && wc > wr);
+        const bool on_diag = diag && wc == wr;  // this wave's tiles (i, i) hold output diagonal entries
+        const int arow = wr * WT;
+        const int brow = (diag ? 0 : ST) + wc * WT;
+        const int l16 = lane & 15, lk = lane >> 4;
+
+        if (kb < ke) load(kb);
+        for (int64_t k0 = kb; k0 < ke; k0 += KC) {
+            __syncthreads();
+            store();
+            __syncthreads();
+            if (k0 + KC < ke) load(k0 + KC);
+            if (active) {
+                if constexpr (PREC == PB3) {
+                    u32x4 ah[TI], al[TI], bh[TI], bl[TI];
+#pragma unroll
+                    for (int i = 0; i < TI; i++) {
+                        const unsigned char *p = lds + (arow + 16 * i + l16) * RS + lk * 16;
+                        ah[i] = *(const u32x4 *)p;
+                        al[i] = *(const u32x4 *)(p + KC * 4);
+                    }
+#pragma unroll
+                    for (int j = 0; j < TI; j++) {
+                        const unsigned char *p = lds + (brow + 16 * j + l16) * RS + lk * 16;
+                        bh[j] = *(const u32x4 *)p;
+                        bl[j] = *(const u32x4 *)(p + KC * 4);
+                    }
+#pragma unroll
+                    for (int i = 0; i < TI; i++) {
+                        const u32x4 wh = bf16_rot(ah[i]), wl = bf16_rot(al[i]);
+                        const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah[i]);
+                        const bf16x8 Al = __builtin_bit_cast(bf16x8, al[i]);
+                        const bf16x8 Wh = __builtin_bit_cast(bf16x8, wh);
+                        const bf16x8 Wl = __builtin_bit_cast(bf16x8, wl);
+#pragma unroll
+                        for (int j = 0; j < TI; j++) {
+                            const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[j]);
+                            const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl[j]);
+                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh, acc_re[i][j], 0, 0, 0);
+                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl, acc_re[i][j], 0, 0, 0);
+                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, acc_re[i][j], 0, 0, 0);
+                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wh, Bh, acc_im[i][j], 0, 0, 0);
+                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wh, Bl, acc_im[i][j], 0, 0, 0);
+                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wl, Bh, acc_im[i][j], 0, 0, 0);
+                            // On the output diagonal the dropped lo lo^H term is a sum of
+                            // |lo|^2, a one-signed bias of relative size ~2^-16; add it
+                            // there (elsewhere it averages out and is left out).
+                            if (on_diag && i == j) {
+                                acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bl, acc_re[i][j], 0, 0, 0);
+                                acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wl, Bl, acc_im[i][j], 0, 0, 0);
+                            }
+                        }
+                    }
+                } else {
+                    typedef typename std::conditional<PREC == P64, double2, float2>::type C;
+                    typedef typename std::conditional<PREC == P64, double, float>::type R;
+#pragma unroll
+                    for (int kk = 0; kk < KC; kk += 4) {
+                        C av[TI], bv[TI];
+#pragma unroll
+                        for (int i = 0; i < TI; i++)
+                            av[i] = *(const C *)(lds + (arow + 16 * i + l16) * RS + (kk + lk) * D::EB);
+#pragma unroll
+                        for (int j = 0; j < TI; j++)
+                            bv[j] = *(const C *)(lds + (brow + 16 * j + l16) * RS + (kk + lk) * D::EB);
+#pragma unroll
+                        for (int i = 0; i < TI; i++) {
+                            const R nre = -av[i].x;
+#pragma unroll
+                            for (int j = 0; j < TI; j++) {
+                                if constexpr (PREC == P64) {
+                                    acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, acc_re[i][j], 0, 0, 0);
+                                    acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].y, acc_re[i][j], 0, 0, 0);
+                                    acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, acc_im[i][j], 0, 0, 0);
+                                    acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nre, bv[j].y, acc_im[i][j], 0, 0, 0);
+                                } else {
+                                    acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, acc_re[i][j], 0, 0, 0);
+                                    acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, acc_re[i][j], 0, 0, 0);
+                                    acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].x, acc_im[i][j], 0, 0, 0);
+                                    acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nre, bv[j].y, acc_im[i][j], 0, 0, 0);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+
+        if (active) {
+            // Accumulator layout of a 16x16 tile: lane l, register e holds column l % 16 of
+            // row 4 (l / 16) + e for the f32 products, and of row 4 e + l / 16 for
+            // v_mfma_f64_16x16x4f64.
+            PartT *P = (PartT *)a.part + ((int64_t)inst * a.max_splits + s) * (int64_t)Np * Np;
+            const int rb = I * ST + wr * WT;
+            const int c0 = J * ST + wc * WT + l16;
+#pragma unroll
+            for (int i = 0; i < TI; i++)
+#pragma unroll
+                for (int j = 0; j < TI; j++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        PartT v;
+                        v.x = acc_re[i][j][e];
+                        v.y = acc_im[i][j][e];
+                        const int row = rb + 16 * i + (PREC == P64 ? 4 * e + lk : 4 * lk + e);
+                        P[(int64_t)row * Np + c0 + 16 * j] = v;
+                    }
+        }
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
+// Fixed-order sum of the k-split partials (and of earlier source chunks),
+// Hermitian fill, and the write of the output layout.  One thread per output
+// element; entries above the diagonal are the conjugates of the same sums.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
+    typedef typename std::conditional<PREC == P64, double2, float2>::type PartT;
+    typedef typename std::conditional<PREC == P64, double2, float2>::type OutT;
+    const int inst = blockIdx.y;
+    const int N = a.n_rows, Np = a.n_rows_pad, nf = a.n_feed, na = a.n_ant;
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (int64_t)N * N) return;
+    int r, c;
+    if (a.out_kind == 0) {
+        const int q = (int)(o % nf), p = (int)((o / nf) % nf);
+        const int b = (int)((o / (nf * nf)) % na), aa = (int)(o / ((int64_t)nf * nf * na));
+        r = aa * nf + p;
+        c = b * nf + q;
+    } else {
+        r = (int)(o / N);
+        c = (int)(o % N);
+    }
+    const int64_t K = a.count ? (int64_t)a.n_ax * a.count[inst / a.nfb] : a.fixed_k;
+    const int ns = (int)((K + a.ksplit - 1) / a.ksplit);
+    const bool lower = r >= c;
+    const int rr = lower ? r : c, cc = lower ? c : r;
+    const PartT *P = (const PartT *)a.part + (int64_t)inst * a.max_splits * Np * Np + (int64_t)rr * Np + cc;
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < ns; s++) {
+        const PartT v = P[(int64_t)s * Np * Np];
+        sr += (double)v.x;
+        si += (double)v.y;
+    }
+    if (!lower) si = -si;
+    if (r == c) si = 0.0;
+    double2 *acc = a.vacc ? (double2 *)a.vacc + ((int64_t)inst * N + r) * N + c : nullptr;
+    if (!a.first) {
+        const double2 prev = *acc;
+        sr += prev.x;
+        si += prev.y;
+    }
+    if (!a.last) {
+        *acc = make_double2(sr, si);
+        return;
+    }
+    OutT v;
+    v.x = sr;
+    v.y = si;
+    if (a.out_kind == 0) {
+        const int t = a.bt.t0 + inst / a.bt.nfb, f = a.bt.f0 + inst % a.bt.nfb;
+        ((OutT *)a.out)[((int64_t)t * a.n_freq_total + f) * (int64_t)N * N + o] = v;
+    } else {
+        ((OutT *)a.out)[o] = v;
+    }
+}
+
+}  // namespace
+
+int herk_super_tile(int prec) { return prec == P64 ? HT<P64>::ST : HT<P32>::ST; }
+
+int herk_occupancy(int prec) {
+    int nb = 1;
+    hipError_t e;
+    if (prec == P64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_herk<P64>, 256, 0);
+    else if (prec == P32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_herk<P32>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_herk<PB3>, 256, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_worklist(int prec, const HerkArgs &a, hipStream_t s) {
+    if (a.n_inst <= 0) return hipSuccess;
+    const int st = herk_super_tile(prec);
+    const int nb = a.n_rows_pad / st;
+    k_worklist<<<1, 1024, 0, s>>>(a.count, a.fixed_k, a.n_ax, a.nfb, a.n_inst, a.ksplit, nb * (nb + 1) / 2, a.work);
+    return hipGetLastError();
+}
+
+hipError_t launch_herk(int prec, const HerkArgs &a, hipStream_t s) {
+    if (a.n_inst <= 0) return hipSuccess;
+    if (prec == P64)
+        k_herk<P64><<<a.grid, 256, 0, s>>>(a);
+    else if (prec == P32)
+        k_herk<P32><<<a.grid, 256, 0, s>>>(a);
+    else
+        k_herk<PB3><<<a.grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int prec, const ReduceArgs &a, hipStream_t s) {
+    if (a.n_inst <= 0 || a.n_rows <= 0) return hipSuccess;
+    dim3 g((unsigned)(((int64_t)a.n_rows * a.n_rows + 255) / 256), a.n_inst);
+    if (prec == P64)
+        k_reduce<P64><<<g, 256, 0, s>>>(a);
+    else
+        k_reduce<P32><<<g, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace mv

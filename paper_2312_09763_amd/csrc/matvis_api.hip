@@ -1,0 +1,625 @@
+// Host side of libmatvis: the C ABI of include/matvis.h.
+//
+// A context owns every device buffer the hot path needs, sized once in
+// matvis_init from the capacities in matvis_config, so matvis_simulate
+// allocates nothing.  A simulate call walks (time batch) x (frequency batch)
+// x (source chunk) and enqueues, per step of Alg. 2:
+//   sky     : rotation + ordered horizon compaction of the chunk, per time;
+//   interp  : beam at the visible sources, per (t, f) instance;
+//   zform   : Z of Eq. (littlez), per instance;
+//   herk    : V partials of Eq. (zz) over a device-built work list;
+//   reduce  : fixed-order sum over k-splits and chunks, Hermitian fill.
+// Nothing in the sequence waits on the host, so the whole call is captured
+// once into a hipGraph (keyed by its arguments) and replayed afterwards.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/matvis.h"
+#include "internal.h"
+
+using namespace mv;
+
+namespace {
+
+struct GraphKey {
+    std::vector<uint64_t> v;
+    bool operator<(const GraphKey &o) const { return v < o.v; }
+};
+
+}  // namespace
+
+struct matvis_ctx {
+    matvis_config cfg{};
+    int device = 0;
+    int n_cu = 256;
+    std::string err;
+    hipStream_t last_stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+
+    // derived geometry
+    int N = 0, Np = 0, st = 128;
+    int64_t chunk = 0, ldz = 0, ksplit = 4096;
+    int max_splits = 1, ntb = 1, nfb = 1, herk_grid = 512;
+    int64_t nblk_cap = 1;
+
+    // device scratch
+    double *xeq = nullptr, *rot = nullptr, *antc = nullptr, *s_hat = nullptr, *za_az = nullptr, *vacc = nullptr;
+    int32_t *bidx = nullptr, *flags = nullptr, *blk_count = nullptr, *blk_off = nullptr, *count = nullptr,
+            *idx = nullptr, *work = nullptr;
+    void *A = nullptr, *Z = nullptr, *Z_lo = nullptr, *part = nullptr;
+    std::vector<void *> allocs;
+
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::vector<GraphKey> graph_order;
+
+    // per-step timing (matvis_profile_*)
+    struct ProfRec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    bool profiling = false;
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+matvis_status fail(matvis_ctx *c, matvis_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+matvis_status hip_fail(matvis_ctx *c, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, MATVIS_EHIP, m);
+}
+
+#define HIPCHK(ctx, expr)                                  \
+    do {                                                   \
+        hipError_t _e = (expr);                            \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+    } while (0)
+
+hipError_t take_event(matvis_ctx *c, hipEvent_t *e) {
+    if (!c->event_pool.empty()) {
+        *e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Launch `expr` (a hipError_t-returning launch helper) as part of step `kind`,
+// bracketed by events when profiling.
+#define STEP(ctx, kind, s, expr)                                        \
+    do {                                                                \
+        hipEvent_t _a = nullptr, _b = nullptr;                          \
+        if ((ctx)->profiling) {                                         \
+            HIPCHK(ctx, take_event(ctx, &_a));                          \
+            HIPCHK(ctx, hipEventRecord(_a, s));                         \
+        }                                                               \
+        HIPCHK(ctx, expr);                                              \
+        if ((ctx)->profiling) {                                         \
+            HIPCHK(ctx, take_event(ctx, &_b));                          \
+            HIPCHK(ctx, hipEventRecord(_b, s));                         \
+            (ctx)->prof.push_back({(kind), _a, _b});                    \
+        }                                                               \
+    } while (0)
+
+template <typename T>
+matvis_status dalloc(matvis_ctx *c, T **p, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, MATVIS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    c->allocs.push_back(q);
+    *p = (T *)q;
+    return MATVIS_OK;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
+
+size_t cbytes(int prec) { return prec == P64 ? 16 : 8; }  // bytes per complex of beams / Z / output
+
+matvis_status validate_cfg(const matvis_config *c, std::string &why) {
+    if (!c) return why = "config is NULL", MATVIS_EINVAL;
+    if (c->n_ant <= 0) return why = "n_ant must be positive", MATVIS_EINVAL;
+    if (c->n_feed != 1 && c->n_feed != 2) return why = "n_feed must be 1 or 2", MATVIS_EINVAL;
+    if (c->n_ax != 1 && c->n_ax != 2) return why = "n_ax must be 1 or 2", MATVIS_EINVAL;
+    if (c->n_beam <= 0) return why = "n_beam must be positive", MATVIS_EINVAL;
+    if (c->max_src <= 0 || c->max_src > (int64_t)1 << 31) return why = "max_src out of range", MATVIS_EINVAL;
+    if (c->max_time <= 0 || c->max_freq <= 0) return why = "max_time and max_freq must be positive", MATVIS_EINVAL;
+    if (c->precision < MATVIS_FP64 || c->precision > MATVIS_BF16X3) return why = "unknown precision", MATVIS_EINVAL;
+    if (c->beam_mode < MATVIS_BEAM_BILINEAR || c->beam_mode > MATVIS_BEAM_SURROGATE)
+        return why = "unknown beam mode", MATVIS_EINVAL;
+    if (c->beam_mode == MATVIS_BEAM_SURROGATE)
+        return why = "the surrogate beam is not available in this build", MATVIS_EUNSUPPORTED;
+    if (c->n_za < 3 || c->n_az < 3) return why = "beam grid must be at least 3 x 3", MATVIS_EINVAL;
+    if (!(c->dza_rad > 0) || !(c->daz_rad > 0)) return why = "grid spacings must be positive", MATVIS_EINVAL;
+    if (std::fabs((c->n_za - 1) * c->dza_rad - M_PI / 2) > 1e-9)
+        return why = "(n_za - 1) * dza_rad must equal pi/2 (za rows 0..90 deg)", MATVIS_EINVAL;
+    if (std::fabs(c->n_az * c->daz_rad - 2 * M_PI) > 1e-9)
+        return why = "n_az * daz_rad must equal 2 pi (periodic az)", MATVIS_EINVAL;
+    if (!std::isfinite(c->latitude_rad) || std::fabs(c->latitude_rad) > M_PI / 2)
+        return why = "latitude out of range", MATVIS_EINVAL;
+    if (c->src_chunk < 0 || c->batch_time < 0 || c->batch_freq < 0) return why = "negative batch sizes", MATVIS_EINVAL;
+    if ((int64_t)c->n_ant * c->n_feed > 8192) return why = "n_ant * n_feed above 8192", MATVIS_EUNSUPPORTED;
+    return MATVIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *matvis_status_string(int32_t s) {
+    switch (s) {
+        case MATVIS_OK: return "MATVIS_OK";
+        case MATVIS_EINVAL: return "MATVIS_EINVAL";
+        case MATVIS_ENOMEM: return "MATVIS_ENOMEM";
+        case MATVIS_EHIP: return "MATVIS_EHIP";
+        case MATVIS_EUNSUPPORTED: return "MATVIS_EUNSUPPORTED";
+        case MATVIS_ESTATE: return "MATVIS_ESTATE";
+        case MATVIS_EDATA: return "MATVIS_EDATA";
+        default: return "unknown status";
+    }
+}
+
+void matvis_destroy(matvis_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &r : c->prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+    for (void *p : c->allocs) (void)hipFree(p);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    delete c;
+}
+
+matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
+    if (!out) return MATVIS_EINVAL;
+    *out = nullptr;
+    std::string why;
+    matvis_status st = validate_cfg(cfg, why);
+    if (st != MATVIS_OK) {
+        fprintf(stderr, "matvis_init: %s\n", why.c_str());
+        return st;
+    }
+    matvis_ctx *c = new matvis_ctx();
+    c->cfg = *cfg;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return MATVIS_EHIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    const int prec = cfg->precision;
+    c->N = cfg->n_ant * cfg->n_feed;
+    c->st = herk_super_tile(prec);
+    c->Np = (int)round_up(c->N, c->st);
+    c->chunk = cfg->src_chunk > 0 ? std::min<int64_t>(cfg->src_chunk, cfg->max_src)
+                                  : std::min<int64_t>(cfg->max_src, (int64_t)1 << 18);
+    c->ldz = round_up((int64_t)cfg->n_ax * c->chunk, kColPad);
+    // Columns per work item.  FP32 accumulators see ksplit / 2 sequential MFMA
+    // updates per item; 2048 keeps that rounding near 2e-6 of the Cauchy-Schwarz
+    // scale, and the items' partials are then summed in FP64.
+    c->ksplit = prec == P64 ? 8192 : 2048;
+    c->max_splits = (int)((c->ldz + c->ksplit - 1) / c->ksplit);
+    // batch: all channels of a few times, enough instances to fill the GPU with
+    // work items while keeping Z within a fixed share of device memory
+    c->nfb = cfg->batch_freq > 0 ? std::min(cfg->batch_freq, cfg->max_freq) : std::min(cfg->max_freq, 16);
+    size_t zinst = (size_t)c->Np * c->ldz * cbytes(prec);
+    size_t budget = (size_t)12 << 30;
+    int ntb_auto = (int)std::max<size_t>(1, budget / std::max<size_t>(1, zinst * c->nfb));
+    c->ntb = cfg->batch_time > 0 ? cfg->batch_time : std::min(ntb_auto, 8);
+    c->ntb = std::max(1, std::min(c->ntb, cfg->max_time));
+    const int B = c->ntb * c->nfb;
+    c->nblk_cap = std::max<int64_t>((c->chunk + 255) / 256, 1);
+    int64_t nblk_total = std::max<int64_t>(c->nblk_cap * c->ntb, (cfg->max_src + 255) / 256);
+    int occ = std::max(1, herk_occupancy(prec));
+    c->herk_grid = std::max(8, (c->n_cu * occ / 8) * 8);
+
+    const size_t ncomp = (size_t)cfg->n_beam * cfg->n_feed * cfg->n_ax;
+#define ALLOC(ptr, bytes)                              \
+    do {                                               \
+        matvis_status _s = dalloc(c, &(ptr), (bytes)); \
+        if (_s != MATVIS_OK) {                         \
+            fprintf(stderr, "matvis_init: %s\n", c->err.c_str()); \
+            matvis_destroy(c);                         \
+            return _s;                                 \
+        }                                              \
+    } while (0)
+    ALLOC(c->xeq, sizeof(double) * 3 * cfg->max_src);
+    ALLOC(c->rot, sizeof(double) * 9 * cfg->max_time);
+    ALLOC(c->antc, sizeof(double) * 3 * cfg->n_ant);
+    ALLOC(c->bidx, sizeof(int32_t) * cfg->n_ant);
+    ALLOC(c->flags, sizeof(int32_t) * 4);
+    ALLOC(c->blk_count, sizeof(int32_t) * nblk_total);
+    ALLOC(c->blk_off, sizeof(int32_t) * nblk_total);
+    ALLOC(c->count, sizeof(int32_t) * std::max(c->ntb, 1));
+    ALLOC(c->idx, sizeof(int32_t) * c->ntb * c->chunk);
+    ALLOC(c->s_hat, sizeof(double) * 3 * c->ntb * c->chunk);
+    ALLOC(c->za_az, sizeof(double) * 2 * c->ntb * c->chunk);
+    ALLOC(c->A, cbytes(prec) * ncomp * B * c->chunk);
+    if (prec == PB3) {
+        ALLOC(c->Z, (size_t)4 * B * c->Np * c->ldz);
+        ALLOC(c->Z_lo, (size_t)4 * B * c->Np * c->ldz);
+    } else {
+        ALLOC(c->Z, cbytes(prec) * B * c->Np * c->ldz);
+    }
+    ALLOC(c->part, cbytes(prec) * B * (size_t)c->max_splits * c->Np * c->Np);
+    if (c->chunk < cfg->max_src) ALLOC(c->vacc, sizeof(double) * 2 * B * (size_t)c->N * c->N);
+    ALLOC(c->work, sizeof(int32_t) * (B + 1));
+#undef ALLOC
+    // Rows N..Np-1 of Z are never written by the kernels and must read as zero.
+    hipError_t e = hipMemset(c->Z, 0, prec == PB3 ? (size_t)4 * B * c->Np * c->ldz : cbytes(prec) * B * c->Np * c->ldz);
+    if (e == hipSuccess && c->Z_lo) e = hipMemset(c->Z_lo, 0, (size_t)4 * B * c->Np * c->ldz);
+    if (e == hipSuccess) e = hipMemset(c->flags, 0, sizeof(int32_t) * 4);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        fprintf(stderr, "matvis_init: %s\n", hipGetErrorString(e));
+        matvis_destroy(c);
+        return MATVIS_EHIP;
+    }
+    *out = c;
+    return MATVIS_OK;
+}
+
+const char *matvis_last_error(const matvis_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+matvis_status matvis_finish(matvis_ctx *c) {
+    if (!c) return MATVIS_EINVAL;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->last_stream));
+    int32_t h[4] = {0, 0, 0, 0};
+    HIPCHK(c, hipMemcpy(h, c->flags, sizeof(h), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemset(c->flags, 0, sizeof(h)));
+    HIPCHK(c, hipDeviceSynchronize());
+    if (h[0]) {
+        std::string m = "invalid input data:";
+        if (h[0] & FLAG_BAD_FLUX) m += " negative or non-finite flux;";
+        if (h[0] & FLAG_BAD_ANTPOS) m += " non-finite antenna position;";
+        if (h[0] & FLAG_BAD_BEAM_IDX) m += " beam index out of range;";
+        return fail(c, MATVIS_EDATA, m);
+    }
+    return MATVIS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Enqueue the whole simulate sequence on stream s (no host waits).
+matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_t *beam_idx, const double *freqs,
+                               int32_t n_freq, const double *lsts, int32_t n_time, const double *radec, int64_t n_src,
+                               const double *flux, const void *grid, void *vis, hipStream_t s) {
+    const matvis_config &g = c->cfg;
+    const int prec = g.precision;
+    STEP(c, MATVIS_STEP_OTHER, s,
+         launch_prep_inputs(antpos, g.n_ant, beam_idx, g.n_beam, flux, (int64_t)n_freq * n_src, c->antc, c->bidx,
+                            c->flags, s));
+    STEP(c, MATVIS_STEP_SKY, s, launch_xeq(radec, n_src, c->xeq, g.max_src, s));
+    STEP(c, MATVIS_STEP_SKY, s, launch_rotmats(lsts, n_time, g.latitude_rad, c->rot, s));
+    const int64_t n_chunks = std::max<int64_t>(1, (n_src + c->chunk - 1) / c->chunk);
+    const int ncomp = g.n_feed * g.n_ax;
+    for (int t0 = 0; t0 < n_time; t0 += c->ntb) {
+        const int ntb = std::min(c->ntb, n_time - t0);
+        for (int f0 = 0; f0 < n_freq; f0 += c->nfb) {
+            const int nfb = std::min(c->nfb, n_freq - f0);
+            Batch bt{t0, f0, ntb, nfb, ntb * nfb};
+            for (int64_t ch = 0; ch < n_chunks; ch++) {
+                const int64_t c0 = ch * c->chunk;
+                const int64_t ns = std::min(c->chunk, n_src - c0);
+                SkyBufs sb{c->xeq, g.max_src, c->rot, c->blk_count, c->blk_off, c->count, c->idx, c->s_hat, c->za_az,
+                           c->chunk};
+                if (n_chunks > 1 || f0 == 0) STEP(c, MATVIS_STEP_SKY, s, launch_sky(sb, t0, ntb, c0, ns, s));
+
+                InterpArgs ia{};
+                ia.grid = grid;
+                ia.n_freq_grid = n_freq;
+                ia.n_beam = g.n_beam;
+                ia.n_feed = g.n_feed;
+                ia.n_ax = g.n_ax;
+                ia.n_za = g.n_za;
+                ia.n_az = g.n_az;
+                ia.dza = g.dza_rad;
+                ia.daz = g.daz_rad;
+                ia.za_az = c->za_az;
+                ia.count = c->count;
+                ia.ld_src = c->chunk;
+                ia.A = c->A;
+                ia.max_m = ns;
+                STEP(c, MATVIS_STEP_BEAM, s, launch_interp(prec, g.beam_mode, ia, bt, s));
+
+                ZformArgs za{};
+                za.antc = c->antc;
+                za.bidx = c->bidx;
+                za.freqs = freqs;
+                za.flux = flux;
+                za.n_src = n_src;
+                za.idx = c->idx;
+                za.s_hat = c->s_hat;
+                za.count = c->count;
+                za.A = c->A;
+                za.ld_src = c->chunk;
+                za.n_ant = g.n_ant;
+                za.n_feed = g.n_feed;
+                za.n_ax = g.n_ax;
+                za.n_beam = g.n_beam;
+                za.Z = c->Z;
+                za.Z_lo = c->Z_lo;
+                za.ldz = c->ldz;
+                za.n_rows_pad = c->Np;
+                za.max_m = (round_up(g.n_ax * ns, kColPad) + g.n_ax - 1) / g.n_ax;
+                STEP(c, MATVIS_STEP_ZFORM, s, launch_zform(prec, za, bt, s));
+
+                HerkArgs ha{};
+                ha.Z = c->Z;
+                ha.Z_lo = c->Z_lo;
+                ha.ldz = c->ldz;
+                ha.inst_stride = (int64_t)c->Np * c->ldz;
+                ha.n_rows = c->N;
+                ha.n_rows_pad = c->Np;
+                ha.count = c->count;
+                ha.n_ax = g.n_ax;
+                ha.nfb = nfb;
+                ha.n_inst = bt.n_inst;
+                ha.ksplit = c->ksplit;
+                ha.max_splits = c->max_splits;
+                ha.part = c->part;
+                ha.work = c->work;
+                ha.grid = c->herk_grid;
+                STEP(c, MATVIS_STEP_OTHER, s, launch_worklist(prec, ha, s));
+                STEP(c, MATVIS_STEP_HERK, s, launch_herk(prec, ha, s));
+
+                ReduceArgs ra{};
+                ra.part = c->part;
+                ra.n_rows = c->N;
+                ra.n_rows_pad = c->Np;
+                ra.max_splits = c->max_splits;
+                ra.count = c->count;
+                ra.n_ax = g.n_ax;
+                ra.nfb = nfb;
+                ra.n_inst = bt.n_inst;
+                ra.ksplit = c->ksplit;
+                ra.vacc = c->vacc;
+                ra.first = ch == 0;
+                ra.last = ch == n_chunks - 1;
+                ra.out = vis;
+                ra.out_kind = 0;
+                ra.n_ant = g.n_ant;
+                ra.n_feed = g.n_feed;
+                ra.n_freq_total = n_freq;
+                ra.bt = bt;
+                STEP(c, MATVIS_STEP_REDUCE, s, launch_reduce(prec, ra, s));
+            }
+        }
+    }
+    (void)ncomp;
+    return MATVIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+matvis_status matvis_simulate(matvis_ctx *c, const double *antpos, const int32_t *beam_idx, const double *freqs,
+                              int32_t n_freq, const double *lsts, int32_t n_time, const double *src_radec,
+                              int64_t n_src, const double *src_flux, const void *beam_grid, void *vis, void *stream) {
+    if (!c) return MATVIS_EINVAL;
+    c->err.clear();
+    const matvis_config &g = c->cfg;
+    if (!antpos || !freqs || !lsts || !vis) return fail(c, MATVIS_EINVAL, "a required pointer is NULL");
+    if (n_src > 0 && (!src_radec || !src_flux)) return fail(c, MATVIS_EINVAL, "src_radec or src_flux is NULL");
+    if (!beam_grid) return fail(c, MATVIS_EINVAL, "beam_grid is NULL");
+    if (n_freq <= 0 || n_freq > g.max_freq) return fail(c, MATVIS_EINVAL, "n_freq outside [1, max_freq]");
+    if (n_time <= 0 || n_time > g.max_time) return fail(c, MATVIS_EINVAL, "n_time outside [1, max_time]");
+    if (n_src < 0 || n_src > g.max_src) return fail(c, MATVIS_EINVAL, "n_src outside [0, max_src]");
+    if (c->chunk < g.max_src && !c->vacc) return fail(c, MATVIS_ESTATE, "chunk accumulator missing");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    c->last_stream = s;
+    if (n_src == 0) {
+        const size_t vb = cbytes(g.precision) * (size_t)n_time * n_freq * g.n_ant * g.n_ant * g.n_feed * g.n_feed;
+        HIPCHK(c, hipMemsetAsync(vis, 0, vb, s));
+        return MATVIS_OK;
+    }
+    if ((g.flags & MATVIS_FLAG_NO_GRAPH) || c->profiling)
+        return enqueue_simulate(c, antpos, beam_idx, freqs, n_freq, lsts, n_time, src_radec, n_src, src_flux, beam_grid,
+                                vis, s);
+    GraphKey key;
+    key.v = {(uint64_t)antpos, (uint64_t)beam_idx, (uint64_t)freqs, (uint64_t)n_freq, (uint64_t)lsts,
+             (uint64_t)n_time, (uint64_t)src_radec, (uint64_t)n_src, (uint64_t)src_flux, (uint64_t)beam_grid,
+             (uint64_t)vis};
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+        matvis_status st = enqueue_simulate(c, antpos, beam_idx, freqs, n_freq, lsts, n_time, src_radec, n_src,
+                                            src_flux, beam_grid, vis, c->capture_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
+        if (st != MATVIS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+        if (c->graph_order.size() >= 8) {
+            auto old = c->graphs.find(c->graph_order.front());
+            if (old != c->graphs.end()) {
+                (void)hipGraphExecDestroy(old->second);
+                c->graphs.erase(old);
+            }
+            c->graph_order.erase(c->graph_order.begin());
+        }
+        it = c->graphs.emplace(key, exec).first;
+        c->graph_order.push_back(key);
+    }
+    HIPCHK(c, hipGraphLaunch(it->second, s));
+    return MATVIS_OK;
+}
+
+matvis_status matvis_profile_enable(matvis_ctx *c, int32_t enable) {
+    if (!c) return MATVIS_EINVAL;
+    c->err.clear();
+    c->profiling = enable != 0;
+    return MATVIS_OK;
+}
+
+matvis_status matvis_profile_read(matvis_ctx *c, double *ms, int64_t *launches) {
+    if (!c) return MATVIS_EINVAL;
+    c->err.clear();
+    if (!ms || !launches) return fail(c, MATVIS_EINVAL, "output arrays are NULL");
+    for (int k = 0; k < MATVIS_N_STEPS; k++) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    matvis_status st = MATVIS_OK;
+    for (auto &r : c->prof) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess && st == MATVIS_OK) st = hip_fail(c, e, "hipEventElapsedTime");
+        ms[r.kind] += t;
+        launches[r.kind] += 1;
+        c->event_pool.push_back(r.a);
+        c->event_pool.push_back(r.b);
+    }
+    c->prof.clear();
+    return st;
+}
+
+matvis_status matvis_step_sky(matvis_ctx *c, const double *lsts, int32_t n_time, const double *src_radec,
+                              int64_t n_src, int32_t *idx, int32_t *count, double *s_hat, double *za_az,
+                              void *stream) {
+    if (!c) return MATVIS_EINVAL;
+    c->err.clear();
+    const matvis_config &g = c->cfg;
+    if (!lsts || !src_radec || !idx || !count || !s_hat || !za_az)
+        return fail(c, MATVIS_EINVAL, "a required pointer is NULL");
+    if (n_time <= 0 || n_time > g.max_time) return fail(c, MATVIS_EINVAL, "n_time outside [1, max_time]");
+    if (n_src <= 0 || n_src > g.max_src) return fail(c, MATVIS_EINVAL, "n_src outside [1, max_src]");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    c->last_stream = s;
+    HIPCHK(c, launch_xeq(src_radec, n_src, c->xeq, g.max_src, s));
+    HIPCHK(c, launch_rotmats(lsts, n_time, g.latitude_rad, c->rot, s));
+    for (int t = 0; t < n_time; t++) {
+        SkyBufs sb{c->xeq, g.max_src, c->rot, c->blk_count, c->blk_off, count + t, idx + (int64_t)t * n_src,
+                   s_hat + (int64_t)t * 3 * n_src, za_az + (int64_t)t * 2 * n_src, n_src};
+        HIPCHK(c, launch_sky(sb, t, 1, 0, n_src, s));
+    }
+    return MATVIS_OK;
+}
+
+matvis_status matvis_step_interp(matvis_ctx *c, const double *za_az, int64_t n, const void *grid, void *A,
+                                 void *stream) {
+    if (!c) return MATVIS_EINVAL;
+    c->err.clear();
+    const matvis_config &g = c->cfg;
+    if (!za_az || !grid || !A) return fail(c, MATVIS_EINVAL, "a required pointer is NULL");
+    if (n < 0) return fail(c, MATVIS_EINVAL, "n must be non-negative");
+    if (g.beam_mode == MATVIS_BEAM_SURROGATE) return fail(c, MATVIS_EUNSUPPORTED, "grid interpolation not selected");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    c->last_stream = s;
+    InterpArgs ia{};
+    ia.grid = grid;
+    ia.n_freq_grid = 1;
+    ia.n_beam = g.n_beam;
+    ia.n_feed = g.n_feed;
+    ia.n_ax = g.n_ax;
+    ia.n_za = g.n_za;
+    ia.n_az = g.n_az;
+    ia.dza = g.dza_rad;
+    ia.daz = g.daz_rad;
+    ia.za_az = za_az;
+    ia.count = nullptr;
+    ia.fixed_count = n;
+    ia.ld_src = n;
+    ia.A = A;
+    ia.max_m = n;
+    Batch bt{0, 0, 1, 1, 1};
+    HIPCHK(c, launch_interp(g.precision, g.beam_mode, ia, bt, s));
+    return MATVIS_OK;
+}
+
+matvis_status matvis_step_herk(matvis_ctx *c, const void *Zin, int32_t n_row, int64_t n_col, int64_t ld, void *V,
+                               void *stream) {
+    if (!c) return MATVIS_EINVAL;
+    c->err.clear();
+    const matvis_config &g = c->cfg;
+    if (!Zin || !V) return fail(c, MATVIS_EINVAL, "a required pointer is NULL");
+    if (n_row <= 0 || n_row > c->N) return fail(c, MATVIS_EINVAL, "n_row outside [1, n_ant * n_feed]");
+    if (n_col < 0 || n_col > c->ldz) return fail(c, MATVIS_EINVAL, "n_col above the context's column capacity");
+    if (ld < n_col) return fail(c, MATVIS_EINVAL, "ld smaller than n_col");
+    const int prec = g.precision;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    c->last_stream = s;
+    const int np = (int)round_up(n_row, c->st);
+    const int64_t ncp = round_up(n_col, kColPad);
+    HIPCHK(c, launch_z_import(prec, Zin, n_row, np, n_col, ld, c->Z, c->Z_lo, c->ldz, ncp, s));
+    HerkArgs ha{};
+    ha.Z = c->Z;
+    ha.Z_lo = c->Z_lo;
+    ha.ldz = c->ldz;
+    ha.inst_stride = (int64_t)np * c->ldz;
+    ha.n_rows = n_row;
+    ha.n_rows_pad = np;
+    ha.count = nullptr;
+    ha.fixed_k = n_col;
+    ha.n_ax = 1;
+    ha.nfb = 1;
+    ha.n_inst = 1;
+    ha.ksplit = c->ksplit;
+    ha.max_splits = c->max_splits;
+    ha.part = c->part;
+    ha.work = c->work;
+    ha.grid = c->herk_grid;
+    HIPCHK(c, launch_worklist(prec, ha, s));
+    HIPCHK(c, launch_herk(prec, ha, s));
+    ReduceArgs ra{};
+    ra.part = c->part;
+    ra.n_rows = n_row;
+    ra.n_rows_pad = np;
+    ra.max_splits = c->max_splits;
+    ra.count = nullptr;
+    ra.fixed_k = n_col;
+    ra.n_ax = 1;
+    ra.nfb = 1;
+    ra.n_inst = 1;
+    ra.ksplit = c->ksplit;
+    ra.vacc = nullptr;
+    ra.first = 1;
+    ra.last = 1;
+    ra.out = V;
+    ra.out_kind = 1;
+    ra.n_ant = g.n_ant;
+    ra.n_feed = g.n_feed;
+    ra.n_freq_total = 1;
+    ra.bt = Batch{0, 0, 1, 1, 1};
+    HIPCHK(c, launch_reduce(prec, ra, s));
+    return MATVIS_OK;
+}
+
+}  // extern "C"

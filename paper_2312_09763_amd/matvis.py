@@ -1,0 +1,276 @@
+"""Python binding of libmatvis (ctypes).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of libmatvis.so.  PyTorch supplies device memory and the stream;
+tensors are passed by ``data_ptr()`` and must already live on the GPU in the
+dtype and layout the C ABI documents (include/matvis.h).
+
+The library is loaded from ``paper_2312_09763_amd/_lib/libmatvis.so`` (built
+in-tree by ``paper_2312_09763_amd/build.py``).  There is no fallback: if the
+library is missing or cannot be loaded, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libmatvis.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ESTATE, EDATA = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32, BF16X3 = 0, 1, 2
+BILINEAR, BICUBIC, SURROGATE = 0, 1, 2
+FLAG_NO_GRAPH = 1
+
+STEPS = ("sky", "beam", "zform", "herk", "reduce", "other")
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+BEAM_MODES = {"bilinear": BILINEAR, "bicubic": BICUBIC, "surrogate": SURROGATE}
+
+
+class MatvisError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_status_name(status)}: {message}")
+        self.status = status
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("n_ant", ctypes.c_int32), ("n_feed", ctypes.c_int32), ("n_ax", ctypes.c_int32),
+                ("n_beam", ctypes.c_int32), ("max_src", ctypes.c_int64), ("max_time", ctypes.c_int32),
+                ("max_freq", ctypes.c_int32), ("latitude_rad", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("beam_mode", ctypes.c_int32), ("n_za", ctypes.c_int32), ("n_az", ctypes.c_int32),
+                ("dza_rad", ctypes.c_double), ("daz_rad", ctypes.c_double), ("src_chunk", ctypes.c_int64),
+                ("batch_time", ctypes.c_int32), ("batch_freq", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def load_library():
+    """Load libmatvis.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libmatvis.so not found at {LIB_PATH}; build it with paper_2312_09763_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    L.matvis_init.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(_P)]
+    L.matvis_init.restype = ctypes.c_int
+    L.matvis_simulate.argtypes = [_P, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P,
+                                  _P, _P]
+    L.matvis_simulate.restype = ctypes.c_int
+    L.matvis_finish.argtypes = [_P]
+    L.matvis_finish.restype = ctypes.c_int
+    L.matvis_last_error.argtypes = [_P]
+    L.matvis_last_error.restype = ctypes.c_char_p
+    L.matvis_status_string.argtypes = [ctypes.c_int32]
+    L.matvis_status_string.restype = ctypes.c_char_p
+    L.matvis_destroy.argtypes = [_P]
+    L.matvis_destroy.restype = None
+    L.matvis_step_sky.argtypes = [_P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P, _P]
+    L.matvis_step_sky.restype = ctypes.c_int
+    L.matvis_step_interp.argtypes = [_P, _P, ctypes.c_int64, _P, _P, _P]
+    L.matvis_step_interp.restype = ctypes.c_int
+    L.matvis_step_herk.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _P, _P]
+    L.matvis_step_herk.restype = ctypes.c_int
+    L.matvis_profile_enable.argtypes = [_P, ctypes.c_int32]
+    L.matvis_profile_enable.restype = ctypes.c_int
+    L.matvis_profile_read.argtypes = [_P, _P, _P]
+    L.matvis_profile_read.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _status_name(s: int) -> str:
+    try:
+        return load_library().matvis_status_string(int(s)).decode()
+    except Exception:  # library unavailable: still give a readable message
+        return f"status {s}"
+
+
+@dataclasses.dataclass
+class Config:
+    """Mirror of matvis_config (include/matvis.h)."""
+    n_ant: int
+    n_feed: int = 1
+    n_ax: int = 1
+    n_beam: int = 1
+    max_src: int = 1
+    max_time: int = 1
+    max_freq: int = 1
+    latitude_rad: float = math.radians(-30.7)
+    precision: str = "fp32"
+    beam_mode: str = "bilinear"
+    n_za: int = 91
+    n_az: int = 360
+    dza_rad: float = math.radians(1.0)
+    daz_rad: float = math.radians(1.0)
+    src_chunk: int = 0
+    batch_time: int = 0
+    batch_freq: int = 0
+    use_graph: bool = True
+
+    def _c(self) -> _Config:
+        return _Config(self.n_ant, self.n_feed, self.n_ax, self.n_beam, self.max_src, self.max_time, self.max_freq,
+                       self.latitude_rad, PRECISIONS[self.precision], BEAM_MODES[self.beam_mode], self.n_za,
+                       self.n_az, self.dza_rad, self.daz_rad, self.src_chunk, self.batch_time, self.batch_freq,
+                       0 if self.use_graph else FLAG_NO_GRAPH)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+def _need(t, dtype, shape, name):
+    import torch
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Context:
+    """A libmatvis context: device scratch for the capacities in ``cfg``."""
+
+    def __init__(self, cfg: Config):
+        self.cfg = cfg
+        self._L = load_library()
+        h = _P()
+        st = self._L.matvis_init(ctypes.byref(cfg._c()), ctypes.byref(h))
+        if st != OK:
+            raise MatvisError(st, "matvis_init failed (details on stderr)")
+        self._h = h
+
+    @property
+    def complex_dtype(self):
+        import torch
+        return torch.complex128 if self.cfg.precision == "fp64" else torch.complex64
+
+    def _check(self, st: int):
+        if st != OK:
+            raise MatvisError(st, self._L.matvis_last_error(self._h).decode())
+
+    def simulate(self, antpos, freqs, lsts, src_radec, src_flux, beam_grid, vis=None, beam_idx=None, stream=None):
+        """Enqueue matvis_simulate; returns vis [t][f][a][b][p][q] (allocated if None)."""
+        import torch
+        c = self.cfg
+        n_freq, n_time, n_src = freqs.shape[0], lsts.shape[0], src_radec.shape[1]
+        _need(antpos, torch.float64, (c.n_ant, 3), "antpos")
+        _need(freqs, torch.float64, (n_freq,), "freqs")
+        _need(lsts, torch.float64, (n_time,), "lsts")
+        _need(src_radec, torch.float64, (2, n_src), "src_radec")
+        _need(src_flux, torch.float64, (n_freq, n_src), "src_flux")
+        _need(beam_grid, self.complex_dtype, (c.n_beam, n_freq, c.n_feed, c.n_ax, c.n_za, c.n_az), "beam_grid")
+        if beam_idx is not None:
+            _need(beam_idx, torch.int32, (c.n_ant,), "beam_idx")
+        shape = (n_time, n_freq, c.n_ant, c.n_ant, c.n_feed, c.n_feed)
+        if vis is None:
+            vis = torch.empty(shape, dtype=self.complex_dtype, device=antpos.device)
+        _need(vis, self.complex_dtype, shape, "vis")
+        self._check(self._L.matvis_simulate(self._h, _ptr(antpos), _ptr(beam_idx), _ptr(freqs), n_freq, _ptr(lsts),
+                                            n_time, _ptr(src_radec), n_src, _ptr(src_flux), _ptr(beam_grid),
+                                            _ptr(vis), _stream_handle(stream)))
+        return vis
+
+    def finish(self):
+        """Synchronise and report deferred device-side errors (MATVIS_EDATA)."""
+        self._check(self._L.matvis_finish(self._h))
+
+    def profile(self, enable: bool = True):
+        """Time every step's launches with HIP events (launches go direct, not via the graph)."""
+        self._check(self._L.matvis_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{step: (total device ms, launches)} since the last read."""
+        ms = (ctypes.c_double * len(STEPS))()
+        n = (ctypes.c_int64 * len(STEPS))()
+        self._check(self._L.matvis_profile_read(self._h, ms, n))
+        return {name: (ms[i], n[i]) for i, name in enumerate(STEPS)}
+
+    def step_sky(self, lsts, src_radec, stream=None):
+        """Alg. 2 step (i): (idx, count, s_hat, za_az) for every time."""
+        import torch
+        n_time, n_src = lsts.shape[0], src_radec.shape[1]
+        _need(lsts, torch.float64, (n_time,), "lsts")
+        _need(src_radec, torch.float64, (2, n_src), "src_radec")
+        dev = lsts.device
+        idx = torch.empty((n_time, n_src), dtype=torch.int32, device=dev)
+        count = torch.empty((n_time,), dtype=torch.int32, device=dev)
+        s_hat = torch.empty((n_time, 3, n_src), dtype=torch.float64, device=dev)
+        za_az = torch.empty((n_time, 2, n_src), dtype=torch.float64, device=dev)
+        self._check(self._L.matvis_step_sky(self._h, _ptr(lsts), n_time, _ptr(src_radec), n_src, _ptr(idx),
+                                            _ptr(count), _ptr(s_hat), _ptr(za_az), _stream_handle(stream)))
+        return idx, count, s_hat, za_az
+
+    def step_interp(self, za_az, grid, stream=None):
+        """Alg. 2 step (ii) alone: beam at points za_az [2][n] from one channel's grid."""
+        import torch
+        c = self.cfg
+        n = za_az.shape[1]
+        _need(za_az, torch.float64, (2, n), "za_az")
+        _need(grid, self.complex_dtype, (c.n_beam, c.n_feed, c.n_ax, c.n_za, c.n_az), "grid")
+        A = torch.empty((c.n_beam, c.n_feed, c.n_ax, n), dtype=self.complex_dtype, device=za_az.device)
+        self._check(self._L.matvis_step_interp(self._h, _ptr(za_az), n, _ptr(grid), _ptr(A), _stream_handle(stream)))
+        return A
+
+    def step_herk(self, Z, stream=None):
+        """Step (v) alone: V = Z Z^H for a [n_row][n_col] complex matrix."""
+        import torch
+        n_row, n_col = Z.shape
+        _need(Z, self.complex_dtype, (n_row, n_col), "Z")
+        V = torch.empty((n_row, n_row), dtype=self.complex_dtype, device=Z.device)
+        self._check(self._L.matvis_step_herk(self._h, _ptr(Z), n_row, n_col, n_col, _ptr(V), _stream_handle(stream)))
+        return V
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.matvis_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def config_for(wl, precision: str = "fp32", **kw) -> Config:
+    """Context configuration sized for a synthetic workload (paper_2312_09763_amd.synth.Workload)."""
+    n_za, n_az = wl.beam.shape[-2], wl.beam.shape[-1]
+    args = dict(n_ant=wl.n_ant, n_feed=wl.n_feed, n_ax=wl.n_ax, n_beam=wl.beam.shape[0], max_src=max(wl.n_src, 1),
+                max_time=wl.n_time, max_freq=wl.n_freq, latitude_rad=wl.latitude, precision=precision,
+                beam_mode=wl.interp, n_za=n_za, n_az=n_az, dza_rad=wl.dza, daz_rad=wl.daz)
+    args.update(kw)
+    return Config(**args)
+
+
+def device_inputs(wl, precision: str = "fp32", device: str = "cuda"):
+    """Move a synthetic workload's arrays to the device in the ABI's dtypes."""
+    import numpy as np
+    import torch
+    cd = np.complex128 if precision == "fp64" else np.complex64
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
+    return dict(antpos=t(wl.antpos, np.float64), freqs=t(wl.freqs, np.float64), lsts=t(wl.lsts, np.float64),
+                src_radec=t(wl.radec, np.float64), src_flux=t(wl.flux, np.float64), beam_grid=t(wl.beam, cd))

@@ -1,0 +1,47 @@
+"""Shared helpers for the GPU tests (run the HIP path, run the oracle)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from oracle import metrics
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-3}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_simulate(wl, precision, **cfgkw):
+    """Run matvis_simulate on the GPU for every (t, f) of a workload; V as [inst][a][b][p][q] c128."""
+    import torch
+    from paper_2312_09763_amd import matvis as mv
+    cfg = mv.config_for(wl, precision, **cfgkw)
+    d = mv.device_inputs(wl, precision)
+    with mv.Context(cfg) as ctx:
+        vis = ctx.simulate(**d)
+        ctx.finish()
+        torch.cuda.synchronize()
+        V = vis.cpu().numpy().astype(np.complex128)
+    return V.reshape((-1,) + V.shape[2:])
+
+
+def oracle_vis(wl, instances=None, grid=None):
+    import oracle
+    g = wl.beam if grid is None else grid
+    return oracle.simulate(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, wl.flux, g, wl.latitude, wl.dza, wl.daz,
+                           wl.interp, instances=instances)
+
+
+def grid_as_used(wl, precision):
+    """The beam grid values the device sees (complex64 unless FP64), upcast for the oracle."""
+    if precision == "fp64":
+        return wl.beam
+    return wl.beam.astype(np.complex64).astype(np.complex128)
+
+
+def errors(V, Vref):
+    return float(metrics.err_f(V, Vref).max()), float(metrics.err_cs(V, Vref).max())

@@ -1,0 +1,82 @@
+"""The C ABI without a GPU: the library loads, exports what the header
+declares, and rejects bad configurations before touching the device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2312_09763_amd import matvis as mv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "matvis.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(matvis_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    L = mv.load_library()
+    names = declared_functions()
+    assert "matvis_simulate" in names and "matvis_init" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    L = mv.load_library()
+    assert L.matvis_status_string(0) == b"MATVIS_OK"
+    assert L.matvis_status_string(-6) == b"MATVIS_EDATA"
+    assert L.matvis_status_string(99) == b"unknown status"
+
+
+def _init(**kw):
+    base = dict(n_ant=4, n_feed=1, n_ax=1, n_beam=1, max_src=10, max_time=1, max_freq=1, n_za=91, n_az=360,
+                dza_rad=math.radians(1.0), daz_rad=math.radians(1.0))
+    base.update(kw)
+    cfg = mv.Config(**base)
+    h = ctypes.c_void_p()
+    return mv.load_library().matvis_init(ctypes.byref(cfg._c()), ctypes.byref(h)), h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_ant=0), mv.EINVAL),
+    (dict(n_feed=3), mv.EINVAL),
+    (dict(n_ax=0), mv.EINVAL),
+    (dict(n_beam=0), mv.EINVAL),
+    (dict(max_src=0), mv.EINVAL),
+    (dict(max_time=0), mv.EINVAL),
+    (dict(n_za=2), mv.EINVAL),
+    (dict(n_za=90), mv.EINVAL),           # rows do not reach the horizon
+    (dict(n_az=359), mv.EINVAL),          # not periodic
+    (dict(latitude_rad=2.0), mv.EINVAL),
+    (dict(beam_mode="surrogate"), mv.EUNSUPPORTED),
+    (dict(n_ant=5000, n_feed=2), mv.EUNSUPPORTED),
+])
+def test_init_rejects_bad_config(kw, status):
+    st, h = _init(**kw)
+    assert st == status
+    assert not h.value
+
+
+def test_init_null_out_pointer():
+    cfg = mv.Config(n_ant=4, max_src=10)
+    assert mv.load_library().matvis_init(ctypes.byref(cfg._c()), None) == mv.EINVAL
+
+
+def test_null_context_calls():
+    L = mv.load_library()
+    assert L.matvis_finish(None) == mv.EINVAL
+    assert L.matvis_last_error(None) == b"NULL context"
+    assert L.matvis_simulate(None, None, None, None, 1, None, 1, None, 1, None, None, None, None) == mv.EINVAL
+    L.matvis_destroy(None)
+
+
+def test_binding_refuses_without_library(monkeypatch):
+    monkeypatch.setattr(mv, "_lib", None)
+    monkeypatch.setattr(mv, "LIB_PATH", "/nonexistent/libmatvis.so")
+    with pytest.raises(RuntimeError):
+        mv.load_library()

@@ -1,0 +1,183 @@
+"""End-to-end parity: matvis_simulate on the GPU against the FP64 direct-sum
+oracle on the same seeded inputs, plus the edge cases of the method.
+
+Tolerances (err_F and err_CS, max over instances): FP64 <= 1e-10, FP32 <=
+1e-5, BF16X3 <= 1e-3 (reported against 1e-5 too).  The FP32 / BF16X3 runs use
+complex64 beam grids; the oracle evaluates the same grid values in FP64.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2312_09763_amd import matvis as mv
+from paper_2312_09763_amd import synth
+
+from helpers import TOL, errors, gpu_simulate, grid_as_used, oracle_vis, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wl1():
+    return synth.workload(1)
+
+
+@pytest.fixture(scope="module")
+def wl2_small():
+    # 128 polarised antennas (N = 256: two row blocks), ragged source count
+    return synth.workload(2, n_src=1501, n_time=3, n_freq=2)
+
+
+@pytest.fixture(scope="module")
+def wl2_ragged():
+    # N = 150 rows (ragged against the 128-row super-tile)
+    return synth.workload(2, n_ant=75, n_src=2333, n_time=2, n_freq=3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_workload1_full(wl1, precision):
+    say(f"workload1 {precision}")
+    V = gpu_simulate(wl1, precision)
+    ref = oracle_vis(wl1, grid=grid_as_used(wl1, precision))
+    ef, ec = errors(V, ref)
+    say(f"  err_F={ef:.3e} err_CS={ec:.3e}")
+    assert ef <= TOL[precision] and ec <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_workload2_polarised(wl2_small, precision):
+    say(f"workload2 small {precision}")
+    V = gpu_simulate(wl2_small, precision)
+    ref = oracle_vis(wl2_small, grid=grid_as_used(wl2_small, precision))
+    ef, ec = errors(V, ref)
+    say(f"  err_F={ef:.3e} err_CS={ec:.3e}")
+    assert ef <= TOL[precision] and ec <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_ragged_rows_chunks_and_batches(wl2_ragged, precision):
+    """N = 150, three source chunks (last one ragged), batches of 1 time x 2 channels."""
+    say(f"ragged {precision}")
+    V = gpu_simulate(wl2_ragged, precision, src_chunk=1000, batch_time=1, batch_freq=2)
+    ref = oracle_vis(wl2_ragged, grid=grid_as_used(wl2_ragged, precision))
+    ef, ec = errors(V, ref)
+    say(f"  err_F={ef:.3e} err_CS={ec:.3e}")
+    assert ef <= TOL[precision] and ec <= TOL[precision]
+
+
+def test_scalar_beam_bicubic_and_per_antenna_beams(orc):
+    """Scalar Gaussian grid, bicubic, two unique beams selected by beam_idx."""
+    import torch
+    wl = synth.workload(1, n_src=800, n_time=2, n_freq=2)
+    g2 = np.concatenate([wl.beam, 0.5 * wl.beam ** 2], axis=0)  # a second, narrower beam
+    bidx = (np.arange(wl.n_ant) % 2).astype(np.int32)
+    cfg = mv.config_for(wl, "fp64", beam_mode="bicubic")
+    cfg.n_beam = 2
+    d = mv.device_inputs(wl, "fp64")
+    d["beam_grid"] = torch.from_numpy(g2).cuda()
+    with mv.Context(cfg) as ctx:
+        V = ctx.simulate(**d, beam_idx=torch.from_numpy(bidx).cuda()).cpu().numpy()
+        ctx.finish()
+    V = V.reshape((-1,) + V.shape[2:])
+    ref = orc.simulate(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, wl.flux, g2, wl.latitude, wl.dza, wl.daz,
+                       "bicubic", beam_idx=bidx)
+    ef, ec = errors(V, ref)
+    say(f"two beams bicubic: err_F={ef:.3e} err_CS={ec:.3e}")
+    assert ef <= 1e-10 and ec <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_zenith_source_gives_flux(precision):
+    """A unit beam and one source at the zenith: V_ab = I for every pair (zero phase)."""
+    import torch
+    wl = synth.workload(1, n_src=1, n_time=1, n_freq=1)
+    lst = 0.9
+    wl.lsts = np.array([lst])
+    wl.ra, wl.dec = np.array([lst]), np.array([wl.latitude])
+    wl.flux = np.array([[2.5]])
+    wl.beam = np.ones_like(wl.beam)
+    V = gpu_simulate(wl, precision)
+    # one source: no averaging, so BF16X3 shows its per-element split error (~2^-16 per factor)
+    tol = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 1e-4}[precision]
+    np.testing.assert_allclose(V[0, :, :, 0, 0], 2.5, rtol=0, atol=2.5 * tol)
+
+
+def test_no_visible_sources_and_no_sources():
+    import torch
+    wl = synth.workload(1, n_src=500, n_time=2, n_freq=1)
+    # declinations above 60 deg never rise at latitude -30.7 deg
+    wl.dec = np.full(wl.n_src, math.radians(75.0))
+    V = gpu_simulate(wl, "fp32")
+    assert np.all(V == 0)
+    cfg = mv.config_for(wl, "fp32")
+    d = mv.device_inputs(wl, "fp32")
+    d["src_radec"] = d["src_radec"][:, :0].contiguous()
+    d["src_flux"] = d["src_flux"][:, :0].contiguous()
+    with mv.Context(cfg) as ctx:
+        vis = ctx.simulate(**d)
+        ctx.finish()
+        assert torch.count_nonzero(vis).item() == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_deterministic_hermitian_and_graph_equals_direct(wl2_small, precision):
+    import torch
+    cfg = mv.config_for(wl2_small, precision)
+    d = mv.device_inputs(wl2_small, precision)
+    with mv.Context(cfg) as ctx:
+        a = ctx.simulate(**d).clone()
+        b = ctx.simulate(**d).clone()  # graph replay
+        ctx.finish()
+    cfg.use_graph = False
+    with mv.Context(cfg) as ctx:
+        c = ctx.simulate(**d).clone()
+        ctx.finish()
+    assert torch.equal(a, b) and torch.equal(a, c)
+    v = a.cpu().numpy()
+    np.testing.assert_array_equal(v, np.conj(np.transpose(v, (0, 1, 3, 2, 5, 4))))
+    auto = np.einsum("tfaapp->tfap", v)
+    assert np.all(auto.imag == 0) and np.all(auto.real > 0)
+
+
+def test_invalid_flux_is_reported_and_context_survives(wl1):
+    import torch
+    cfg = mv.config_for(wl1, "fp32")
+    d = mv.device_inputs(wl1, "fp32")
+    with mv.Context(cfg) as ctx:
+        bad = d["src_flux"].clone()
+        bad[1, 7] = -1.0
+        ctx.simulate(**{**d, "src_flux": bad})
+        with pytest.raises(mv.MatvisError) as e:
+            ctx.finish()
+        assert e.value.status == mv.EDATA
+        bad[1, 7] = float("nan")
+        ctx.simulate(**{**d, "src_flux": bad})
+        with pytest.raises(mv.MatvisError):
+            ctx.finish()
+        # a good call afterwards works and matches a fresh context
+        v1 = ctx.simulate(**d).clone()
+        ctx.finish()
+    with mv.Context(cfg) as ctx:
+        v2 = ctx.simulate(**d).clone()
+        ctx.finish()
+    assert torch.equal(v1, v2)
+
+
+def test_argument_errors(wl1):
+    import torch
+    cfg = mv.config_for(wl1, "fp32")
+    d = mv.device_inputs(wl1, "fp32")
+    with mv.Context(cfg) as ctx:
+        L = mv.load_library()
+        st = L.matvis_simulate(ctx._h, d["antpos"].data_ptr(), None, d["freqs"].data_ptr(), 99,
+                               d["lsts"].data_ptr(), 1, d["src_radec"].data_ptr(), wl1.n_src,
+                               d["src_flux"].data_ptr(), d["beam_grid"].data_ptr(), d["antpos"].data_ptr(), None)
+        assert st == mv.EINVAL and b"n_freq" in L.matvis_last_error(ctx._h)
+        st = L.matvis_simulate(ctx._h, d["antpos"].data_ptr(), None, d["freqs"].data_ptr(), 1,
+                               d["lsts"].data_ptr(), 1, d["src_radec"].data_ptr(), wl1.n_src + 1,
+                               d["src_flux"].data_ptr(), d["beam_grid"].data_ptr(), d["antpos"].data_ptr(), None)
+        assert st == mv.EINVAL
+        # still usable
+        ctx.simulate(**d)
+        ctx.finish()

@@ -354,3 +354,18 @@ def test_fringe_spacing_matches_paper(orc):
         period_rad = 2 * math.pi / abs(np.polyfit(ha, ph, 1)[0])
         period_arcmin = math.degrees(period_rad) * 60
         assert abs(period_arcmin - case["spacing_arcmin"]) / case["spacing_arcmin"] < gold["rel_tol"], period_arcmin
+
+
+def test_pair_subset_equals_full_direct_sum(orc):
+    """The pair-sampled direct sum gives exactly the listed entries of the full one."""
+    d = _small_workload(orc)
+    wl = d["wl"]
+    V = orc.simulate(*d["args"])
+    inst = [(0, 0), (1, 1)]
+    pairs = [(0, 0), (0, 5), (5, 0), (3, 2)]
+    args = d["args"]
+    Vp = orc.simulate_pairs(*args[:11], instances=inst, pairs=pairs)
+    for ii, (t, f) in enumerate(inst):
+        full = V[t * wl.n_freq + f]
+        for j, (a, b) in enumerate(pairs):
+            np.testing.assert_array_equal(Vp[ii, j], full[a, b])
