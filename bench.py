@@ -50,6 +50,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--profile-steps", type=int, default=2)
+    ap.add_argument("--unfused", action="store_true", help="write Z to HBM in its own step (FP32 / BF16X3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-src", type=int, default=None, help="shrink the workload (smoke runs only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -78,7 +79,7 @@ def main():
     prec = args.precision
     wl = synth.workload(2, n_src=args.n_src)
     log(f"workload2: n_ant={wl.n_ant} n_src={wl.n_src} n_time={wl.n_time} n_freq={wl.n_freq} precision={prec}")
-    cfg = mv.config_for(wl, prec)
+    cfg = mv.config_for(wl, prec, unfused=args.unfused)
     ctx = mv.Context(cfg)
     d = mv.device_inputs(wl, prec)
     vis = torch.empty((wl.n_time, wl.n_freq, wl.n_ant, wl.n_ant, wl.n_feed, wl.n_feed), dtype=ctx.complex_dtype,
@@ -165,10 +166,11 @@ def main():
         "config": {"workload": "128-antenna polarised hex array, 50000 point sources, 32 LSTs x 16 channels "
                                "100-200 MHz, dipole Jones beam 0.5 deg grid bicubic",
                    "n_ant": wl.n_ant, "n_feed": wl.n_feed, "n_ax": wl.n_ax, "n_src": wl.n_src,
-                   "n_time": wl.n_time, "n_freq": wl.n_freq, "precision": prec},
+                   "n_time": wl.n_time, "n_freq": wl.n_freq, "precision": prec,
+                   "z_in_hbm": bool(prec == "fp64" or args.unfused)},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
-                     "kernel": "k_herk", "launch_ms": herk_ms_launch, "flops_per_launch": flops_launch,
+                     "kernel": "k_herk" if (prec == "fp64" or args.unfused) else "k_herk_fused", "launch_ms": herk_ms_launch, "flops_per_launch": flops_launch,
                      "useful_tflops": achieved / PRODUCTS[prec]},
         "zform": {"achieved_GBps": z_bytes_step * args.profile_steps / (zform_ms / 1e3) / 1e9 if zform_ms else None,
                   "peak_GBps": HBM_GBS},

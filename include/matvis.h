@@ -90,6 +90,8 @@ typedef struct {
 } matvis_config;
 
 #define MATVIS_FLAG_NO_GRAPH 1 /* launch kernels directly instead of replaying a captured hipGraph */
+#define MATVIS_FLAG_UNFUSED 2  /* FP32 / BF16X3: write Z to device memory in a separate step
+                                  (Alg. 2 step (iv)) instead of forming it inside the product */
 
 /* Create a context on the current HIP device and allocate all scratch for the
  * capacities in *cfg.  Returns MATVIS_EINVAL for inconsistent sizes (n_feed or

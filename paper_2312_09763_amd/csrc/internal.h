@@ -66,6 +66,10 @@ struct InterpArgs {
     int64_t ld_src;
     void *A;                 // [n_inst][n_beam][n_feed][n_ax][ld_src]
     int64_t max_m;           // grid size along sources
+    // optional: multiply by sqrt(I) of the source (B = sqrt(I) A for the fused product)
+    const int32_t *idx;      // [nslots][ld_src] absolute source indices, or null
+    const double *flux;      // [n_freq][n_src]
+    int64_t n_src;
 };
 hipError_t launch_interp(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s);
 
@@ -118,6 +122,27 @@ int herk_occupancy(int prec);  // resident workgroups per CU
 // Item prefix over the batch (k_worklist), then the persistent product kernel.
 hipError_t launch_worklist(int prec, const HerkArgs &a, hipStream_t s);
 hipError_t launch_herk(int prec, const HerkArgs &a, hipStream_t s);
+
+// Product with Z formed in LDS (kernels_herk_fused.hip); FP32 and BF16X3 only.
+struct FusedArgs {
+    const double *antc;      // [n_ant][3] centred ENU
+    const int32_t *bidx;     // [n_ant]
+    const double *freqs;     // [n_freq]
+    const double *s_hat;     // [nslots][3][ld_src]
+    const void *B;           // sqrt(I) A, complex64 [n_inst][n_beam][n_feed][n_ax][ld_src]
+    const int32_t *count;    // [nslots]
+    int64_t ld_src;
+    int32_t n_ant, n_feed, n_ax, n_beam;
+    int32_t n_rows_pad;
+    int32_t f0, nfb, n_inst;
+    int64_t ksplit;          // columns per work item (a multiple of 64)
+    int32_t max_splits;
+    void *part;
+    int32_t *work;           // built by launch_worklist
+    int32_t grid;
+};
+hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s);
+int herk_fused_occupancy(int prec);
 
 struct ReduceArgs {
     const void *part;

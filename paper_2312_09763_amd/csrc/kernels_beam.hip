@@ -65,6 +65,8 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs a, Batch bt) {
     const int ncomp = a.n_feed * a.n_ax;
     const C *grid = (const C *)a.grid;
     C *out = (C *)a.A + (int64_t)inst * a.n_beam * ncomp * a.ld_src;
+    // B = sqrt(I) A when the product forms Z itself
+    const R sq = a.idx ? (R)sqrt(a.flux[(int64_t)f * a.n_src + a.idx[(int64_t)slot * a.ld_src + m]]) : R(1);
 
     if (MODE == BILINEAR) {
         const int k1 = k0 + 1 == n_az ? 0 : k0 + 1;
@@ -76,8 +78,8 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs a, Batch bt) {
                 const C g00 = g[(int64_t)j0 * n_az + k0], g01 = g[(int64_t)j0 * n_az + k1];
                 const C g10 = g[(int64_t)(j0 + 1) * n_az + k0], g11 = g[(int64_t)(j0 + 1) * n_az + k1];
                 C r;
-                r.x = w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x;
-                r.y = w00 * g00.y + w01 * g01.y + w10 * g10.y + w11 * g11.y;
+                r.x = sq * (w00 * g00.x + w01 * g01.x + w10 * g10.x + w11 * g11.x);
+                r.y = sq * (w00 * g00.y + w01 * g01.y + w10 * g10.y + w11 * g11.y);
                 out[((int64_t)b * ncomp + c) * a.ld_src + m] = r;
             }
     } else {
@@ -124,8 +126,8 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs a, Batch bt) {
                     accy += wj[dj] * ry;
                 }
                 C r;
-                r.x = accx;
-                r.y = accy;
+                r.x = sq * accx;
+                r.y = sq * accy;
                 out[((int64_t)b * ncomp + c) * a.ld_src + m] = r;
             }
     }

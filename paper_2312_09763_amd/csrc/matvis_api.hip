@@ -21,7 +21,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/matvis.h"
+#include "matvis.h"
 #include "internal.h"
 
 using namespace mv;
@@ -46,8 +46,9 @@ struct matvis_ctx {
     // derived geometry
     int N = 0, Np = 0, st = 128;
     int64_t chunk = 0, ldz = 0, ksplit = 4096;
-    int max_splits = 1, ntb = 1, nfb = 1, herk_grid = 512;
+    int max_splits = 1, ntb = 1, nfb = 1, herk_grid = 512, fused_grid = 256;
     int64_t nblk_cap = 1;
+    bool fused = false;  // Z formed inside the product (FP32 / BF16X3)
 
     // device scratch
     double *xeq = nullptr, *rot = nullptr, *antc = nullptr, *s_hat = nullptr, *za_az = nullptr, *vacc = nullptr;
@@ -221,7 +222,10 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     // batch: all channels of a few times, enough instances to fill the GPU with
     // work items while keeping Z within a fixed share of device memory
     c->nfb = cfg->batch_freq > 0 ? std::min(cfg->batch_freq, cfg->max_freq) : std::min(cfg->max_freq, 16);
-    size_t zinst = (size_t)c->Np * c->ldz * cbytes(prec);
+    c->fused = prec != P64 && !(cfg->flags & MATVIS_FLAG_UNFUSED);
+    // per-instance scratch that scales with the batch: Z (unfused only) and the k-split partials
+    size_t zinst = (c->fused ? 0 : (size_t)c->Np * c->ldz * cbytes(prec)) +
+                   (size_t)c->max_splits * c->Np * c->Np * cbytes(prec);
     size_t budget = (size_t)12 << 30;
     int ntb_auto = (int)std::max<size_t>(1, budget / std::max<size_t>(1, zinst * c->nfb));
     c->ntb = cfg->batch_time > 0 ? cfg->batch_time : std::min(ntb_auto, 8);
@@ -231,6 +235,10 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     int64_t nblk_total = std::max<int64_t>(c->nblk_cap * c->ntb, (cfg->max_src + 255) / 256);
     int occ = std::max(1, herk_occupancy(prec));
     c->herk_grid = std::max(8, (c->n_cu * occ / 8) * 8);
+    if (c->fused) c->fused_grid = std::max(8, (c->n_cu * std::max(1, herk_fused_occupancy(prec)) / 8) * 8);
+    // Z scratch: a whole batch when Z goes through device memory, else one
+    // instance (used only by matvis_step_herk)
+    const int zinst_n = c->fused ? 1 : B;
 
     const size_t ncomp = (size_t)cfg->n_beam * cfg->n_feed * cfg->n_ax;
 #define ALLOC(ptr, bytes)                              \
@@ -254,19 +262,16 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     ALLOC(c->s_hat, sizeof(double) * 3 * c->ntb * c->chunk);
     ALLOC(c->za_az, sizeof(double) * 2 * c->ntb * c->chunk);
     ALLOC(c->A, cbytes(prec) * ncomp * B * c->chunk);
-    if (prec == PB3) {
-        ALLOC(c->Z, (size_t)4 * B * c->Np * c->ldz);
-        ALLOC(c->Z_lo, (size_t)4 * B * c->Np * c->ldz);
-    } else {
-        ALLOC(c->Z, cbytes(prec) * B * c->Np * c->ldz);
-    }
+    const size_t zbytes = (prec == PB3 ? (size_t)4 : cbytes(prec)) * zinst_n * c->Np * c->ldz;
+    ALLOC(c->Z, zbytes);
+    if (prec == PB3) ALLOC(c->Z_lo, zbytes);
     ALLOC(c->part, cbytes(prec) * B * (size_t)c->max_splits * c->Np * c->Np);
     if (c->chunk < cfg->max_src) ALLOC(c->vacc, sizeof(double) * 2 * B * (size_t)c->N * c->N);
     ALLOC(c->work, sizeof(int32_t) * (B + 1));
 #undef ALLOC
     // Rows N..Np-1 of Z are never written by the kernels and must read as zero.
-    hipError_t e = hipMemset(c->Z, 0, prec == PB3 ? (size_t)4 * B * c->Np * c->ldz : cbytes(prec) * B * c->Np * c->ldz);
-    if (e == hipSuccess && c->Z_lo) e = hipMemset(c->Z_lo, 0, (size_t)4 * B * c->Np * c->ldz);
+    hipError_t e = hipMemset(c->Z, 0, zbytes);
+    if (e == hipSuccess && c->Z_lo) e = hipMemset(c->Z_lo, 0, zbytes);
     if (e == hipSuccess) e = hipMemset(c->flags, 0, sizeof(int32_t) * 4);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -344,7 +349,55 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 ia.ld_src = c->chunk;
                 ia.A = c->A;
                 ia.max_m = ns;
+                if (c->fused) {
+                    ia.idx = c->idx;
+                    ia.flux = flux;
+                    ia.n_src = n_src;
+                }
                 STEP(c, MATVIS_STEP_BEAM, s, launch_interp(prec, g.beam_mode, ia, bt, s));
+
+                HerkArgs ha{};
+                ha.Z = c->Z;
+                ha.Z_lo = c->Z_lo;
+                ha.ldz = c->ldz;
+                ha.inst_stride = (int64_t)c->Np * c->ldz;
+                ha.n_rows = c->N;
+                ha.n_rows_pad = c->Np;
+                ha.count = c->count;
+                ha.n_ax = g.n_ax;
+                ha.nfb = nfb;
+                ha.n_inst = bt.n_inst;
+                ha.ksplit = c->ksplit;
+                ha.max_splits = c->max_splits;
+                ha.part = c->part;
+                ha.work = c->work;
+                ha.grid = c->herk_grid;
+                STEP(c, MATVIS_STEP_OTHER, s, launch_worklist(prec, ha, s));
+
+                if (c->fused) {
+                    FusedArgs fa{};
+                    fa.antc = c->antc;
+                    fa.bidx = c->bidx;
+                    fa.freqs = freqs;
+                    fa.s_hat = c->s_hat;
+                    fa.B = c->A;
+                    fa.count = c->count;
+                    fa.ld_src = c->chunk;
+                    fa.n_ant = g.n_ant;
+                    fa.n_feed = g.n_feed;
+                    fa.n_ax = g.n_ax;
+                    fa.n_beam = g.n_beam;
+                    fa.n_rows_pad = c->Np;
+                    fa.f0 = f0;
+                    fa.nfb = nfb;
+                    fa.n_inst = bt.n_inst;
+                    fa.ksplit = c->ksplit;
+                    fa.max_splits = c->max_splits;
+                    fa.part = c->part;
+                    fa.work = c->work;
+                    fa.grid = c->fused_grid;
+                    STEP(c, MATVIS_STEP_HERK, s, launch_herk_fused(prec, fa, s));
+                }
 
                 ZformArgs za{};
                 za.antc = c->antc;
@@ -366,26 +419,10 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 za.ldz = c->ldz;
                 za.n_rows_pad = c->Np;
                 za.max_m = (round_up(g.n_ax * ns, kColPad) + g.n_ax - 1) / g.n_ax;
-                STEP(c, MATVIS_STEP_ZFORM, s, launch_zform(prec, za, bt, s));
-
-                HerkArgs ha{};
-                ha.Z = c->Z;
-                ha.Z_lo = c->Z_lo;
-                ha.ldz = c->ldz;
-                ha.inst_stride = (int64_t)c->Np * c->ldz;
-                ha.n_rows = c->N;
-                ha.n_rows_pad = c->Np;
-                ha.count = c->count;
-                ha.n_ax = g.n_ax;
-                ha.nfb = nfb;
-                ha.n_inst = bt.n_inst;
-                ha.ksplit = c->ksplit;
-                ha.max_splits = c->max_splits;
-                ha.part = c->part;
-                ha.work = c->work;
-                ha.grid = c->herk_grid;
-                STEP(c, MATVIS_STEP_OTHER, s, launch_worklist(prec, ha, s));
-                STEP(c, MATVIS_STEP_HERK, s, launch_herk(prec, ha, s));
+                if (!c->fused) {
+                    STEP(c, MATVIS_STEP_ZFORM, s, launch_zform(prec, za, bt, s));
+                    STEP(c, MATVIS_STEP_HERK, s, launch_herk(prec, ha, s));
+                }
 
                 ReduceArgs ra{};
                 ra.part = c->part;

@@ -24,6 +24,7 @@ OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ESTATE, EDATA = 0, -1, -2, -3, -4, -5, -
 FP64, FP32, BF16X3 = 0, 1, 2
 BILINEAR, BICUBIC, SURROGATE = 0, 1, 2
 FLAG_NO_GRAPH = 1
+FLAG_UNFUSED = 2
 
 STEPS = ("sky", "beam", "zform", "herk", "reduce", "other")
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
@@ -112,12 +113,13 @@ class Config:
     batch_time: int = 0
     batch_freq: int = 0
     use_graph: bool = True
+    unfused: bool = False  # FP32 / BF16X3: separate Z-formation step (Z in device memory)
 
     def _c(self) -> _Config:
         return _Config(self.n_ant, self.n_feed, self.n_ax, self.n_beam, self.max_src, self.max_time, self.max_freq,
                        self.latitude_rad, PRECISIONS[self.precision], BEAM_MODES[self.beam_mode], self.n_za,
                        self.n_az, self.dza_rad, self.daz_rad, self.src_chunk, self.batch_time, self.batch_freq,
-                       0 if self.use_graph else FLAG_NO_GRAPH)
+                       (0 if self.use_graph else FLAG_NO_GRAPH) | (FLAG_UNFUSED if self.unfused else 0))
 
 
 def _ptr(t) -> Optional[int]:

@@ -7,7 +7,8 @@ import numpy as np
 
 from oracle import metrics
 
-TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-3}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-3, "fp32-unfused": 1e-5, "bf16x3-unfused": 1e-3}
+ALL_PATHS = ["fp64", "fp32", "bf16x3", "fp32-unfused", "bf16x3-unfused"]
 
 
 def say(*a):
@@ -16,9 +17,15 @@ def say(*a):
 
 
 def gpu_simulate(wl, precision, **cfgkw):
-    """Run matvis_simulate on the GPU for every (t, f) of a workload; V as [inst][a][b][p][q] c128."""
+    """Run matvis_simulate on the GPU for every (t, f) of a workload; V as [inst][a][b][p][q] c128.
+
+    ``precision`` may carry a "-unfused" suffix: Z then goes through device
+    memory in its own step instead of being formed inside the product."""
     import torch
     from paper_2312_09763_amd import matvis as mv
+    if precision.endswith("-unfused"):
+        precision = precision[:-len("-unfused")]
+        cfgkw["unfused"] = True
     cfg = mv.config_for(wl, precision, **cfgkw)
     d = mv.device_inputs(wl, precision)
     with mv.Context(cfg) as ctx:
@@ -38,7 +45,7 @@ def oracle_vis(wl, instances=None, grid=None):
 
 def grid_as_used(wl, precision):
     """The beam grid values the device sees (complex64 unless FP64), upcast for the oracle."""
-    if precision == "fp64":
+    if precision.startswith("fp64"):
         return wl.beam
     return wl.beam.astype(np.complex64).astype(np.complex128)
 

@@ -13,7 +13,7 @@ import pytest
 from paper_2312_09763_amd import matvis as mv
 from paper_2312_09763_amd import synth
 
-from helpers import TOL, errors, gpu_simulate, grid_as_used, oracle_vis, say
+from helpers import ALL_PATHS, TOL, errors, gpu_simulate, grid_as_used, oracle_vis, say
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +35,7 @@ def wl2_ragged():
     return synth.workload(2, n_ant=75, n_src=2333, n_time=2, n_freq=3)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ALL_PATHS)
 def test_workload1_full(wl1, precision):
     say(f"workload1 {precision}")
     V = gpu_simulate(wl1, precision)
@@ -45,7 +45,7 @@ def test_workload1_full(wl1, precision):
     assert ef <= TOL[precision] and ec <= TOL[precision]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ALL_PATHS)
 def test_workload2_polarised(wl2_small, precision):
     say(f"workload2 small {precision}")
     V = gpu_simulate(wl2_small, precision)
@@ -55,7 +55,7 @@ def test_workload2_polarised(wl2_small, precision):
     assert ef <= TOL[precision] and ec <= TOL[precision]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ALL_PATHS)
 def test_ragged_rows_chunks_and_batches(wl2_ragged, precision):
     """N = 150, three source chunks (last one ragged), batches of 1 time x 2 channels."""
     say(f"ragged {precision}")
@@ -87,7 +87,7 @@ def test_scalar_beam_bicubic_and_per_antenna_beams(orc):
     assert ef <= 1e-10 and ec <= 1e-10
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ALL_PATHS)
 def test_zenith_source_gives_flux(precision):
     """A unit beam and one source at the zenith: V_ab = I for every pair (zero phase)."""
     import torch
@@ -99,7 +99,7 @@ def test_zenith_source_gives_flux(precision):
     wl.beam = np.ones_like(wl.beam)
     V = gpu_simulate(wl, precision)
     # one source: no averaging, so BF16X3 shows its per-element split error (~2^-16 per factor)
-    tol = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 1e-4}[precision]
+    tol = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 1e-4}[precision.split("-")[0]]
     np.testing.assert_allclose(V[0, :, :, 0, 0], 2.5, rtol=0, atol=2.5 * tol)
 
 
