@@ -120,7 +120,8 @@ struct HerkArgs {
 int herk_super_tile(int prec);
 int herk_occupancy(int prec);  // resident workgroups per CU
 // Item prefix over the batch (k_worklist), then the persistent product kernel.
-hipError_t launch_worklist(int prec, const HerkArgs &a, hipStream_t s);
+// unit != 0 counts k-splits only (the fused product multiplies by its item kinds).
+hipError_t launch_worklist(int prec, const HerkArgs &a, int unit, hipStream_t s);
 hipError_t launch_herk(int prec, const HerkArgs &a, hipStream_t s);
 
 // Product with Z formed in LDS (kernels_herk_fused.hip); FP32 and BF16X3 only.

@@ -384,11 +384,12 @@ int herk_occupancy(int prec) {
     return nb < 1 ? 1 : nb;
 }
 
-hipError_t launch_worklist(int prec, const HerkArgs &a, hipStream_t s) {
+hipError_t launch_worklist(int prec, const HerkArgs &a, int unit, hipStream_t s) {
     if (a.n_inst <= 0) return hipSuccess;
     const int st = herk_super_tile(prec);
     const int nb = a.n_rows_pad / st;
-    k_worklist<<<1, 1024, 0, s>>>(a.count, a.fixed_k, a.n_ax, a.nfb, a.n_inst, a.ksplit, nb * (nb + 1) / 2, a.work);
+    const int n_st = unit ? 1 : nb * (nb + 1) / 2;
+    k_worklist<<<1, 1024, 0, s>>>(a.count, a.fixed_k, a.n_ax, a.nfb, a.n_inst, a.ksplit, n_st, a.work);
     return hipGetLastError();
 }
 

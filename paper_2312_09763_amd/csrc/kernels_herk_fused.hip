@@ -33,18 +33,18 @@ constexpr int kST = 128, kWT = 64, kKC = 32, kTI = 4;
 
 __device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
-__device__ inline uint32_t bf16_rne(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
-}
-__device__ inline float bf16_to_f(uint32_t h) { return __uint_as_float(h << 16); }
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
-// packed (hi, lo) bf16 words of one complex64 value
+// packed (hi, lo) bf16 words of one complex64 value: hi = bf16(z), lo = bf16(z - hi),
+// both round-to-nearest-even (v_cvt_pk_bf16_f32 on gfx950)
 __device__ inline void split2(float re, float im, uint32_t &hi, uint32_t &lo) {
-    const uint32_t hr = bf16_rne(re), hm = bf16_rne(im);
-    hi = hr | (hm << 16);
-    lo = bf16_rne(re - bf16_to_f(hr)) | (bf16_rne(im - bf16_to_f(hm)) << 16);
+    const f32x2_t z = {re, im};
+    const bf16x2_t h = __builtin_convertvector(z, bf16x2_t);
+    const f32x2_t r = z - __builtin_convertvector(h, f32x2_t);
+    const bf16x2_t l = __builtin_convertvector(r, bf16x2_t);
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, l);
 }
 
 __device__ inline u32x4 bf16_rot(u32x4 v) {
@@ -69,7 +69,193 @@ struct AntEntry {
     int pad;
 };
 
-template <int PREC, int NF, int NX>
+// ---------------------------------------------------------------------------
+// Consumers.  An accumulator pair (re, im) per 16 x 16 output tile; one
+// k-stage (KC = 32 complex columns) is read from the LDS stage buffer, whose
+// rows 0..127 hold block I and rows 128..255 block J.
+//
+// BF16X3 tile update with row operand (Ah, Al, Wh, Wl) and column operand
+// (Bh, Bl): re += Ah Bh + Ah Bl + Al Bh, im += Wh Bh + Wh Bl + Wl Bh, and on
+// output-diagonal tiles also the lo lo products (a one-signed |lo|^2 bias
+// there; elsewhere it averages out and is omitted).
+// FP32 tile update with one complex element per lane (a, b):
+// re += a.re b.re + a.im b.im, im += a.im b.re - a.re b.im.
+// ---------------------------------------------------------------------------
+
+struct RowB3 {
+    bf16x8 h, l, wh, wl;
+};
+
+template <int PREC>
+__device__ __forceinline__ RowB3 load_row_b3(const unsigned char *buf, int row, int ks, int lk) {
+    typedef FL<PREC> L;
+    const unsigned char *p = buf + row * L::RS + ks * 64 + lk * 16;
+    const u32x4 h = *(const u32x4 *)p;
+    const u32x4 l = *(const u32x4 *)(p + L::PLANEB);
+    RowB3 r;
+    r.h = __builtin_bit_cast(bf16x8, h);
+    r.l = __builtin_bit_cast(bf16x8, l);
+    r.wh = __builtin_bit_cast(bf16x8, bf16_rot(h));
+    r.wl = __builtin_bit_cast(bf16x8, bf16_rot(l));
+    return r;
+}
+
+// Off-diagonal super-tile: wave tile of 4 x 4 tiles (rows arow.., columns brow..).
+template <int PREC>
+__device__ __forceinline__ void consume_full(const unsigned char *buf, int arow, int brow, int l16, int lk,
+                                             f32x4 (&re)[16], f32x4 (&im)[16]) {
+    typedef FL<PREC> L;
+    if constexpr (PREC == PB3) {
+#pragma unroll
+        for (int ks = 0; ks < kKC / 16; ks++) {
+            RowB3 A[kTI];
+#pragma unroll
+            for (int i = 0; i < kTI; i++) A[i] = load_row_b3<PREC>(buf, arow + 16 * i + l16, ks, lk);
+            const unsigned char *pc = buf + (brow + l16) * L::RS + ks * 64 + lk * 16;
+            u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
+#pragma unroll
+            for (int j = 0; j < kTI; j++) {
+                const bf16x8 Bh = __builtin_bit_cast(bf16x8, nh);
+                const bf16x8 Bl = __builtin_bit_cast(bf16x8, nl);
+                if (j + 1 < kTI) {
+                    const unsigned char *p = pc + 16 * (j + 1) * L::RS;
+                    nh = *(const u32x4 *)p;
+                    nl = *(const u32x4 *)(p + L::PLANEB);
+                }
+#pragma unroll
+                for (int i = 0; i < kTI; i++) {
+                    re[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i].h, Bh, re[i * kTI + j], 0, 0, 0);
+                    im[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i].wh, Bh, im[i * kTI + j], 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < kTI; i++) {
+                    re[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i].h, Bl, re[i * kTI + j], 0, 0, 0);
+                    im[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i].wh, Bl, im[i * kTI + j], 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < kTI; i++) {
+                    re[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i].l, Bh, re[i * kTI + j], 0, 0, 0);
+                    im[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i].wl, Bh, im[i * kTI + j], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < kKC; kk += 4) {
+            float2 av[kTI], bv[kTI];
+#pragma unroll
+            for (int i = 0; i < kTI; i++) av[i] = *(const float2 *)(buf + (arow + 16 * i + l16) * L::RS + (kk + lk) * 8);
+#pragma unroll
+            for (int j = 0; j < kTI; j++) bv[j] = *(const float2 *)(buf + (brow + 16 * j + l16) * L::RS + (kk + lk) * 8);
+#pragma unroll
+            for (int i = 0; i < kTI; i++) {
+                const float nre = -av[i].x;
+#pragma unroll
+                for (int j = 0; j < kTI; j++) {
+                    re[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, re[i * kTI + j], 0, 0, 0);
+                    im[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].x, im[i * kTI + j], 0, 0, 0);
+                }
+#pragma unroll
+                for (int j = 0; j < kTI; j++) {
+                    re[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, re[i * kTI + j], 0, 0, 0);
+                    im[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nre, bv[j].y, im[i * kTI + j], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
+// Diagonal super-tile: its lower triangle has 36 tiles; wave W takes the
+// 16-row blocks W and 7 - W, i.e. tiles (7 - W, 0..7 - W) in slots
+// 0..7 - W and (W, 0..W) in slots 8 - W.., nine tiles for every wave.
+template <int PREC, int W>
+__device__ __forceinline__ void consume_tri(const unsigned char *buf, int l16, int lk, f32x4 (&re)[16],
+                                            f32x4 (&im)[16]) {
+    typedef FL<PREC> L;
+    constexpr int R1 = 7 - W, R0 = W, NCOL = 8 - W;
+    if constexpr (PREC == PB3) {
+#pragma unroll
+        for (int ks = 0; ks < kKC / 16; ks++) {
+            const RowB3 a1 = load_row_b3<PREC>(buf, 16 * R1 + l16, ks, lk);
+            const RowB3 a0 = load_row_b3<PREC>(buf, 16 * R0 + l16, ks, lk);
+            // column fragments are prefetched one tile ahead; the scheduling fences
+            // keep the compiler from hoisting every column's loads (register pressure)
+            const unsigned char *pc = buf + l16 * L::RS + ks * 64 + lk * 16;
+            u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
+#pragma unroll
+            for (int c = 0; c < NCOL; c++) {
+                const bf16x8 Bh = __builtin_bit_cast(bf16x8, nh);
+                const bf16x8 Bl = __builtin_bit_cast(bf16x8, nl);
+                if (c + 1 < NCOL) {
+                    const unsigned char *p = pc + 16 * (c + 1) * L::RS;
+                    nh = *(const u32x4 *)p;
+                    nl = *(const u32x4 *)(p + L::PLANEB);
+                }
+                const int s1 = c, s0 = NCOL + c;
+                const bool two = c <= R0;
+                re[s1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.h, Bh, re[s1], 0, 0, 0);
+                im[s1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.wh, Bh, im[s1], 0, 0, 0);
+                if (two) {
+                    re[s0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.h, Bh, re[s0], 0, 0, 0);
+                    im[s0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.wh, Bh, im[s0], 0, 0, 0);
+                }
+                re[s1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.h, Bl, re[s1], 0, 0, 0);
+                im[s1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.wh, Bl, im[s1], 0, 0, 0);
+                if (two) {
+                    re[s0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.h, Bl, re[s0], 0, 0, 0);
+                    im[s0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.wh, Bl, im[s0], 0, 0, 0);
+                }
+                re[s1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.l, Bh, re[s1], 0, 0, 0);
+                im[s1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.wl, Bh, im[s1], 0, 0, 0);
+                if (two) {
+                    re[s0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.l, Bh, re[s0], 0, 0, 0);
+                    im[s0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.wl, Bh, im[s0], 0, 0, 0);
+                }
+                if (c == R1) {
+                    re[s1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.l, Bl, re[s1], 0, 0, 0);
+                    im[s1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.wl, Bl, im[s1], 0, 0, 0);
+                }
+                if (c == R0) {
+                    re[s0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.l, Bl, re[s0], 0, 0, 0);
+                    im[s0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.wl, Bl, im[s0], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < kKC; kk += 4) {
+            const float2 a1 = *(const float2 *)(buf + (16 * R1 + l16) * L::RS + (kk + lk) * 8);
+            const float2 a0 = *(const float2 *)(buf + (16 * R0 + l16) * L::RS + (kk + lk) * 8);
+            const float n1 = -a1.x, n0 = -a0.x;
+#pragma unroll
+            for (int c = 0; c < NCOL; c++) {
+                const float2 b = *(const float2 *)(buf + (16 * c + l16) * L::RS + (kk + lk) * 8);
+                const int s1 = c, s0 = NCOL + c;
+                re[s1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, b.x, re[s1], 0, 0, 0);
+                im[s1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, b.x, im[s1], 0, 0, 0);
+                if (c <= R0) {
+                    re[s0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, b.x, re[s0], 0, 0, 0);
+                    im[s0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, b.x, im[s0], 0, 0, 0);
+                }
+                re[s1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, b.y, re[s1], 0, 0, 0);
+                im[s1] = __builtin_amdgcn_mfma_f32_16x16x4f32(n1, b.y, im[s1], 0, 0, 0);
+                if (c <= R0) {
+                    re[s0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, b.y, re[s0], 0, 0, 0);
+                    im[s0] = __builtin_amdgcn_mfma_f32_16x16x4f32(n0, b.y, im[s0], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
+// One launch per item kind: DIAG = the nb diagonal super-tiles (I, I) of each
+// (instance, k-split), consumed with the triangular wave mapping; otherwise the
+// nb (nb - 1) / 2 off-diagonal ones (I > J), consumed as 2 x 2 wave tiles.
+// a.work is the per-instance prefix of k-splits; instance i owns items
+// [work[i] n_kind, work[i + 1] n_kind).
+template <int PREC, int NF, int NX, bool DIAG>
 __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
     typedef FL<PREC> L;
     constexpr int RS = L::RS;
@@ -88,34 +274,39 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
     const int l16 = lane & 15, lk = lane >> 4;
     const int Np = a.n_rows_pad;
     const int nb = Np / kST;
-    const int n_st = nb * (nb + 1) / 2;
-    const int total = a.work[a.n_inst];
+    const int n_kind = DIAG ? nb : nb * (nb - 1) / 2;
+    const int total = a.work[a.n_inst] * n_kind;
     const int per_xcd = a.grid / 8;
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     // producer thread roles
     const int pt = tid - 256;
     const int msl = pt % SPS, g = pt / SPS;
+    constexpr bool diag = DIAG;
 
     for (int item = slot_x; item < total; item += a.grid) {
         int lo = 0, hi = a.n_inst - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (a.work[mid] <= item)
+            if (a.work[mid] * n_kind <= item)
                 lo = mid;
             else
                 hi = mid - 1;
         }
         const int inst = lo;
-        const int local = item - a.work[inst];
-        const int s = local / n_st;
-        int st = local % n_st;
-        int I = 0;
-        while (st > I) {
-            st -= I + 1;
-            I++;
+        const int local = item - a.work[inst] * n_kind;
+        const int s = local / n_kind;
+        int st = local % n_kind;
+        int I, J;
+        if (DIAG) {
+            I = J = st;
+        } else {  // st enumerates the pairs (1, 0), (2, 0), (2, 1), (3, 0), ...
+            I = 1;
+            while (st >= I) {
+                st -= I;
+                I++;
+            }
+            J = st;
         }
-        const int J = st;
-        const bool diag = I == J;
         const int tslot = inst / a.nfb;
         const int f = a.f0 + inst % a.nfb;
         const int64_t M = a.count[tslot];
@@ -155,6 +346,8 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
         auto fetch = [&](int stage) {
             m_cur = m_begin + (int64_t)stage * SPS + msl;
             live = stage < n_stage && m_cur < m_end;
+            sx = sy = sz = 0.0;
+            for (int c = 0; c < NC; c++) w[c] = make_float2(0.f, 0.f);
             if (live) {
                 sx = sh[m_cur];
                 sy = sh[a.ld_src + m_cur];
@@ -164,31 +357,34 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
             }
         };
 
-        // ---- producer: form the Z rows of blocks I (and J) for one stage
+        // ---- producer: form the Z rows of blocks I (and J) for one stage.
+        // The fringe factor uses the hardware sine / cosine, whose argument is in
+        // revolutions, on the FP64-reduced phase r in [-1/2, 1/2]:
+        // F = exp(-2 pi i r) = cos(-r rev) + i sin(-r rev).  Rows past n_ant and
+        // sources past the split are written as zeros (mask factor 0).
         auto produce = [&](unsigned char *buf) {
             const bool lv = live;
             const double x0 = sx, x1 = sy, x2 = sz;
             const int64_t m = m_cur;
             float2 wl[NC];
             for (int c = 0; c < NC; c++) wl[c] = w[c];
-            int cur_b = a.n_beam == 1 ? 0 : -1;
+            const bool multi_beam = a.n_beam != 1;
+            int cur_b = multi_beam ? -1 : 0;
             for (int as = g; as < na_tot; as += NG) {
                 const AntEntry e = tab[as];
+                if (multi_beam && lv && e.b >= 0 && e.b != cur_b) {
+                    for (int c = 0; c < NC; c++) wl[c] = Bm[((int64_t)e.b * NC + c) * a.ld_src + m];
+                    cur_b = e.b;
+                }
+                const double p = e.ux * x0 + e.uy * x1 + e.uz * x2;
+                const float r = (float)(p - rint(p));
+                const float msk = (lv && e.b >= 0) ? 1.0f : 0.0f;
+                const float sn = msk * __builtin_amdgcn_sinf(-r);
+                const float cs = msk * __builtin_amdgcn_cosf(-r);
                 float2 z[NC];
-                for (int c = 0; c < NC; c++) z[c] = make_float2(0.f, 0.f);
-                if (lv && e.b >= 0) {
-                    if (e.b != cur_b) {
-                        for (int c = 0; c < NC; c++) wl[c] = Bm[((int64_t)e.b * NC + c) * a.ld_src + m];
-                        cur_b = e.b;
-                    }
-                    const double p = e.ux * x0 + e.uy * x1 + e.uz * x2;
-                    const double r = p - rint(p);
-                    float sn, cs;
-                    sincospif(-2.0f * (float)r, &sn, &cs);
-                    for (int c = 0; c < NC; c++) {
-                        z[c].x = wl[c].x * cs - wl[c].y * sn;
-                        z[c].y = wl[c].x * sn + wl[c].y * cs;
-                    }
+                for (int c = 0; c < NC; c++) {
+                    z[c].x = wl[c].x * cs - wl[c].y * sn;
+                    z[c].y = wl[c].x * sn + wl[c].y * cs;
                 }
 #pragma unroll
                 for (int p = 0; p < NF; p++) {
@@ -216,92 +412,24 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
             }
         };
 
-        typedef f32x4 Acc;
-        Acc acc_re[kTI][kTI], acc_im[kTI][kTI];
-        for (int i = 0; i < kTI; i++)
-            for (int j = 0; j < kTI; j++)
-                for (int e = 0; e < 4; e++) {
-                    acc_re[i][j][e] = 0.f;
-                    acc_im[i][j][e] = 0.f;
-                }
-        const bool active = consumer && !(diag && wc > wr);
-        const bool on_diag = diag && wc == wr;
+        f32x4 acc_re[16], acc_im[16];
+        for (int t = 0; t < 16; t++)
+            for (int e = 0; e < 4; e++) {
+                acc_re[t][e] = 0.f;
+                acc_im[t][e] = 0.f;
+            }
         const int arow = wr * kWT;
-        const int brow = (diag ? 0 : kST) + wc * kWT;
+        const int brow = kST + wc * kWT;
 
         auto consume = [&](const unsigned char *buf) {
-            if constexpr (PREC == PB3) {
-#pragma unroll
-                for (int ks = 0; ks < kKC / 16; ks++) {
-                    u32x4 ah[kTI], al[kTI], bh[kTI], bl[kTI];
-#pragma unroll
-                    for (int i = 0; i < kTI; i++) {
-                        const unsigned char *p = buf + (arow + 16 * i + l16) * RS + ks * 64 + lk * 16;
-                        ah[i] = *(const u32x4 *)p;
-                        al[i] = *(const u32x4 *)(p + L::PLANEB);
-                    }
-#pragma unroll
-                    for (int j = 0; j < kTI; j++) {
-                        const unsigned char *p = buf + (brow + 16 * j + l16) * RS + ks * 64 + lk * 16;
-                        bh[j] = *(const u32x4 *)p;
-                        bl[j] = *(const u32x4 *)(p + L::PLANEB);
-                    }
-                    // per row tile: three passes over the column tiles, so updates of one
-                    // accumulator are eight MFMAs apart
-#pragma unroll
-                    for (int i = 0; i < kTI; i++) {
-                        const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah[i]);
-                        const bf16x8 Al = __builtin_bit_cast(bf16x8, al[i]);
-                        const bf16x8 Wh = __builtin_bit_cast(bf16x8, bf16_rot(ah[i]));
-                        const bf16x8 Wl = __builtin_bit_cast(bf16x8, bf16_rot(al[i]));
-#pragma unroll
-                        for (int j = 0; j < kTI; j++) {
-                            const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[j]);
-                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh, acc_re[i][j], 0, 0, 0);
-                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wh, Bh, acc_im[i][j], 0, 0, 0);
-                        }
-#pragma unroll
-                        for (int j = 0; j < kTI; j++) {
-                            const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl[j]);
-                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl, acc_re[i][j], 0, 0, 0);
-                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wh, Bl, acc_im[i][j], 0, 0, 0);
-                        }
-#pragma unroll
-                        for (int j = 0; j < kTI; j++) {
-                            const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[j]);
-                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, acc_re[i][j], 0, 0, 0);
-                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wl, Bh, acc_im[i][j], 0, 0, 0);
-                        }
-                        // lo lo^H only where it is a one-signed bias: the output diagonal
-                        if (on_diag) {
-                            const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl[i]);
-                            acc_re[i][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bl, acc_re[i][i], 0, 0, 0);
-                            acc_im[i][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wl, Bl, acc_im[i][i], 0, 0, 0);
-                        }
-                    }
-                }
+            if constexpr (!DIAG) {
+                consume_full<PREC>(buf, arow, brow, l16, lk, acc_re, acc_im);
             } else {
-#pragma unroll
-                for (int kk = 0; kk < kKC; kk += 4) {
-                    float2 av[kTI], bv[kTI];
-#pragma unroll
-                    for (int i = 0; i < kTI; i++) av[i] = *(const float2 *)(buf + (arow + 16 * i + l16) * RS + (kk + lk) * 8);
-#pragma unroll
-                    for (int j = 0; j < kTI; j++) bv[j] = *(const float2 *)(buf + (brow + 16 * j + l16) * RS + (kk + lk) * 8);
-#pragma unroll
-                    for (int i = 0; i < kTI; i++) {
-                        const float nre = -av[i].x;
-#pragma unroll
-                        for (int j = 0; j < kTI; j++) {
-                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, acc_re[i][j], 0, 0, 0);
-                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].x, acc_im[i][j], 0, 0, 0);
-                        }
-#pragma unroll
-                        for (int j = 0; j < kTI; j++) {
-                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, acc_re[i][j], 0, 0, 0);
-                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nre, bv[j].y, acc_im[i][j], 0, 0, 0);
-                        }
-                    }
+                switch (wave) {
+                    case 0: consume_tri<PREC, 0>(buf, l16, lk, acc_re, acc_im); break;
+                    case 1: consume_tri<PREC, 1>(buf, l16, lk, acc_re, acc_im); break;
+                    case 2: consume_tri<PREC, 2>(buf, l16, lk, acc_re, acc_im); break;
+                    default: consume_tri<PREC, 3>(buf, l16, lk, acc_re, acc_im); break;
                 }
             }
         };
@@ -317,7 +445,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
             unsigned char *cur = lds + (stg & 1) * L::BUF;
             unsigned char *nxt = lds + ((stg + 1) & 1) * L::BUF;
             if (consumer) {
-                if (active) consume(cur);
+                consume(cur);
             } else if (stg + 1 < n_stage) {
                 produce(nxt);
                 fetch(stg + 2);
@@ -325,32 +453,55 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
             __syncthreads();
         }
 
-        if (active) {
+        if (consumer) {
             float2 *P = (float2 *)a.part + ((int64_t)inst * a.max_splits + s) * (int64_t)Np * Np;
-            const int rb = I * kST + wr * kWT + 4 * lk;
-            const int c0 = J * kST + wc * kWT + l16;
+            if constexpr (!DIAG) {
+                const int rb = I * kST + wr * kWT + 4 * lk;
+                const int c0 = J * kST + wc * kWT + l16;
 #pragma unroll
-            for (int i = 0; i < kTI; i++)
+                for (int i = 0; i < kTI; i++)
 #pragma unroll
-                for (int j = 0; j < kTI; j++)
+                    for (int j = 0; j < kTI; j++)
+#pragma unroll
+                        for (int e = 0; e < 4; e++)
+                            P[(int64_t)(rb + 16 * i + e) * Np + c0 + 16 * j] =
+                                make_float2(acc_re[i * kTI + j][e], acc_im[i * kTI + j][e]);
+            } else {
+                // slot t of wave w: tile (7 - w, t) for t < 8 - w, else tile (w, t - (8 - w))
+                const int ncol = 8 - wave;
+#pragma unroll
+                for (int t = 0; t < 9; t++) {
+                    const int R = t < ncol ? 7 - wave : wave;
+                    const int C = t < ncol ? t : t - ncol;
+                    const int r0 = I * kST + 16 * R + 4 * lk;
+                    const int c0 = I * kST + 16 * C + l16;
 #pragma unroll
                     for (int e = 0; e < 4; e++)
-                        P[(int64_t)(rb + 16 * i + e) * Np + c0 + 16 * j] = make_float2(acc_re[i][j][e], acc_im[i][j][e]);
+                        P[(int64_t)(r0 + e) * Np + c0] = make_float2(acc_re[t][e], acc_im[t][e]);
+                }
+            }
         }
     }
 }
 
+template <int PREC, bool DIAG>
+hipError_t launch_kind(const FusedArgs &a, hipStream_t s) {
+    if (a.n_feed == 2 && a.n_ax == 2)
+        k_herk_fused<PREC, 2, 2, DIAG><<<a.grid, 512, 0, s>>>(a);
+    else if (a.n_feed == 2)
+        k_herk_fused<PREC, 2, 1, DIAG><<<a.grid, 512, 0, s>>>(a);
+    else if (a.n_ax == 2)
+        k_herk_fused<PREC, 1, 2, DIAG><<<a.grid, 512, 0, s>>>(a);
+    else
+        k_herk_fused<PREC, 1, 1, DIAG><<<a.grid, 512, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 template <int PREC>
 hipError_t launch_prec(const FusedArgs &a, hipStream_t s) {
-    if (a.n_feed == 2 && a.n_ax == 2)
-        k_herk_fused<PREC, 2, 2><<<a.grid, 512, 0, s>>>(a);
-    else if (a.n_feed == 2)
-        k_herk_fused<PREC, 2, 1><<<a.grid, 512, 0, s>>>(a);
-    else if (a.n_ax == 2)
-        k_herk_fused<PREC, 1, 2><<<a.grid, 512, 0, s>>>(a);
-    else
-        k_herk_fused<PREC, 1, 1><<<a.grid, 512, 0, s>>>(a);
-    return hipGetLastError();
+    hipError_t e = launch_kind<PREC, true>(a, s);
+    if (e != hipSuccess || a.n_rows_pad <= kST) return e;  // a single row block has no off-diagonal tiles
+    return launch_kind<PREC, false>(a, s);
 }
 
 }  // namespace
@@ -364,8 +515,8 @@ hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s) {
 
 int herk_fused_occupancy(int prec) {
     int nb = 1;
-    hipError_t e = prec == P32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_herk_fused<P32, 2, 2>, 512, 0)
-                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_herk_fused<PB3, 2, 2>, 512, 0);
+    hipError_t e = prec == P32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_herk_fused<P32, 2, 2, false>, 512, 0)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_herk_fused<PB3, 2, 2, false>, 512, 0);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 1;

@@ -372,7 +372,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 ha.part = c->part;
                 ha.work = c->work;
                 ha.grid = c->herk_grid;
-                STEP(c, MATVIS_STEP_OTHER, s, launch_worklist(prec, ha, s));
+                STEP(c, MATVIS_STEP_OTHER, s, launch_worklist(prec, ha, c->fused ? 1 : 0, s));
 
                 if (c->fused) {
                     FusedArgs fa{};
@@ -633,7 +633,7 @@ matvis_status matvis_step_herk(matvis_ctx *c, const void *Zin, int32_t n_row, in
     ha.part = c->part;
     ha.work = c->work;
     ha.grid = c->herk_grid;
-    HIPCHK(c, launch_worklist(prec, ha, s));
+    HIPCHK(c, launch_worklist(prec, ha, 0, s));
     HIPCHK(c, launch_herk(prec, ha, s));
     ReduceArgs ra{};
     ra.part = c->part;
