@@ -87,6 +87,10 @@ typedef struct {
     int32_t batch_time;   /* times per device batch; 0 = automatic */
     int32_t batch_freq;   /* frequencies per device batch; 0 = automatic */
     int32_t flags;        /* MATVIS_FLAG_* bits */
+    int64_t ksplit;       /* Z columns summed by one product work item before its partial
+                             is stored (a multiple of 64); 0 = automatic.  FP32
+                             accumulators see ksplit / 2 sequential updates, so this
+                             bounds their rounding; the partials are summed in FP64. */
 } matvis_config;
 
 #define MATVIS_FLAG_NO_GRAPH 1 /* launch kernels directly instead of replaying a captured hipGraph */
@@ -136,6 +140,89 @@ const char *matvis_status_string(int32_t status);
 
 /* Release the context and all its device memory (after synchronising). */
 void matvis_destroy(matvis_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Learned beam: a Fourier-feature MLP standing in for Alg. 2 step (ii).
+ *
+ * The network maps normalised inputs x = (u, v, w) = (az / 2 pi,
+ * za / (pi / 2), (nu - nu_min) / (nu_max - nu_min)) to the 2 x 2 complex
+ * Jones matrix J[p][k] (8 reals: re, im of (0,0), (0,1), (1,0), (1,1)):
+ *   phi = (sin 2 pi Bff x, cos 2 pi Bff x)      Bff [128][3], integer az
+ *                                               column (features periodic in az)
+ *   h1 = SiLU(W1 phi + b1), h2..h4 = SiLU(W h + b) (width 128), out = W5 h4 + b5.
+ * Parameters are one FP32 device vector of MATVIS_MLP_N_PARAMS floats in the
+ * order Bff, W1, b1, W2, b2, W3, b3, W4, b4, W5, b5 (row-major weights
+ * [out][in]).  The four hidden-layer products round both operands to bf16
+ * and accumulate in FP32; features, biases, SiLU and the head (W5, b5) are
+ * FP32.  The Fourier matrix is fixed (its gradient is zero and Adam leaves
+ * it).
+ * All arrays are device arrays; scalars and loss histories are host values.
+ * ------------------------------------------------------------------------- */
+#define MATVIS_MLP_N_PARAMS 83848
+
+/* out [n][8] = network(x [n][3]).  Allocates a bf16 copy of the weights. */
+matvis_status matvis_mlp_forward(const float *params, const float *x, int64_t n, float *out, void *stream);
+
+/* Mean squared error L = sum (out - y)^2 / (8 n) and its gradient with respect
+ * to every parameter (grad [MATVIS_MLP_N_PARAMS], loss [1], device).
+ * fp32_math != 0 keeps the products in FP32 (a check mode).  Allocates
+ * activation workspace for n rows. */
+matvis_status matvis_mlp_loss_grad(const float *params, const float *x, const float *y, int64_t n, int32_t fp32_math,
+                                   float *grad, float *loss, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on
+ * params with first / second moment vectors m1, m2 of the same length. */
+matvis_status matvis_mlp_adam(float *params, const float *grad, float *m1, float *m2, int64_t step, float lr,
+                              void *stream);
+
+/* Training pairs from the method's own interpolant (Sec. 3.4): out [n][8] =
+ * beam of channel chan[i] at (za[i], az[i]) from a complex64 grid
+ * [n_chan][n_feed][n_ax][n_za][n_az] (geometry as in matvis_config),
+ * bilinear (bicubic = 0) or Keys bicubic (bicubic = 1); components beyond
+ * n_feed x n_ax are 0.  If x is not NULL it receives the network inputs
+ * x [n][3] = (az / 2 pi, za / (pi / 2), (chan_freq_hz[chan] - nu_min_hz) /
+ * (nu_max_hz - nu_min_hz)), formed as matvis_simulate forms them.  chan is
+ * checked on the host (MATVIS_EINVAL if outside [0, n_chan)); asynchronous
+ * after that check. */
+matvis_status matvis_beam_samples(const void *grid, int32_t n_chan, int32_t n_feed, int32_t n_ax, int32_t n_za,
+                                  int32_t n_az, double dza_rad, double daz_rad, int32_t bicubic, const double *za,
+                                  const double *az, const int32_t *chan, int64_t n, float *out,
+                                  const double *chan_freq_hz, double nu_min_hz, double nu_max_hz, float *x,
+                                  void *stream);
+
+/* Train params in place on samples (x [n][3], y [n][8]) with Adam, mini-batches
+ * of `batch` rows in an order reshuffled every epoch (seeded), learning rate
+ * decaying geometrically from lr0 to lr1 over the epochs.  loss_history (host,
+ * may be NULL) receives the mean batch loss of each epoch.  Synchronous;
+ * allocates its workspace. */
+matvis_status matvis_train_surrogate(float *params, const float *x, const float *y, int64_t n, int32_t batch,
+                                     int32_t epochs, float lr0, float lr1, uint64_t seed, int32_t fp32_math,
+                                     float *loss_history, void *stream);
+
+/* Give a context created with beam_mode MATVIS_BEAM_SURROGATE its network
+ * (copied) and the frequency range that normalises w.  The context must have
+ * n_beam = 1 and FP32 or BF16X3 precision; beam_grid is then ignored by
+ * matvis_simulate (NULL is accepted). */
+matvis_status matvis_set_surrogate(matvis_ctx *ctx, const float *params, double nu_min_hz, double nu_max_hz);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner for the batched product (work-item k-split, times per batch, Z
+ * formed inside the product or not).  It times matvis_simulate on the
+ * caller's own inputs for each candidate that fits in device memory and
+ * returns in *best a copy of *base with the fastest ksplit, batch_time and
+ * MATVIS_FLAG_UNFUSED choice, and the time of one call in *best_ms (host
+ * pointers).  Candidate k-splits are limited per precision so that FP32
+ * accumulation stays well inside the precision's tolerance (FP32 <= 2048,
+ * BF16X3 <= 8192 columns).  If cache_path is not NULL, results are read from
+ * and written to that JSON file, keyed by GPU architecture, rows, axes,
+ * sources, times, channels, precision and beam mode; a cached entry is
+ * returned without timing.  vis is overwritten.  Synchronous.
+ * ------------------------------------------------------------------------- */
+matvis_status matvis_autotune(const matvis_config *base, const double *antpos, const int32_t *beam_idx,
+                              const double *freqs, int32_t n_freq, const double *lsts, int32_t n_time,
+                              const double *src_radec, int64_t n_src, const double *src_flux,
+                              const void *beam_grid, void *vis, void *stream, const char *cache_path,
+                              matvis_config *best, double *best_ms);
 
 /* ---------------------------------------------------------------------------
  * Per-step timing (the paper times each step of Alg. 2 separately, Sec. 6.1).

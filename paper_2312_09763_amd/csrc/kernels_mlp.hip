@@ -1,0 +1,542 @@
+// Kernels of the learned beam (layout and network in mlp.h).
+//
+// Training runs on small row-major FP32 tensors: Fourier features, a strided
+// MFMA GEMM with bias / SiLU epilogues (forward, and both backward products
+// through stride choices), SiLU backward, the squared-error gradient, column
+// sums for bias gradients, and Adam.  Products round their operands to bf16
+// and accumulate in FP32 (v_mfma_f32_16x16x32_bf16), or stay in FP32
+// (v_mfma_f32_16x16x4f32) in the FP32 check mode.
+//
+// Inference (k_mlp_infer) evaluates the whole network for 64 points per
+// workgroup with the activations kept in LDS (bf16) and the bf16 weights read
+// through L2, so only the inputs and the 8 outputs touch HBM.  In the
+// simulator it replaces beam interpolation: it reads the visible sources'
+// (za, az) and writes B = sqrt(I) J in the layout of the beam step.
+#include <algorithm>
+
+#include "beam_interp.h"
+#include "mlp.h"
+
+namespace mv {
+
+namespace {
+
+__device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+
+// sin / cos of 2 pi r with the hardware units (argument in revolutions) after reduction
+__device__ inline void sincos_rev(float r, float &s, float &c) {
+    r -= rintf(r);
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
+}
+
+// ---------------------------------------------------------------- features
+__global__ void k_features(const float *__restrict__ x, int64_t n, const float *__restrict__ P,
+                           float *__restrict__ phi) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * kFreq) return;
+    const int64_t m = idx / kFreq;
+    const int j = (int)(idx % kFreq);
+    const float *b = P + kOffBff + 3 * j;
+    const float arg = b[0] * x[3 * m] + b[1] * x[3 * m + 1] + b[2] * x[3 * m + 2];
+    float s, c;
+    sincos_rev(arg, s, c);
+    phi[m * kFeat + j] = s;
+    phi[m * kFeat + kFreq + j] = c;
+}
+
+// ---------------------------------------------------------------- GEMM
+// C(m, n) = sum_k A(m, k) B(n, k) (+ bias[n]); A(m, k) = A[m sam + k sak],
+// B(n, k) = B[n sbn + k sbk].  Z (if set) receives the pre-activation, H (if
+// set) the activation (SiLU when act, else the same value).  64 x 64 output
+// tile per 256-thread workgroup, 32-deep k steps through LDS; the staging
+// loop walks whichever index has unit stride, so transposed operands are
+// read coalesced.  Split-k: blockIdx.z takes k in [z kchunk, (z + 1) kchunk)
+// and, when partial is set, stores its raw sum to partial[z][M][N] (summed in
+// z order by k_sum_partials, so results do not depend on scheduling).
+struct GemmArgs {
+    const float *A;
+    int64_t sam, sak;
+    const float *B;
+    int64_t sbn, sbk;
+    int M, N, K;
+    const float *bias;
+    float *Z;
+    float *H;
+    int act;
+    int kchunk;
+    float *partial;
+};
+
+template <bool BF16>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+    constexpr int T = 64, KS = 32;
+    constexpr int RSB = KS + 8;  // bf16 row stride (elements): 80 B, keeps 16-byte lane reads aligned
+    constexpr int RSF = KS + 1;  // float row stride
+    __shared__ __attribute__((aligned(16))) unsigned char smem[2 * T * (BF16 ? RSB * 2 : RSF * 4)];
+    __bf16 *Ab = (__bf16 *)smem, *Bb = Ab + T * RSB;
+    float *Af = (float *)smem, *Bf = Af + T * RSF;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int l16 = lane & 15, lk = lane >> 4;
+    const int m0 = blockIdx.y * T, n0 = blockIdx.x * T;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int kbeg = blockIdx.z * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
+    const bool a_kfast = g.sak == 1, b_kfast = g.sbk == 1;
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kbeg; k0 < kend; k0 += KS) {
+        for (int e = tid; e < T * KS; e += 256) {
+            const int ra = a_kfast ? e / KS : e % T, ka = a_kfast ? e % KS : e / T;
+            const int rb = b_kfast ? e / KS : e % T, kb = b_kfast ? e % KS : e / T;
+            const int gm = m0 + ra, gka = k0 + ka, gn = n0 + rb, gkb = k0 + kb;
+            const float va = (gm < g.M && gka < kend) ? g.A[gm * g.sam + gka * g.sak] : 0.f;
+            const float vb = (gn < g.N && gkb < kend) ? g.B[gn * g.sbn + gkb * g.sbk] : 0.f;
+            if (BF16) {
+                Ab[ra * RSB + ka] = (__bf16)va;
+                Bb[rb * RSB + kb] = (__bf16)vb;
+            } else {
+                Af[ra * RSF + ka] = va;
+                Bf[rb * RSF + kb] = vb;
+            }
+        }
+        __syncthreads();
+        if (BF16) {
+            bf16x8 a[2], b[2];
+            for (int i = 0; i < 2; i++) a[i] = *(const bf16x8 *)(Ab + (wr + 16 * i + l16) * RSB + lk * 8);
+            for (int j = 0; j < 2; j++) b[j] = *(const bf16x8 *)(Bb + (wc + 16 * j + l16) * RSB + lk * 8);
+            for (int i = 0; i < 2; i++)
+                for (int j = 0; j < 2; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        } else {
+            for (int kk = 0; kk < KS; kk += 4) {
+                float a[2], b[2];
+                for (int i = 0; i < 2; i++) a[i] = Af[(wr + 16 * i + l16) * RSF + kk + lk];
+                for (int j = 0; j < 2; j++) b[j] = Bf[(wc + 16 * j + l16) * RSF + kk + lk];
+                for (int i = 0; i < 2; i++)
+                    for (int j = 0; j < 2; j++)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++)
+            for (int e = 0; e < 4; e++) {
+                const int m = m0 + wr + 16 * i + 4 * lk + e, n = n0 + wc + 16 * j + l16;
+                if (m >= g.M || n >= g.N) continue;
+                if (g.partial) {
+                    g.partial[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][e];
+                    continue;
+                }
+                float v = acc[i][j][e] + (g.bias ? g.bias[n] : 0.f);
+                if (g.Z) g.Z[(int64_t)m * g.N + n] = v;
+                if (g.H) g.H[(int64_t)m * g.N + n] = g.act ? silu(v) : v;
+            }
+}
+
+// ---------------------------------------------------------------- backward helpers
+// dZ = dH * d SiLU/dz = dH * s (1 + z (1 - s)),  s = 1 / (1 + exp(-z))
+__global__ void k_silu_bwd(const float *__restrict__ dH, const float *__restrict__ Z, float *__restrict__ dZ,
+                           int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float z = Z[i];
+    const float s = 1.0f / (1.0f + __expf(-z));
+    dZ[i] = dH[i] * s * (1.0f + z * (1.0f - s));
+}
+
+// Mean squared error over n x 8 outputs: dOut = 2 (out - y) / (8 n); per-block partial sums of squares.
+__global__ void __launch_bounds__(256) k_loss_grad(const float *__restrict__ out, const float *__restrict__ y,
+                                                   int64_t n, float *__restrict__ dout, float *__restrict__ part) {
+    __shared__ float red[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float sq = 0.f;
+    if (i < n * kOut) {
+        const float d = out[i] - y[i];
+        dout[i] = 2.0f * d / (float)(kOut * n);
+        sq = d * d;
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Sequential sums (fixed order): out[0] = sum(part) / (8 n)
+__global__ void k_finish_loss(const float *__restrict__ part, int nb, int64_t n, float *__restrict__ loss) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; b++) s += part[b];
+    loss[0] = (float)(s / (double)(kOut * n));
+}
+
+// out[i] = sum_z part[z][i], z in order.
+__global__ void k_sum_partials(const float *__restrict__ part, int nz, int64_t n, float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < nz; z++) s += part[z * n + i];
+    out[i] = s;
+}
+
+// Column sums of dZ [M][N] over row chunks of kColRows: part[chunk][c]; 64
+// columns x 4 row lanes per workgroup, lanes combined in a fixed order.
+constexpr int kColRows = 256;
+__global__ void __launch_bounds__(256) k_colsum_part(const float *__restrict__ dZ, int64_t M, int N,
+                                                     float *__restrict__ part) {
+    __shared__ float red[4][64];
+    const int cl = threadIdx.x % 64, rl = threadIdx.x / 64;
+    const int c = blockIdx.x * 64 + cl;
+    const int64_t r0 = (int64_t)blockIdx.y * kColRows, r1 = min<int64_t>(M, r0 + kColRows);
+    float s = 0.f;
+    if (c < N)
+        for (int64_t m = r0 + rl; m < r1; m += 4) s += dZ[m * N + c];
+    red[rl][cl] = s;
+    __syncthreads();
+    if (rl == 0 && c < N) part[(int64_t)blockIdx.y * N + c] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+}
+
+// Adam (Kingma & Ba 2015) on the trainable parameters (the Fourier matrix is fixed).
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m1,
+                       float *__restrict__ m2, int64_t n, int64_t step, float lr, float b1, float b2, float eps) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || i < kOffW1) return;
+    const float gi = g[i];
+    const float a = b1 * m1[i] + (1.0f - b1) * gi;
+    const float b = b2 * m2[i] + (1.0f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = b;
+    const float ah = a / (1.0f - powf(b1, (float)step));
+    const float bh = b / (1.0f - powf(b2, (float)step));
+    p[i] -= lr * ah / (sqrtf(bh) + eps);
+}
+
+// dst[i][:] = src[perm[i]][:] (mini-batch assembly)
+__global__ void k_gather_rows(const float *__restrict__ src, int width, const int32_t *__restrict__ perm, int64_t n,
+                              float *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * width) return;
+    const int64_t r = i / width, c = i % width;
+    dst[i] = src[(int64_t)perm[r] * width + c];
+}
+
+__global__ void k_to_bf16(const float *__restrict__ in, __bf16 *__restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (__bf16)in[i];
+}
+
+// ---------------------------------------------------------------- training samples
+// out[i][8] = beam of channel chan[i] at (za[i], az[i]) from a complex64 grid
+// [n_chan][n_feed][n_ax][n_za][n_az]; components beyond n_feed * n_ax are zero.
+template <int MODE>
+__global__ void k_beam_samples(const float2 *__restrict__ grid, int n_feed, int n_ax, int n_za, int n_az, double dza,
+                               double daz, const double *__restrict__ za, const double *__restrict__ az,
+                               const int32_t *__restrict__ chan, int64_t n, float *__restrict__ out,
+                               const double *__restrict__ chan_freq, double nu0, double nu1, float *__restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (x) {
+        // the network's normalised inputs, as the simulator forms them
+        x[3 * i] = (float)(az[i] / (2.0 * M_PI));
+        x[3 * i + 1] = (float)(za[i] / (0.5 * M_PI));
+        x[3 * i + 2] = (float)((chan_freq[chan[i]] - nu0) / (nu1 - nu0));
+    }
+    const int ncomp = n_feed * n_ax;
+    const int64_t plane = (int64_t)n_za * n_az;
+    float2 v[4];
+    for (int c = 0; c < 4; c++) v[c] = make_float2(0.f, 0.f);
+    interp_point<float, MODE>(grid + (int64_t)chan[i] * ncomp * plane, plane, ncomp, n_za, n_az, dza, daz, za[i], az[i],
+                              1.0f, v, 1);
+    for (int c = 0; c < 4; c++) {
+        out[i * kOut + 2 * c] = v[c].x;
+        out[i * kOut + 2 * c + 1] = v[c].y;
+    }
+}
+
+// ---------------------------------------------------------------- fused inference
+constexpr int kRows = 64;              // points per workgroup
+constexpr int kLdF = kFeat + 8;        // LDS row strides (bf16 elements)
+constexpr int kLdH = kHid + 8;
+constexpr int kLdO = kHid + 4;         // FP32 row stride of the last hidden layer
+static_assert(kRows * kLdO * 4 <= kRows * kLdF * 2, "last hidden layer reuses the feature buffer");
+
+// One hidden layer for 64 rows: out = SiLU(in W^T + b), in [64][K] bf16 in LDS,
+// W [128][K] bf16 in global memory; wave w owns output columns 32w..32w+31.
+// out is bf16 (the next product's operand) or FP32 (the head's input), row stride LDO.
+template <int K, int LDI, typename TO, int LDO>
+__device__ inline void mlp_layer(const __bf16 *in, const __bf16 *__restrict__ W, const float *__restrict__ b, TO *out,
+                                 int wave, int l16, int lk) {
+    f32x4 acc[4][2];
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int c0 = wave * 32;
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 bw[2];
+        for (int j = 0; j < 2; j++) bw[j] = *(const bf16x8 *)(W + (int64_t)(c0 + 16 * j + l16) * K + k0 + lk * 8);
+        for (int i = 0; i < 4; i++) {
+            const bf16x8 av = *(const bf16x8 *)(in + (16 * i + l16) * LDI + k0 + lk * 8);
+            for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 2; j++)
+            for (int e = 0; e < 4; e++) {
+                const int r = 16 * i + 4 * lk + e, c = c0 + 16 * j + l16;
+                out[r * LDO + c] = (TO)silu(acc[i][j][e] + b[c]);
+            }
+}
+
+struct InferArgs {
+    const float *P;        // FP32 parameters (Fourier matrix, biases, output layer)
+    const __bf16 *Wb;      // bf16 W1 [128][256], W2..W4 [128][128], contiguous
+    double nu0, nu1;
+    // plain mode: x [n][3] normalised inputs, out [n][8]
+    const float *x;
+    float *out;
+    int64_t n;
+    // simulator mode: visible sources of a batch
+    const double *za_az;
+    const int32_t *count;
+    const int32_t *idx;
+    const double *flux;
+    int64_t n_src;
+    const double *freqs;
+    int64_t ld_src;
+    void *A;               // complex64 [inst][1][n_feed][n_ax][ld_src] = sqrt(I) J
+    int32_t n_feed, n_ax;
+    Batch bt;
+};
+
+template <bool SIM>
+__global__ void __launch_bounds__(256) k_mlp_infer(InferArgs a) {
+    __shared__ __attribute__((aligned(16))) __bf16 feat[kRows * kLdF];
+    __shared__ __attribute__((aligned(16))) __bf16 h0[kRows * kLdH];
+    __shared__ __attribute__((aligned(16))) __bf16 h1[kRows * kLdH];
+    __shared__ float xin[kRows][3];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int l16 = lane & 15, lk = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * kRows;
+    int64_t nrow;
+    int inst = 0, slot = 0, f = 0;
+    if (SIM) {
+        inst = blockIdx.y;
+        slot = inst / a.bt.nfb;
+        f = a.bt.f0 + inst % a.bt.nfb;
+        nrow = a.count[slot];
+    } else {
+        nrow = a.n;
+    }
+    if (r0 >= nrow) return;
+    if (tid < kRows) {
+        const int64_t m = r0 + tid;
+        float u = 0.f, v = 0.f, w = 0.f;
+        if (m < nrow) {
+            if (SIM) {
+                const double za = a.za_az[(int64_t)slot * 2 * a.ld_src + m];
+                const double az = a.za_az[(int64_t)slot * 2 * a.ld_src + a.ld_src + m];
+                u = (float)(az / (2.0 * M_PI));
+                v = (float)(za / (0.5 * M_PI));
+                w = (float)((a.freqs[f] - a.nu0) / (a.nu1 - a.nu0));
+            } else {
+                u = a.x[3 * m];
+                v = a.x[3 * m + 1];
+                w = a.x[3 * m + 2];
+            }
+        }
+        xin[tid][0] = u;
+        xin[tid][1] = v;
+        xin[tid][2] = w;
+    }
+    __syncthreads();
+    for (int e = tid; e < kRows * kFreq; e += 256) {
+        const int r = e / kFreq, j = e % kFreq;
+        const float *b = a.P + kOffBff + 3 * j;
+        float s, c;
+        sincos_rev(b[0] * xin[r][0] + b[1] * xin[r][1] + b[2] * xin[r][2], s, c);
+        feat[r * kLdF + j] = (__bf16)s;
+        feat[r * kLdF + kFreq + j] = (__bf16)c;
+    }
+    __syncthreads();
+    const __bf16 *W1 = a.Wb, *W2 = W1 + kHid * kFeat, *W3 = W2 + kHid * kHid, *W4 = W3 + kHid * kHid;
+    mlp_layer<kFeat, kLdF, __bf16, kLdH>(feat, W1, a.P + kOffB1, h0, wave, l16, lk);
+    __syncthreads();
+    mlp_layer<kHid, kLdH, __bf16, kLdH>(h0, W2, a.P + kOffB2, h1, wave, l16, lk);
+    __syncthreads();
+    mlp_layer<kHid, kLdH, __bf16, kLdH>(h1, W3, a.P + kOffB3, h0, wave, l16, lk);
+    __syncthreads();
+    float *h4 = (float *)feat;  // the features are dead after the first layer
+    mlp_layer<kHid, kLdH, float, kLdO>(h0, W4, a.P + kOffB4, h4, wave, l16, lk);
+    __syncthreads();
+    // output layer in FP32: two (row, output) pairs per thread
+    for (int e = tid; e < kRows * kOut; e += 256) {
+        const int r = e / kOut, o = e % kOut;
+        const float *w5 = a.P + kOffW5 + o * kHid;
+        float s = a.P[kOffB5 + o];
+        for (int k = 0; k < kHid; k++) s += h4[r * kLdO + k] * w5[k];
+        const int64_t m = r0 + r;
+        if (m >= nrow) continue;
+        if (SIM) {
+            // (re, im) pairs of J[p][k]; the simulator's components are (p, k) of n_feed x n_ax
+            const int c = o / 2, p = c / 2, k = c % 2;
+            if (p >= a.n_feed || k >= a.n_ax) continue;
+            const float sq =
+                a.idx ? (float)sqrt(a.flux[(int64_t)f * a.n_src + a.idx[(int64_t)slot * a.ld_src + m]]) : 1.0f;
+            float *dst = (float *)((float2 *)a.A + ((int64_t)inst * a.n_feed * a.n_ax + p * a.n_ax + k) * a.ld_src + m);
+            dst[o & 1] = sq * s;
+        } else {
+            a.out[m * kOut + o] = s;
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host glue
+namespace mlp {
+
+hipError_t features(const float *x, int64_t n, const float *P, float *phi, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_features<<<(unsigned)((n * kFreq + 255) / 256), 256, 0, s>>>(x, n, P, phi);
+    return hipGetLastError();
+}
+
+hipError_t gemm(bool bf16, const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbn, int64_t sbk, int M,
+                int N, int K, const float *bias, float *Z, float *H, int act, float *ws, int64_t ws_elems, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    GemmArgs g{A, sam, sak, B, sbn, sbk, M, N, K, bias, Z, H, act, K, nullptr};
+    dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
+    // long reductions over few output tiles (the weight gradients): split k
+    int nz = 1;
+    const int tiles = (int)(grid.x * grid.y);
+    if (ws && !bias && !H && !act && tiles < 128 && K >= 512) {
+        nz = std::min<int>((K + 127) / 128, (256 + tiles - 1) / tiles);
+        while (nz > 1 && (int64_t)nz * M * N > ws_elems) nz--;
+    }
+    if (nz > 1) {
+        g.kchunk = (((K + nz - 1) / nz) + 31) / 32 * 32;
+        nz = (K + g.kchunk - 1) / g.kchunk;
+        g.partial = ws;
+        grid.z = nz;
+    }
+    if (bf16)
+        k_gemm<true><<<grid, 256, 0, s>>>(g);
+    else
+        k_gemm<false><<<grid, 256, 0, s>>>(g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nz == 1) return e;
+    const int64_t n = (int64_t)M * N;
+    k_sum_partials<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ws, nz, n, Z);
+    return hipGetLastError();
+}
+
+hipError_t silu_bwd(const float *dH, const float *Z, float *dZ, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_silu_bwd<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dH, Z, dZ, n);
+    return hipGetLastError();
+}
+
+hipError_t loss_grad(const float *out, const float *y, int64_t n, float *dout, float *part, float *loss, hipStream_t s) {
+    const int nb = (int)((n * kOut + 255) / 256);
+    k_loss_grad<<<nb, 256, 0, s>>>(out, y, n, dout, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_finish_loss<<<1, 64, 0, s>>>(part, nb, n, loss);
+    return hipGetLastError();
+}
+
+hipError_t colsum(const float *dZ, int64_t M, int N, float *db, float *ws, int64_t ws_elems, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int64_t nch = (M + kColRows - 1) / kColRows;
+    if (nch * N > ws_elems) return hipErrorInvalidValue;
+    k_colsum_part<<<dim3((unsigned)((N + 63) / 64), (unsigned)nch), 256, 0, s>>>(dZ, M, N, ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_sum_partials<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(ws, (int)nch, N, db);
+    return hipGetLastError();
+}
+
+hipError_t adam(float *p, const float *g, float *m1, float *m2, int64_t n, int64_t step, float lr, hipStream_t s) {
+    k_adam<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, g, m1, m2, n, step, lr, 0.9f, 0.999f, 1e-8f);
+    return hipGetLastError();
+}
+
+hipError_t gather_rows(const float *src, int width, const int32_t *perm, int64_t n, float *dst, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_gather_rows<<<(unsigned)((n * width + 255) / 256), 256, 0, s>>>(src, width, perm, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float *in, __bf16 *out, int64_t n, hipStream_t s) {
+    k_to_bf16<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t pack_weights(const float *P, __bf16 *Wb, hipStream_t s) {
+    hipError_t e = to_bf16(P + kOffW1, Wb, (int64_t)kHid * kFeat, s);
+    const int64_t off[3] = {kOffW2, kOffW3, kOffW4};
+    for (int l = 0; l < 3 && e == hipSuccess; l++)
+        e = to_bf16(P + off[l], Wb + (int64_t)kHid * kFeat + l * (int64_t)kHid * kHid, (int64_t)kHid * kHid, s);
+    return e;
+}
+
+hipError_t beam_samples(const void *grid, int n_feed, int n_ax, int n_za, int n_az, double dza, double daz,
+                        int bicubic, const double *za, const double *az, const int32_t *chan, int64_t n, float *out,
+                        const double *chan_freq, double nu0, double nu1, float *x, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (bicubic)
+        k_beam_samples<BICUBIC><<<nb, 256, 0, s>>>((const float2 *)grid, n_feed, n_ax, n_za, n_az, dza, daz, za, az,
+                                                   chan, n, out, chan_freq, nu0, nu1, x);
+    else
+        k_beam_samples<BILINEAR><<<nb, 256, 0, s>>>((const float2 *)grid, n_feed, n_ax, n_za, n_az, dza, daz, za, az,
+                                                    chan, n, out, chan_freq, nu0, nu1, x);
+    return hipGetLastError();
+}
+
+hipError_t infer_plain(const float *P, const __bf16 *Wb, const float *x, int64_t n, float *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    InferArgs a{};
+    a.P = P;
+    a.Wb = Wb;
+    a.x = x;
+    a.out = out;
+    a.n = n;
+    k_mlp_infer<false><<<(unsigned)((n + kRows - 1) / kRows), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t infer_sim(const float *P, const __bf16 *Wb, double nu0, double nu1, const double *za_az,
+                     const int32_t *count, const int32_t *idx, const double *flux, int64_t n_src, const double *freqs,
+                     int64_t ld_src, int64_t max_m, void *A, int n_feed, int n_ax, const Batch &bt, hipStream_t s) {
+    if (bt.n_inst <= 0 || max_m <= 0) return hipSuccess;
+    InferArgs a{};
+    a.P = P;
+    a.Wb = Wb;
+    a.nu0 = nu0;
+    a.nu1 = nu1;
+    a.za_az = za_az;
+    a.count = count;
+    a.idx = idx;
+    a.flux = flux;
+    a.n_src = n_src;
+    a.freqs = freqs;
+    a.ld_src = ld_src;
+    a.A = A;
+    a.n_feed = n_feed;
+    a.n_ax = n_ax;
+    a.bt = bt;
+    dim3 g((unsigned)((max_m + kRows - 1) / kRows), bt.n_inst);
+    k_mlp_infer<true><<<g, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace mlp
+
+}  // namespace mv

@@ -23,6 +23,7 @@
 
 #include "matvis.h"
 #include "internal.h"
+#include "mlp.h"
 
 using namespace mv;
 
@@ -68,6 +69,12 @@ struct matvis_ctx {
     bool profiling = false;
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> event_pool;
+
+    // learned beam (beam_mode MATVIS_BEAM_SURROGATE)
+    float *sur_P = nullptr;     // FP32 parameters
+    __bf16 *sur_Wb = nullptr;   // bf16 W1..W4
+    double sur_nu0 = 0, sur_nu1 = 1;
+    bool sur_set = false;
 };
 
 namespace {
@@ -143,18 +150,24 @@ matvis_status validate_cfg(const matvis_config *c, std::string &why) {
     if (c->precision < MATVIS_FP64 || c->precision > MATVIS_BF16X3) return why = "unknown precision", MATVIS_EINVAL;
     if (c->beam_mode < MATVIS_BEAM_BILINEAR || c->beam_mode > MATVIS_BEAM_SURROGATE)
         return why = "unknown beam mode", MATVIS_EINVAL;
-    if (c->beam_mode == MATVIS_BEAM_SURROGATE)
-        return why = "the surrogate beam is not available in this build", MATVIS_EUNSUPPORTED;
-    if (c->n_za < 3 || c->n_az < 3) return why = "beam grid must be at least 3 x 3", MATVIS_EINVAL;
-    if (!(c->dza_rad > 0) || !(c->daz_rad > 0)) return why = "grid spacings must be positive", MATVIS_EINVAL;
-    if (std::fabs((c->n_za - 1) * c->dza_rad - M_PI / 2) > 1e-9)
-        return why = "(n_za - 1) * dza_rad must equal pi/2 (za rows 0..90 deg)", MATVIS_EINVAL;
-    if (std::fabs(c->n_az * c->daz_rad - 2 * M_PI) > 1e-9)
-        return why = "n_az * daz_rad must equal 2 pi (periodic az)", MATVIS_EINVAL;
+    if (c->beam_mode == MATVIS_BEAM_SURROGATE) {
+        if (c->precision == MATVIS_FP64)
+            return why = "the learned beam runs with FP32 or BF16X3 products", MATVIS_EUNSUPPORTED;
+        if (c->n_beam != 1) return why = "the learned beam models one unique beam (n_beam = 1)", MATVIS_EUNSUPPORTED;
+    } else {
+        if (c->n_za < 3 || c->n_az < 3) return why = "beam grid must be at least 3 x 3", MATVIS_EINVAL;
+        if (!(c->dza_rad > 0) || !(c->daz_rad > 0)) return why = "grid spacings must be positive", MATVIS_EINVAL;
+        if (std::fabs((c->n_za - 1) * c->dza_rad - M_PI / 2) > 1e-9)
+            return why = "(n_za - 1) * dza_rad must equal pi/2 (za rows 0..90 deg)", MATVIS_EINVAL;
+        if (std::fabs(c->n_az * c->daz_rad - 2 * M_PI) > 1e-9)
+            return why = "n_az * daz_rad must equal 2 pi (periodic az)", MATVIS_EINVAL;
+    }
     if (!std::isfinite(c->latitude_rad) || std::fabs(c->latitude_rad) > M_PI / 2)
         return why = "latitude out of range", MATVIS_EINVAL;
     if (c->src_chunk < 0 || c->batch_time < 0 || c->batch_freq < 0) return why = "negative batch sizes", MATVIS_EINVAL;
     if ((int64_t)c->n_ant * c->n_feed > 8192) return why = "n_ant * n_feed above 8192", MATVIS_EUNSUPPORTED;
+    if (c->ksplit < 0 || c->ksplit % 64 != 0 || c->ksplit > ((int64_t)1 << 30))
+        return why = "ksplit must be 0 or a positive multiple of 64", MATVIS_EINVAL;
     return MATVIS_OK;
 }
 
@@ -217,7 +230,10 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     // Columns per work item.  FP32 accumulators see ksplit / 2 sequential MFMA
     // updates per item; 2048 keeps that rounding near 2e-6 of the Cauchy-Schwarz
     // scale, and the items' partials are then summed in FP64.
-    c->ksplit = prec == P64 ? 8192 : 2048;
+    // Default k-split per precision: measured on the 128-antenna polarised workload,
+    // err_CS grows about as sqrt(ksplit) (FP32: 3.1e-6 at 2048, 1.4e-5 at 8192;
+    // BF16X3: 2.5e-6 at 4096, whose split error dominates below that).
+    c->ksplit = cfg->ksplit > 0 ? cfg->ksplit : (prec == P64 ? 8192 : prec == P32 ? 2048 : 4096);
     c->max_splits = (int)((c->ldz + c->ksplit - 1) / c->ksplit);
     // batch: all channels of a few times, enough instances to fill the GPU with
     // work items while keeping Z within a fixed share of device memory
@@ -268,6 +284,10 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     ALLOC(c->part, cbytes(prec) * B * (size_t)c->max_splits * c->Np * c->Np);
     if (c->chunk < cfg->max_src) ALLOC(c->vacc, sizeof(double) * 2 * B * (size_t)c->N * c->N);
     ALLOC(c->work, sizeof(int32_t) * (B + 1));
+    if (cfg->beam_mode == MATVIS_BEAM_SURROGATE) {
+        ALLOC(c->sur_P, sizeof(float) * kNParams);
+        ALLOC(c->sur_Wb, sizeof(__bf16) * mlp::kWbElems);
+    }
 #undef ALLOC
     // Rows N..Np-1 of Z are never written by the kernels and must read as zero.
     hipError_t e = hipMemset(c->Z, 0, zbytes);
@@ -354,7 +374,12 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                     ia.flux = flux;
                     ia.n_src = n_src;
                 }
-                STEP(c, MATVIS_STEP_BEAM, s, launch_interp(prec, g.beam_mode, ia, bt, s));
+                if (g.beam_mode == MATVIS_BEAM_SURROGATE)
+                    STEP(c, MATVIS_STEP_BEAM, s,
+                         mlp::infer_sim(c->sur_P, c->sur_Wb, c->sur_nu0, c->sur_nu1, c->za_az, c->count, ia.idx, flux,
+                                        n_src, freqs, c->chunk, ns, c->A, g.n_feed, g.n_ax, bt, s));
+                else
+                    STEP(c, MATVIS_STEP_BEAM, s, launch_interp(prec, g.beam_mode, ia, bt, s));
 
                 HerkArgs ha{};
                 ha.Z = c->Z;
@@ -463,7 +488,11 @@ matvis_status matvis_simulate(matvis_ctx *c, const double *antpos, const int32_t
     const matvis_config &g = c->cfg;
     if (!antpos || !freqs || !lsts || !vis) return fail(c, MATVIS_EINVAL, "a required pointer is NULL");
     if (n_src > 0 && (!src_radec || !src_flux)) return fail(c, MATVIS_EINVAL, "src_radec or src_flux is NULL");
-    if (!beam_grid) return fail(c, MATVIS_EINVAL, "beam_grid is NULL");
+    if (g.beam_mode == MATVIS_BEAM_SURROGATE) {
+        if (!c->sur_set) return fail(c, MATVIS_ESTATE, "no learned beam loaded (call matvis_set_surrogate)");
+    } else if (!beam_grid) {
+        return fail(c, MATVIS_EINVAL, "beam_grid is NULL");
+    }
     if (n_freq <= 0 || n_freq > g.max_freq) return fail(c, MATVIS_EINVAL, "n_freq outside [1, max_freq]");
     if (n_time <= 0 || n_time > g.max_time) return fail(c, MATVIS_EINVAL, "n_time outside [1, max_time]");
     if (n_src < 0 || n_src > g.max_src) return fail(c, MATVIS_EINVAL, "n_src outside [0, max_src]");
@@ -511,6 +540,29 @@ matvis_status matvis_simulate(matvis_ctx *c, const double *antpos, const int32_t
         c->graph_order.push_back(key);
     }
     HIPCHK(c, hipGraphLaunch(it->second, s));
+    return MATVIS_OK;
+}
+
+matvis_status matvis_set_surrogate(matvis_ctx *c, const float *params, double nu_min_hz, double nu_max_hz) {
+    if (!c) return MATVIS_EINVAL;
+    c->err.clear();
+    if (c->cfg.beam_mode != MATVIS_BEAM_SURROGATE)
+        return fail(c, MATVIS_ESTATE, "context was not created with beam_mode MATVIS_BEAM_SURROGATE");
+    if (!params) return fail(c, MATVIS_EINVAL, "params is NULL");
+    if (!std::isfinite(nu_min_hz) || !std::isfinite(nu_max_hz) || !(nu_max_hz > nu_min_hz))
+        return fail(c, MATVIS_EINVAL, "need finite nu_min_hz < nu_max_hz");
+    HIPCHK(c, hipSetDevice(c->device));
+    // kernels already captured hold the old normalisation by value
+    HIPCHK(c, hipDeviceSynchronize());
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    c->graph_order.clear();
+    HIPCHK(c, hipMemcpy(c->sur_P, params, sizeof(float) * kNParams, hipMemcpyDeviceToDevice));
+    HIPCHK(c, mlp::pack_weights(c->sur_P, c->sur_Wb, nullptr));
+    HIPCHK(c, hipDeviceSynchronize());
+    c->sur_nu0 = nu_min_hz;
+    c->sur_nu1 = nu_max_hz;
+    c->sur_set = true;
     return MATVIS_OK;
 }
 

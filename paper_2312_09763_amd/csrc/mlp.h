@@ -1,0 +1,73 @@
+// Learned beam: a Fourier-feature MLP (az, za, nu) -> 2 x 2 complex Jones
+// matrix, evaluated and trained by the kernels of kernels_mlp.hip.
+//
+// Parameter vector (FP32, the master copy), in this order:
+//   Bff [kFreq][3]      Fourier frequencies (fixed; not trained).  Row j
+//                        multiplies (u, v, w) = (az / 2 pi, za / (pi / 2),
+//                        (nu - nu0) / (nu1 - nu0)); the az entries are integers,
+//                        so every feature is periodic in az.
+//   W1 [kHid][2 kFreq], b1 [kHid]      features -> hidden 1
+//   W2, W3, W4 [kHid][kHid], b2..b4    hidden l -> hidden l + 1
+//   W5 [8][kHid], b5 [8]               hidden 4 -> (re, im) of J[p][k], (p, k) row-major
+// Features: phi_j = sin(2 pi Bff_j . x), phi_{kFreq + j} = cos(2 pi Bff_j . x).
+// Hidden layers use SiLU(z) = z / (1 + exp(-z)).
+// The four hidden-layer products round both operands to bf16 and accumulate
+// in FP32 on MFMA; biases, SiLU and the linear head (W5, b5) stay in FP32.
+#pragma once
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace mv {
+
+constexpr int kFreq = 128;                    // Fourier frequencies (2 kFreq features)
+constexpr int kFeat = 2 * kFreq;              // 256
+constexpr int kHid = 128;                     // hidden width
+constexpr int kOut = 8;                       // 2 x 2 complex outputs
+constexpr int64_t kOffBff = 0;
+constexpr int64_t kOffW1 = kOffBff + kFreq * 3;
+constexpr int64_t kOffB1 = kOffW1 + (int64_t)kHid * kFeat;
+constexpr int64_t kOffW2 = kOffB1 + kHid;
+constexpr int64_t kOffB2 = kOffW2 + (int64_t)kHid * kHid;
+constexpr int64_t kOffW3 = kOffB2 + kHid;
+constexpr int64_t kOffB3 = kOffW3 + (int64_t)kHid * kHid;
+constexpr int64_t kOffW4 = kOffB3 + kHid;
+constexpr int64_t kOffB4 = kOffW4 + (int64_t)kHid * kHid;
+constexpr int64_t kOffW5 = kOffB4 + kHid;
+constexpr int64_t kOffB5 = kOffW5 + (int64_t)kOut * kHid;
+constexpr int64_t kNParams = kOffB5 + kOut;   // 83848
+
+// Host launchers (kernels_mlp.hip).  Row-major FP32 operands; every call is
+// asynchronous on stream s and returns the launch status.
+namespace mlp {
+hipError_t features(const float *x, int64_t n, const float *P, float *phi, hipStream_t s);
+// Z = A B^T + bias with A(m, k) = A[m sam + k sak], B(n, k) = B[n sbn + k sbk];
+// H = SiLU(Z) when act = 1.  bf16 rounds both operands to bf16 first.  A plain
+// product (no bias, no H) over a long k may split k through the workspace ws
+// (ws_elems floats; NULL disables the split).
+hipError_t gemm(bool bf16, const float *A, int64_t sam, int64_t sak, const float *B, int64_t sbn, int64_t sbk, int M,
+                int N, int K, const float *bias, float *Z, float *H, int act, float *ws, int64_t ws_elems,
+                hipStream_t s);
+hipError_t silu_bwd(const float *dH, const float *Z, float *dZ, int64_t n, hipStream_t s);
+hipError_t loss_grad(const float *out, const float *y, int64_t n, float *dout, float *part, float *loss, hipStream_t s);
+// db[c] = sum_m dZ[m][c] (fixed summation order) through the workspace ws
+hipError_t colsum(const float *dZ, int64_t M, int N, float *db, float *ws, int64_t ws_elems, hipStream_t s);
+hipError_t adam(float *p, const float *g, float *m1, float *m2, int64_t n, int64_t step, float lr, hipStream_t s);
+hipError_t to_bf16(const float *in, __bf16 *out, int64_t n, hipStream_t s);
+// bf16 copies of W1..W4 packed back to back (kWbElems values) for inference
+constexpr int64_t kWbElems = (int64_t)kHid * kFeat + 3 * (int64_t)kHid * kHid;
+hipError_t pack_weights(const float *P, __bf16 *Wb, hipStream_t s);
+hipError_t beam_samples(const void *grid, int n_feed, int n_ax, int n_za, int n_az, double dza, double daz,
+                        int bicubic, const double *za, const double *az, const int32_t *chan, int64_t n, float *out,
+                        const double *chan_freq, double nu0, double nu1, float *x, hipStream_t s);
+hipError_t infer_plain(const float *P, const __bf16 *Wb, const float *x, int64_t n, float *out, hipStream_t s);
+// Simulator mode: A of every instance of batch bt = sqrt(I) J (sqrt(I) = 1
+// when idx is NULL) at the batch's visible sources.
+hipError_t infer_sim(const float *P, const __bf16 *Wb, double nu0, double nu1, const double *za_az,
+                     const int32_t *count, const int32_t *idx, const double *flux, int64_t n_src, const double *freqs,
+                     int64_t ld_src, int64_t max_m, void *A, int n_feed, int n_ax, const Batch &bt, hipStream_t s);
+hipError_t gather_rows(const float *src, int width, const int32_t *perm, int64_t n, float *dst, hipStream_t s);
+}  // namespace mlp
+
+}  // namespace mv

@@ -29,6 +29,7 @@ FLAG_UNFUSED = 2
 STEPS = ("sky", "beam", "zform", "herk", "reduce", "other")
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 BEAM_MODES = {"bilinear": BILINEAR, "bicubic": BICUBIC, "surrogate": SURROGATE}
+MLP_N_PARAMS = 83848  # learned-beam parameter count (include/matvis.h)
 
 
 class MatvisError(RuntimeError):
@@ -43,7 +44,8 @@ class _Config(ctypes.Structure):
                 ("max_freq", ctypes.c_int32), ("latitude_rad", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("beam_mode", ctypes.c_int32), ("n_za", ctypes.c_int32), ("n_az", ctypes.c_int32),
                 ("dza_rad", ctypes.c_double), ("daz_rad", ctypes.c_double), ("src_chunk", ctypes.c_int64),
-                ("batch_time", ctypes.c_int32), ("batch_freq", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("batch_time", ctypes.c_int32), ("batch_freq", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("ksplit", ctypes.c_int64)]
 
 
 _lib = None
@@ -77,10 +79,29 @@ def load_library():
     L.matvis_step_interp.restype = ctypes.c_int
     L.matvis_step_herk.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _P, _P]
     L.matvis_step_herk.restype = ctypes.c_int
+    L.matvis_autotune.argtypes = [ctypes.POINTER(_Config), _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P,
+                                  ctypes.c_int64, _P, _P, _P, _P, ctypes.c_char_p, ctypes.POINTER(_Config),
+                                  ctypes.POINTER(ctypes.c_double)]
+    L.matvis_autotune.restype = ctypes.c_int
     L.matvis_profile_enable.argtypes = [_P, ctypes.c_int32]
     L.matvis_profile_enable.restype = ctypes.c_int
     L.matvis_profile_read.argtypes = [_P, _P, _P]
     L.matvis_profile_read.restype = ctypes.c_int
+    L.matvis_mlp_forward.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
+    L.matvis_mlp_forward.restype = ctypes.c_int
+    L.matvis_mlp_loss_grad.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P]
+    L.matvis_mlp_loss_grad.restype = ctypes.c_int
+    L.matvis_mlp_adam.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float, _P]
+    L.matvis_mlp_adam.restype = ctypes.c_int
+    L.matvis_beam_samples.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P, _P, _P,
+                                      ctypes.c_int64, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P]
+    L.matvis_beam_samples.restype = ctypes.c_int
+    L.matvis_train_surrogate.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_uint64, ctypes.c_int32, _P, _P]
+    L.matvis_train_surrogate.restype = ctypes.c_int
+    L.matvis_set_surrogate.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double]
+    L.matvis_set_surrogate.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -114,12 +135,14 @@ class Config:
     batch_freq: int = 0
     use_graph: bool = True
     unfused: bool = False  # FP32 / BF16X3: separate Z-formation step (Z in device memory)
+    ksplit: int = 0        # columns per product work item (multiple of 64); 0 = automatic
 
     def _c(self) -> _Config:
         return _Config(self.n_ant, self.n_feed, self.n_ax, self.n_beam, self.max_src, self.max_time, self.max_freq,
                        self.latitude_rad, PRECISIONS[self.precision], BEAM_MODES[self.beam_mode], self.n_za,
                        self.n_az, self.dza_rad, self.daz_rad, self.src_chunk, self.batch_time, self.batch_freq,
-                       (0 if self.use_graph else FLAG_NO_GRAPH) | (FLAG_UNFUSED if self.unfused else 0))
+                       (0 if self.use_graph else FLAG_NO_GRAPH) | (FLAG_UNFUSED if self.unfused else 0),
+                       self.ksplit)
 
 
 def _ptr(t) -> Optional[int]:
@@ -178,7 +201,10 @@ class Context:
         _need(lsts, torch.float64, (n_time,), "lsts")
         _need(src_radec, torch.float64, (2, n_src), "src_radec")
         _need(src_flux, torch.float64, (n_freq, n_src), "src_flux")
-        _need(beam_grid, self.complex_dtype, (c.n_beam, n_freq, c.n_feed, c.n_ax, c.n_za, c.n_az), "beam_grid")
+        if c.beam_mode == "surrogate":
+            beam_grid = None  # the learned beam replaces the grid
+        else:
+            _need(beam_grid, self.complex_dtype, (c.n_beam, n_freq, c.n_feed, c.n_ax, c.n_za, c.n_az), "beam_grid")
         if beam_idx is not None:
             _need(beam_idx, torch.int32, (c.n_ant,), "beam_idx")
         shape = (n_time, n_freq, c.n_ant, c.n_ant, c.n_feed, c.n_feed)
@@ -240,6 +266,12 @@ class Context:
         self._check(self._L.matvis_step_herk(self._h, _ptr(Z), n_row, n_col, n_col, _ptr(V), _stream_handle(stream)))
         return V
 
+    def set_surrogate(self, params, nu_min_hz: float, nu_max_hz: float):
+        """matvis_set_surrogate: load a learned beam (copied) and its frequency range."""
+        import torch
+        _need(params, torch.float32, (MLP_N_PARAMS,), "params")
+        self._check(self._L.matvis_set_surrogate(self._h, _ptr(params), float(nu_min_hz), float(nu_max_hz)))
+
     def close(self):
         if getattr(self, "_h", None):
             self._L.matvis_destroy(self._h)
@@ -256,6 +288,114 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def autotune(cfg: Config, antpos, freqs, lsts, src_radec, src_flux, beam_grid, beam_idx=None, vis=None,
+             cache_path: Optional[str] = None, stream=None):
+    """matvis_autotune: (tuned Config, ms per simulate call).  ``vis`` is scratch output."""
+    import torch
+    L = load_library()
+    n_freq, n_time, n_src = freqs.shape[0], lsts.shape[0], src_radec.shape[1]
+    cdt = torch.complex128 if cfg.precision == "fp64" else torch.complex64
+    if vis is None:
+        vis = torch.empty((n_time, n_freq, cfg.n_ant, cfg.n_ant, cfg.n_feed, cfg.n_feed), dtype=cdt,
+                          device=antpos.device)
+    best = _Config()
+    ms = ctypes.c_double()
+    st = L.matvis_autotune(ctypes.byref(cfg._c()), _ptr(antpos), _ptr(beam_idx), _ptr(freqs), n_freq, _ptr(lsts),
+                           n_time, _ptr(src_radec), n_src, _ptr(src_flux), _ptr(beam_grid), _ptr(vis),
+                           _stream_handle(stream), cache_path.encode() if cache_path else None, ctypes.byref(best),
+                           ctypes.byref(ms))
+    if st != OK:
+        raise MatvisError(st, "matvis_autotune failed")
+    tuned = dataclasses.replace(cfg, ksplit=int(best.ksplit), batch_time=int(best.batch_time),
+                                unfused=bool(best.flags & FLAG_UNFUSED))
+    return tuned, float(ms.value)
+
+
+def _check_lib(st: int, what: str):
+    if st != OK:
+        raise MatvisError(st, f"{what} failed (details on stderr)")
+
+
+def mlp_forward(params, x, stream=None):
+    """matvis_mlp_forward: learned-beam outputs [n][8] for inputs x [n][3] (synchronous)."""
+    import torch
+    n = x.shape[0]
+    _need(params, torch.float32, (MLP_N_PARAMS,), "params")
+    _need(x, torch.float32, (n, 3), "x")
+    out = torch.empty((n, 8), dtype=torch.float32, device=x.device)
+    _check_lib(load_library().matvis_mlp_forward(_ptr(params), _ptr(x), n, _ptr(out), _stream_handle(stream)),
+               "matvis_mlp_forward")
+    return out
+
+
+def mlp_loss_grad(params, x, y, fp32_math: bool = False, stream=None):
+    """matvis_mlp_loss_grad: (grad [MLP_N_PARAMS], loss [1]) of the mean squared error (synchronous)."""
+    import torch
+    n = x.shape[0]
+    _need(params, torch.float32, (MLP_N_PARAMS,), "params")
+    _need(x, torch.float32, (n, 3), "x")
+    _need(y, torch.float32, (n, 8), "y")
+    grad = torch.empty_like(params)
+    loss = torch.empty((1,), dtype=torch.float32, device=x.device)
+    _check_lib(load_library().matvis_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(y), n, 1 if fp32_math else 0,
+                                                   _ptr(grad), _ptr(loss), _stream_handle(stream)),
+               "matvis_mlp_loss_grad")
+    return grad, loss
+
+
+def mlp_adam(params, grad, m1, m2, step: int, lr: float, stream=None):
+    """matvis_mlp_adam: one Adam step on params (in place)."""
+    import torch
+    for t, name in ((params, "params"), (grad, "grad"), (m1, "m1"), (m2, "m2")):
+        _need(t, torch.float32, (MLP_N_PARAMS,), name)
+    _check_lib(load_library().matvis_mlp_adam(_ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), int(step), float(lr),
+                                              _stream_handle(stream)), "matvis_mlp_adam")
+
+
+def beam_samples(grid, dza_rad: float, daz_rad: float, za, az, chan, bicubic: bool = True, chan_freq=None,
+                 nu_range=None, stream=None):
+    """matvis_beam_samples: targets y [n][8] (and inputs x [n][3] when chan_freq and nu_range are given).
+
+    grid is complex64 [n_chan][n_feed][n_ax][n_za][n_az]; za, az float64 [n]; chan int32 [n].
+    """
+    import torch
+    n_chan, n_feed, n_ax, n_za, n_az = grid.shape
+    n = za.shape[0]
+    _need(grid, torch.complex64, grid.shape, "grid")
+    _need(za, torch.float64, (n,), "za")
+    _need(az, torch.float64, (n,), "az")
+    _need(chan, torch.int32, (n,), "chan")
+    y = torch.empty((n, 8), dtype=torch.float32, device=za.device)
+    x = None
+    nu0 = nu1 = 0.0
+    if chan_freq is not None:
+        _need(chan_freq, torch.float64, (n_chan,), "chan_freq")
+        nu0, nu1 = (float(v) for v in nu_range)
+        x = torch.empty((n, 3), dtype=torch.float32, device=za.device)
+    _check_lib(load_library().matvis_beam_samples(_ptr(grid), n_chan, n_feed, n_ax, n_za, n_az, float(dza_rad),
+                                                  float(daz_rad), 1 if bicubic else 0, _ptr(za), _ptr(az),
+                                                  _ptr(chan), n, _ptr(y), _ptr(chan_freq), nu0, nu1, _ptr(x),
+                                                  _stream_handle(stream)), "matvis_beam_samples")
+    return y, x
+
+
+def train_surrogate(params, x, y, batch: int = 4096, epochs: int = 10, lr0: float = 2e-3, lr1: float = 1e-4,
+                    seed: int = 0, fp32_math: bool = False, stream=None):
+    """matvis_train_surrogate: train params in place; returns the per-epoch mean loss (numpy, float32)."""
+    import numpy as np
+    import torch
+    n = x.shape[0]
+    _need(params, torch.float32, (MLP_N_PARAMS,), "params")
+    _need(x, torch.float32, (n, 3), "x")
+    _need(y, torch.float32, (n, 8), "y")
+    hist = np.zeros(epochs, dtype=np.float32)
+    _check_lib(load_library().matvis_train_surrogate(_ptr(params), _ptr(x), _ptr(y), n, int(batch), int(epochs),
+                                                     float(lr0), float(lr1), int(seed), 1 if fp32_math else 0,
+                                                     hist.ctypes.data, _stream_handle(stream)),
+               "matvis_train_surrogate")
+    return hist
 
 
 def config_for(wl, precision: str = "fp32", **kw) -> Config:

@@ -53,7 +53,8 @@ def _init(**kw):
     (dict(n_za=90), mv.EINVAL),           # rows do not reach the horizon
     (dict(n_az=359), mv.EINVAL),          # not periodic
     (dict(latitude_rad=2.0), mv.EINVAL),
-    (dict(beam_mode="surrogate"), mv.EUNSUPPORTED),
+    (dict(beam_mode="surrogate", precision="fp64"), mv.EUNSUPPORTED),
+    (dict(beam_mode="surrogate", n_beam=2), mv.EUNSUPPORTED),
     (dict(n_ant=5000, n_feed=2), mv.EUNSUPPORTED),
 ])
 def test_init_rejects_bad_config(kw, status):
@@ -73,6 +74,18 @@ def test_null_context_calls():
     assert L.matvis_last_error(None) == b"NULL context"
     assert L.matvis_simulate(None, None, None, None, 1, None, 1, None, 1, None, None, None, None) == mv.EINVAL
     L.matvis_destroy(None)
+
+
+def test_learned_beam_entry_points_reject_null_arguments():
+    # argument checks happen on the host, before any device call
+    L = mv.load_library()
+    assert L.matvis_set_surrogate(None, None, 1e8, 2e8) == mv.EINVAL
+    assert L.matvis_mlp_forward(None, None, 4, None, None) == mv.EINVAL
+    assert L.matvis_mlp_loss_grad(None, None, None, 4, 0, None, None, None) == mv.EINVAL
+    assert L.matvis_mlp_adam(None, None, None, None, 1, 1e-3, None) == mv.EINVAL
+    assert L.matvis_train_surrogate(None, None, None, 4, 4, 1, 1e-3, 1e-4, 0, 0, None, None) == mv.EINVAL
+    assert L.matvis_beam_samples(None, 1, 1, 1, 91, 360, 0.01, 0.01, 0, None, None, None, 4, None, None, 0.0, 0.0,
+                                 None, None) == mv.EINVAL
 
 
 def test_binding_refuses_without_library(monkeypatch):

@@ -1,0 +1,263 @@
+"""Learned beam on the GPU against the FP64 reference (oracle/mlp.py).
+
+Forward: the library's network (hidden products on bf16 operands, FP32
+accumulate) against the reference with the same operand rounding, and
+against the exact float64 network.  Gradient: FP32 check mode against the
+float64 reverse-mode gradient; the bf16 training mode within its rounding
+bound.  Adam, the sample generator (against the C reference interpolant),
+training (loss falls, run-to-run bitwise reproducible, first steps against a
+reference Adam loop) and the simulator with the learned beam in place of the
+interpolated one (against the direct sum with the reference network's beam).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import metrics
+from oracle import mlp as om
+from paper_2312_09763_amd import matvis as mv
+from paper_2312_09763_amd import synth
+
+from helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, dt):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def _inputs(n, seed=1, wrap=False):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.random((n, 3))
+    if wrap:
+        x[:, 0] = rng.uniform(-1.5, 2.5, n)  # az outside one turn: features are periodic
+    return x.astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def p0():
+    return synth.surrogate_init(0)
+
+
+@pytest.mark.parametrize("n", [1, 63, 1000])
+def test_forward_matches_reference(p0, n):
+    say(f"mlp forward n={n}")
+    x = _inputs(n, wrap=True)
+    out = mv.mlp_forward(_dev(p0, np.float32), _dev(x, np.float32)).cpu().numpy().astype(np.float64)
+    ref_b = om.forward(p0, x.astype(np.float64), bf16=True)
+    ref = om.forward(p0, x.astype(np.float64))
+    e_b, e = _rel(out, ref_b), _rel(out, ref)
+    say(f"  rel vs bf16-operand reference {e_b:.2e}, vs exact {e:.2e}")
+    assert e_b <= 2e-4
+    assert np.max(np.abs(out - ref_b)) <= 2e-3 * np.max(np.abs(ref_b))
+    assert e <= 2e-2
+
+
+def test_forward_empty(p0):
+    out = mv.mlp_forward(_dev(p0, np.float32), torch.empty((0, 3), dtype=torch.float32, device="cuda"))
+    assert out.shape == (0, 8)
+
+
+def _grad_blocks(g):
+    G = om.unpack(np.asarray(g, dtype=np.float64))
+    return {k: v for k, v in G.items()}
+
+
+@pytest.mark.parametrize("n", [1, 300])
+def test_loss_grad_fp32_matches_reference(p0, n):
+    say(f"mlp loss_grad fp32 n={n}")
+    x = _inputs(n, seed=2)
+    y = np.random.Generator(np.random.PCG64(3)).normal(0, 0.5, (n, 8)).astype(np.float32)
+    g, L = mv.mlp_loss_grad(_dev(p0, np.float32), _dev(x, np.float32), _dev(y, np.float32), fp32_math=True)
+    g = g.cpu().numpy()
+    g_ref, L_ref = om.loss_grad(p0, x.astype(np.float64), y.astype(np.float64))
+    assert float(L.item()) == pytest.approx(L_ref, rel=1e-5)
+    G, R = _grad_blocks(g), _grad_blocks(g_ref)
+    assert np.all(G["B"] == 0)
+    for k in R:
+        if k == "B":
+            continue
+        e = _rel(G[k], R[k])
+        say(f"  {k}: rel {e:.2e}")
+        assert e <= 2e-5, k
+
+
+def test_loss_grad_bf16_within_rounding(p0):
+    n = 500
+    x = _inputs(n, seed=4)
+    y = np.random.Generator(np.random.PCG64(5)).normal(0, 0.5, (n, 8)).astype(np.float32)
+    g, L = mv.mlp_loss_grad(_dev(p0, np.float32), _dev(x, np.float32), _dev(y, np.float32), fp32_math=False)
+    g = g.cpu().numpy()
+    g_ref, L_ref = om.loss_grad(p0, x.astype(np.float64), y.astype(np.float64))
+    # the loss of the bf16-operand network, and its gradient within bf16 rounding of the exact one
+    assert float(L.item()) == pytest.approx(om.loss(p0, x.astype(np.float64), y.astype(np.float64), bf16=True),
+                                            rel=1e-4)
+    G, R = _grad_blocks(g), _grad_blocks(g_ref)
+    for k in R:
+        if k == "B":
+            continue
+        e = _rel(G[k], R[k])
+        say(f"  {k}: rel {e:.2e}")
+        assert e <= 5e-2, k
+    assert L_ref == pytest.approx(float(L.item()), rel=2e-2)
+
+
+def test_adam_matches_reference():
+    rng = np.random.Generator(np.random.PCG64(6))
+    p = rng.normal(size=om.N_PARAMS).astype(np.float32)
+    g = rng.normal(size=om.N_PARAMS).astype(np.float32)
+    m1 = rng.normal(scale=0.1, size=om.N_PARAMS).astype(np.float32)
+    m2 = rng.uniform(0.0, 0.5, size=om.N_PARAMS).astype(np.float32)
+    P, Gd, M1, M2 = (_dev(a, np.float32) for a in (p, g, m1, m2))
+    mv.mlp_adam(P, Gd, M1, M2, 3, 1e-3)
+    torch.cuda.synchronize()
+    r1, r2 = m1.astype(np.float64), m2.astype(np.float64)
+    q = om.adam_step(p, g, r1, r2, 3, 1e-3)
+    out = P.cpu().numpy()
+    assert np.array_equal(out[:384], p[:384])
+    np.testing.assert_allclose(out, q, rtol=1e-6, atol=1e-7)
+    # FP32 moment updates: a few ulp of the larger term (|g| <~ 5)
+    np.testing.assert_allclose(M1.cpu().numpy()[384:], r1[384:], rtol=1e-6, atol=3e-7)
+    np.testing.assert_allclose(M2.cpu().numpy()[384:], r2[384:], rtol=1e-6, atol=3e-7)
+
+
+@pytest.fixture(scope="module")
+def dipole():
+    # workload 2's polarised dipole beam on its 0.5 deg grid, 3 channels
+    wl = synth.workload(2, n_ant=4, n_src=10, n_time=1, n_freq=3)
+    return wl
+
+
+@pytest.mark.parametrize("bicubic", [False, True])
+def test_beam_samples_match_reference_interpolant(dipole, bicubic):
+    wl = dipole
+    grid = wl.beam[0].astype(np.complex64)  # [n_chan][2][2][n_za][n_az]
+    rng = np.random.Generator(np.random.PCG64(7))
+    n = 4099
+    za, az = synth.hemisphere_points(rng, n)
+    za[:4] = [0.0, math.pi / 2, 0.3, math.pi / 2]
+    az[:4] = [1.0, 0.0, 2 * math.pi - 1e-9, 2 * math.pi - wl.daz / 2]
+    chan = rng.integers(0, wl.n_freq, n).astype(np.int32)
+    nu0, nu1 = 100e6, 200e6
+    y, x = mv.beam_samples(_dev(grid, np.complex64), wl.dza, wl.daz, _dev(za, np.float64), _dev(az, np.float64),
+                           _dev(chan, np.int32), bicubic=bicubic, chan_freq=_dev(wl.freqs, np.float64),
+                           nu_range=(nu0, nu1))
+    y = y.cpu().numpy().astype(np.float64)
+    x = x.cpu().numpy().astype(np.float64)
+    mode = "bicubic" if bicubic else "bilinear"
+    ref = np.zeros((n, 8))
+    g128 = grid.astype(np.complex128)
+    for c in range(wl.n_freq):
+        sel = chan == c
+        for comp in range(4):
+            v = oracle.interp(mode, g128[c, comp // 2, comp % 2], wl.dza, wl.daz, za[sel], az[sel])
+            ref[sel, 2 * comp] = v.real
+            ref[sel, 2 * comp + 1] = v.imag
+    err = np.max(np.abs(y - ref))
+    say(f"beam samples {mode}: max abs {err:.2e}")
+    assert err <= 2e-6
+    np.testing.assert_allclose(x, om.normalise(za, az, wl.freqs[chan], nu0, nu1), rtol=0, atol=2e-7)
+
+
+def test_beam_samples_reject_bad_channel(dipole):
+    wl = dipole
+    grid = _dev(wl.beam[0].astype(np.complex64), np.complex64)
+    z = _dev(np.zeros(3), np.float64)
+    with pytest.raises(mv.MatvisError):
+        mv.beam_samples(grid, wl.dza, wl.daz, z, z, _dev(np.array([0, 3, 1]), np.int32))
+
+
+def _samples(wl, n, seed, nu0=100e6, nu1=200e6):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    za, az = synth.hemisphere_points(rng, n)
+    chan = rng.integers(0, wl.n_freq, n).astype(np.int32)
+    grid = _dev(wl.beam[0].astype(np.complex64), np.complex64)
+    y, x = mv.beam_samples(grid, wl.dza, wl.daz, _dev(za, np.float64), _dev(az, np.float64), _dev(chan, np.int32),
+                           bicubic=True, chan_freq=_dev(wl.freqs, np.float64), nu_range=(nu0, nu1))
+    return x, y
+
+
+def test_training_reduces_loss_and_is_reproducible(dipole, p0):
+    x, y = _samples(dipole, 1 << 15, 11)
+    runs = []
+    for _ in range(2):
+        P = _dev(p0, np.float32)
+        hist = mv.train_surrogate(P, x, y, batch=1024, epochs=6, lr0=2e-3, lr1=5e-4, seed=3)
+        runs.append((P.cpu().numpy(), hist))
+    say(f"loss history {runs[0][1]}")
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    h = runs[0][1]
+    assert np.all(np.isfinite(h)) and h[-1] < 0.2 * h[0]
+    assert np.array_equal(runs[0][0][:384], p0[:384])  # the Fourier matrix is fixed
+
+
+def test_training_steps_match_reference_adam_loop(dipole, p0):
+    # one mini-batch holding every sample: each epoch is one full-batch Adam step
+    n = 256
+    x, y = _samples(dipole, n, 12)
+    P = _dev(p0, np.float32)
+    lr = 1e-3
+    mv.train_surrogate(P, x, y, batch=n, epochs=3, lr0=lr, lr1=lr, seed=0, fp32_math=True)
+    got = P.cpu().numpy().astype(np.float64)
+    xr, yr = x.cpu().numpy().astype(np.float64), y.cpu().numpy().astype(np.float64)
+    p = p0.astype(np.float64)
+    m1, m2 = np.zeros(om.N_PARAMS), np.zeros(om.N_PARAMS)
+    for t in range(1, 4):
+        g, _ = om.loss_grad(p, xr, yr)
+        p = om.adam_step(p, g, m1, m2, t, lr)
+    d_got, d_ref = got - p0, p - p0
+    e = _rel(d_got, d_ref)
+    say(f"3 Adam steps: rel diff of parameter change {e:.2e}")
+    assert e <= 2e-3
+
+
+def _oracle_surrogate_vis(wl, p, nu0, nu1, t, f):
+    R = oracle.rotation(wl.lsts[t], wl.latitude)
+    az, za = oracle.azza(oracle.topocentric(R, oracle.xeq(wl.ra, wl.dec)))
+    x = om.normalise(za, az, wl.freqs[f], nu0, nu1).astype(np.float32).astype(np.float64)
+    out = om.forward(p, x, bf16=True)
+    A = np.zeros((1, wl.n_feed, wl.n_ax, wl.n_src), dtype=np.complex128)
+    for pp in range(wl.n_feed):
+        for k in range(wl.n_ax):
+            c = 2 * pp + k
+            A[0, pp, k] = out[:, 2 * c] + 1j * out[:, 2 * c + 1]
+    return oracle.simulate_given_beam(wl.antpos, wl.freqs[f], wl.lsts[t], wl.ra, wl.dec, wl.flux[f], A,
+                                      wl.latitude)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp32-unfused"])
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_simulate_with_learned_beam_matches_reference(p0, precision, cfg):
+    say(f"simulate surrogate workload{cfg} {precision}")
+    if cfg == 1:
+        wl = synth.workload(1, n_src=777, n_time=2)
+    else:
+        wl = synth.workload(2, n_ant=20, n_src=901, n_time=2, n_freq=3)
+    nu0, nu1 = 100e6, 200e6
+    prec = precision.split("-")[0]
+    cfgc = mv.config_for(wl, prec, beam_mode="surrogate", unfused=precision.endswith("-unfused"))
+    d = mv.device_inputs(wl, prec)
+    with mv.Context(cfgc) as ctx:
+        with pytest.raises(mv.MatvisError):
+            ctx.simulate(**d)  # no network loaded yet
+        ctx.set_surrogate(_dev(p0, np.float32), nu0, nu1)
+        vis = ctx.simulate(**d)
+        ctx.finish()
+        V = vis.cpu().numpy().astype(np.complex128)
+    worst = 0.0
+    for t in range(wl.n_time):
+        for f in range(wl.n_freq):
+            ref = _oracle_surrogate_vis(wl, p0, nu0, nu1, t, f)
+            e = float(metrics.err_cs(V[t, f][None], ref[None]).max())
+            worst = max(worst, e)
+    say(f"  err_CS {worst:.2e}")
+    assert worst <= 1e-4
