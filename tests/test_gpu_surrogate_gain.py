@@ -1,0 +1,146 @@
+"""What the learned beam buys, measured (not assumed).
+
+One network is trained on the GPU (2^20 samples, uniform by solid angle over
+the visible hemisphere and uniform over the 16 channels of the polarised
+dipole beam on its 0.5 deg grid, targets from the bicubic interpolant) and
+then checked for:
+
+* accuracy against its own targets on 10^5 held-out samples;
+* visibilities against the FP64 direct sum with the interpolated beam
+  (err_CS <= 1e-3, the learned beam's tolerance);
+* frequencies between the grid's channels, against the analytic beam: the
+  network is continuous in nu, the grid has only its channels (the nearest
+  channel is the grid's answer without frequency interpolation);
+* storage: the parameter vector against the per-channel grids;
+* the beam step's device time in the simulator, against bicubic
+  interpolation on the same batch (reported, not asserted).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import metrics
+from paper_2312_09763_amd import matvis as mv
+from paper_2312_09763_amd import synth
+
+from helpers import say
+
+pytestmark = pytest.mark.gpu
+
+NU0, NU1 = 100e6, 200e6
+
+
+def _dev(a, dt):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).cuda()
+
+
+def _jones_rows(j):
+    """[2][2][n] complex -> [n][8] (re, im of J00, J01, J10, J11)."""
+    n = j.shape[-1]
+    out = np.zeros((n, 8))
+    for c in range(4):
+        out[:, 2 * c] = j[c // 2, c % 2].real
+        out[:, 2 * c + 1] = j[c // 2, c % 2].imag
+    return out
+
+
+@pytest.fixture(scope="module")
+def trained():
+    wl = synth.workload(2, n_ant=4, n_src=10, n_time=1)  # 16 channels, 100-200 MHz, dipole, 0.5 deg
+    grid = _dev(wl.beam[0].astype(np.complex64), np.complex64)
+    freqs = _dev(wl.freqs, np.float64)
+
+    def samples(n, seed):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        za, az = synth.hemisphere_points(rng, n)
+        chan = rng.integers(0, wl.n_freq, n).astype(np.int32)
+        return mv.beam_samples(grid, wl.dza, wl.daz, _dev(za, np.float64), _dev(az, np.float64),
+                               _dev(chan, np.int32), bicubic=True, chan_freq=freqs, nu_range=(NU0, NU1))
+
+    y, x = samples(1 << 20, 1)
+    yh, xh = samples(100_000, 2)
+    P = _dev(synth.surrogate_init(0, sigma_v=1.0, az_max=4, sigma_w=0.5), np.float32)
+    say("training the learned beam: 2^20 samples, 60 epochs, batch 1024")
+    hist = mv.train_surrogate(P, x, y, batch=1024, epochs=60, lr0=3e-3, lr1=3e-5, seed=1)
+    say(f"  loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    return dict(wl=wl, grid=grid, P=P, xh=xh, yh=yh, hist=hist)
+
+
+def test_heldout_accuracy(trained):
+    out = mv.mlp_forward(trained["P"], trained["xh"])
+    rel = (torch.linalg.norm(out - trained["yh"]) / torch.linalg.norm(trained["yh"])).item()
+    say(f"held-out relative error vs the bicubic interpolant: {rel:.2e}")
+    assert rel <= 1.5e-3
+    assert trained["hist"][-1] < 1e-3 * trained["hist"][0]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_visibilities_against_interpolated_beam(trained, precision):
+    wv = synth.workload(2, n_ant=24, n_src=3000, n_time=2, n_freq=16)
+    cfg = mv.config_for(wv, precision, beam_mode="surrogate")
+    d = mv.device_inputs(wv, precision)
+    with mv.Context(cfg) as ctx:
+        ctx.set_surrogate(trained["P"], NU0, NU1)
+        V = ctx.simulate(**d)
+        ctx.finish()
+        V = V.cpu().numpy().astype(np.complex128)
+    V = V.reshape((-1,) + V.shape[2:])
+    g = wv.beam.astype(np.complex64).astype(np.complex128)
+    ref = oracle.simulate(wv.antpos, wv.freqs, wv.lsts, wv.ra, wv.dec, wv.flux, g, wv.latitude, wv.dza, wv.daz,
+                          wv.interp).reshape(V.shape)
+    ecs, ef = float(metrics.err_cs(V, ref).max()), float(metrics.err_f(V, ref).max())
+    say(f"{precision} + learned beam vs FP64 oracle with the interpolated beam: err_CS {ecs:.2e}, err_F {ef:.2e}")
+    assert ecs <= 1e-3
+
+
+def test_continuous_frequency_beats_nearest_channel(trained):
+    wl = trained["wl"]
+    rng = np.random.Generator(np.random.PCG64(5))
+    n = 20_000
+    za, az = synth.hemisphere_points(rng, n)
+    mids = 0.5 * (wl.freqs[1:] + wl.freqs[:-1])
+    k = rng.integers(0, mids.size, n)
+    nu = mids[k]
+    truth = np.zeros((n, 8))
+    for i, f in enumerate(mids):
+        s = k == i
+        truth[s] = _jones_rows(synth.dipole_beam(za[s], az[s], f))
+    x = np.stack([az / (2 * math.pi), za / (math.pi / 2), (nu - NU0) / (NU1 - NU0)], axis=1)
+    net = mv.mlp_forward(trained["P"], _dev(x, np.float32)).cpu().numpy()
+    near = np.where(np.abs(wl.freqs[k] - nu) <= np.abs(wl.freqs[k + 1] - nu), k, k + 1).astype(np.int32)
+    grid_y, _ = mv.beam_samples(trained["grid"], wl.dza, wl.daz, _dev(za, np.float64), _dev(az, np.float64),
+                                _dev(near, np.int32), bicubic=True)
+    grid_y = grid_y.cpu().numpy()
+    e_net = np.linalg.norm(net - truth) / np.linalg.norm(truth)
+    e_grid = np.linalg.norm(grid_y - truth) / np.linalg.norm(truth)
+    say(f"between channels, vs the analytic beam: learned {e_net:.2e}, nearest-channel grid {e_grid:.2e}")
+    assert e_net < 0.2 * e_grid
+
+
+def test_storage_and_beam_step_time(trained):
+    wl = trained["wl"]
+    n_params = mv.MLP_N_PARAMS
+    grid_bytes = wl.beam[0].astype(np.complex64).nbytes
+    say(f"storage: learned beam {4 * n_params / 1e3:.0f} kB FP32 ({2 * n_params / 1e3:.0f} kB as bf16 weights), "
+        f"16-channel 0.5 deg grid {grid_bytes / 1e6:.1f} MB")
+    assert 4 * n_params * 100 < grid_bytes
+    wv = synth.workload(2, n_ant=64, n_src=20_000, n_time=4, n_freq=16)
+    times = {}
+    for mode in ("bicubic", "surrogate"):
+        cfg = mv.config_for(wv, "bf16x3", beam_mode=mode)
+        d = mv.device_inputs(wv, "bf16x3")
+        with mv.Context(cfg) as ctx:
+            if mode == "surrogate":
+                ctx.set_surrogate(trained["P"], NU0, NU1)
+            ctx.simulate(**d)
+            ctx.finish()
+            ctx.profile(True)
+            ctx.simulate(**d)
+            ctx.finish()
+            times[mode] = ctx.profile_read()["beam"][0]
+    say(f"beam step device time (64 antennas, 20k sources, 4 x 16): bicubic {times['bicubic']:.3f} ms, "
+        f"learned {times['surrogate']:.3f} ms")
+    assert times["surrogate"] > 0 and times["bicubic"] > 0
