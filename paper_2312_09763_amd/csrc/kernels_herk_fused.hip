@@ -484,6 +484,340 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-block items (BF16X3, 129..256 rows): one workgroup owns every row of an
+// (instance, k-split), so each Z element is formed exactly once, and all
+// eight waves both form Z and run MFMA products.  The 136 lower-triangle
+// 16 x 16 tiles of the 256 x 256 product are split as
+//   waves 0-3: the off-diagonal 128 x 128 block, a 64 x 64 wave tile each;
+//   waves 4-7: the two 128-row diagonal triangles, rows {0, 7, 1, 6} or
+//              {2, 5, 3, 4} of one triangle (18 tiles each).
+// Waves w and w + 4 share a SIMD; the first forms Z after its products and
+// the second before them, so matrix and vector work overlap on every SIMD.
+// The column operand carries the rotation here: im += a . (-b_im, b_re).
+// ---------------------------------------------------------------------------
+
+// the column fragment rotated for the imaginary part: (re, im) -> (-im, re) per bf16 pair
+__device__ inline u32x4 bf16_rot_col(u32x4 v) {
+    u32x4 r;
+    for (int q = 0; q < 4; q++) r[q] = __builtin_amdgcn_alignbit(v[q], v[q], 16) ^ 0x00008000u;
+    return r;
+}
+
+__device__ __forceinline__ void mfma_pair(const u32x4 &a, const u32x4 &b, const u32x4 &w, f32x4 &re, f32x4 &im) {
+    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), re, 0, 0,
+                                                 0);
+    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, w), im, 0, 0,
+                                                 0);
+}
+
+// Off-diagonal block: rows 16 (rb + i), columns 16 (cb + j), i, j < 4.
+__device__ __forceinline__ void consume_sq_b3(const unsigned char *buf, int rb, int cb, int l16, int lk,
+                                              f32x4 (&re)[18], f32x4 (&im)[18]) {
+    typedef FL<PB3> L;
+#pragma unroll
+    for (int ks = 0; ks < kKC / 16; ks++) {
+        u32x4 ah[kTI], al[kTI];
+#pragma unroll
+        for (int i = 0; i < kTI; i++) {
+            const unsigned char *p = buf + (16 * (rb + i) + l16) * L::RS + ks * 64 + lk * 16;
+            ah[i] = *(const u32x4 *)p;
+            al[i] = *(const u32x4 *)(p + L::PLANEB);
+        }
+        const unsigned char *pc = buf + (16 * cb + l16) * L::RS + ks * 64 + lk * 16;
+        u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
+#pragma unroll
+        for (int j = 0; j < kTI; j++) {
+            const u32x4 bh = nh, bl = nl;
+            if (j + 1 < kTI) {
+                const unsigned char *p = pc + 16 * (j + 1) * L::RS;
+                nh = *(const u32x4 *)p;
+                nl = *(const u32x4 *)(p + L::PLANEB);
+            }
+            __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this column's products
+            const u32x4 wh = bf16_rot_col(bh), wl = bf16_rot_col(bl);
+            // one product term for every row before the next, so that MFMAs into the
+            // same accumulator are eight issues apart
+#pragma unroll
+            for (int i = 0; i < kTI; i++) mfma_pair(ah[i], bh, wh, re[i * kTI + j], im[i * kTI + j]);
+#pragma unroll
+            for (int i = 0; i < kTI; i++) mfma_pair(ah[i], bl, wl, re[i * kTI + j], im[i * kTI + j]);
+#pragma unroll
+            for (int i = 0; i < kTI; i++) mfma_pair(al[i], bh, wh, re[i * kTI + j], im[i * kTI + j]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// Row sets of the triangle waves and the first accumulator slot of each row
+// (row r of a set holds columns 0..r in consecutive slots).
+template <int S>
+struct TriSet {
+    static constexpr int r[4] = {S == 0 ? 0 : 2, S == 0 ? 7 : 5, S == 0 ? 1 : 3, S == 0 ? 6 : 4};
+    static constexpr int base[4] = {0, r[0] + 1, r[0] + r[1] + 2, r[0] + r[1] + r[2] + 3};
+};
+
+// One 128-row diagonal triangle starting at LDS row o: tiles (r, c), c <= r, r in the set.
+template <int S>
+__device__ __forceinline__ void consume_tri_b3(const unsigned char *buf, int o, int l16, int lk, f32x4 (&re)[18],
+                                               f32x4 (&im)[18]) {
+    typedef FL<PB3> L;
+    typedef TriSet<S> T;
+#pragma unroll
+    for (int ks = 0; ks < kKC / 16; ks++) {
+        u32x4 ah[4], al[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const unsigned char *p = buf + (o + 16 * T::r[k] + l16) * L::RS + ks * 64 + lk * 16;
+            ah[k] = *(const u32x4 *)p;
+            al[k] = *(const u32x4 *)(p + L::PLANEB);
+        }
+        const unsigned char *pc = buf + (o + l16) * L::RS + ks * 64 + lk * 16;
+        u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            const u32x4 bh = nh, bl = nl;
+            if (c + 1 < 8) {
+                const unsigned char *p = pc + 16 * (c + 1) * L::RS;
+                nh = *(const u32x4 *)p;
+                nl = *(const u32x4 *)(p + L::PLANEB);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            const u32x4 wh = bf16_rot_col(bh), wl = bf16_rot_col(bl);
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (T::r[k] >= c) mfma_pair(ah[k], bh, wh, re[T::base[k] + c], im[T::base[k] + c]);
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (T::r[k] >= c) mfma_pair(ah[k], bl, wl, re[T::base[k] + c], im[T::base[k] + c]);
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (T::r[k] >= c) mfma_pair(al[k], bh, wh, re[T::base[k] + c], im[T::base[k] + c]);
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (T::r[k] == c) mfma_pair(al[k], bl, wl, re[T::base[k] + c], im[T::base[k] + c]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <int NC>
+struct SrcEntry {
+    double x, y, z;   // s_hat of the source
+    float2 w[NC];     // its beam values (one unique beam)
+    int64_t m;        // source index, -1 past the split
+};
+
+template <int NF, int NX>
+__global__ void __launch_bounds__(512, 1) k_herk_b3_pair(FusedArgs a) {
+    typedef FL<PB3> L;
+    constexpr int RS = L::RS;
+    constexpr int NC = NF * NX;       // beam components per source
+    constexpr int SPS = kKC / NX;     // sources per stage
+    constexpr int NA = 2 * kST / NF;  // antennas of the 256 rows
+    constexpr int NG = 512 / SPS;     // thread groups (one source per thread)
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * L::BUF];
+    __shared__ AntEntry tab[NA];
+    __shared__ SrcEntry<NC> src[2][SPS];
+
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid / kWave;
+    const bool sq = wave < 4;
+    const int l16 = lane & 15, lk = lane >> 4;
+    const int Np = a.n_rows_pad;  // 256
+    const int total = a.work[a.n_inst];
+    const int per_xcd = a.grid / 8;
+    const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int msl = tid % SPS, g = tid / SPS;
+    // wave roles: square tile origin, or triangle (row offset, row set)
+    const int sq_rb = 8 + 4 * (wave >> 1), sq_cb = 4 * (wave & 1);
+    const int tri_o = ((wave - 4) >> 1) * kST, tri_s = (wave - 4) & 1;
+
+    for (int item = slot_x; item < total; item += a.grid) {
+        int lo = 0, hi = a.n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.work[mid] <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int inst = lo;
+        const int s = item - a.work[inst];
+        const int tslot = inst / a.nfb;
+        const int f = a.f0 + inst % a.nfb;
+        const int64_t M = a.count[tslot];
+        const int64_t ms_per_split = a.ksplit / NX;
+        const int64_t m_begin = (int64_t)s * ms_per_split;
+        const int64_t m_end = m_begin + ms_per_split < M ? m_begin + ms_per_split : M;
+        const int n_stage = (int)((m_end - m_begin + SPS - 1) / SPS);
+        const double *sh = a.s_hat + (int64_t)tslot * 3 * a.ld_src;
+        const float2 *Bm = (const float2 *)a.B + (int64_t)inst * a.n_beam * NC * a.ld_src;
+
+        {
+            const double nu_c = a.freqs[f] / kSpeedOfLight;
+            for (int as = tid; as < NA; as += 512) {
+                AntEntry e;
+                if (as < a.n_ant) {
+                    e.ux = nu_c * a.antc[3 * as];
+                    e.uy = nu_c * a.antc[3 * as + 1];
+                    e.uz = nu_c * a.antc[3 * as + 2];
+                    e.b = a.bidx[as];
+                } else {
+                    e.ux = e.uy = e.uz = 0.0;
+                    e.b = -1;
+                }
+                e.pad = 0;
+                tab[as] = e;
+            }
+        }
+
+        // Source data of a stage (direction, beam, index) is loaded by the first
+        // SPS lanes of wave 0 one stage ahead and kept in LDS (src[stage & 1]),
+        // so no other wave holds it in registers while it runs its products.
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        float2 fw[NC];
+        int64_t fm = -1;
+        const bool fetcher = tid < SPS;
+        auto fetch = [&](int stage) {  // issue the loads (wave 0)
+            const int64_t m = m_begin + (int64_t)stage * SPS + tid;
+            fm = (stage < n_stage && m < m_end) ? m : -1;
+            fx = fy = fz = 0.0;
+            for (int c = 0; c < NC; c++) fw[c] = make_float2(0.f, 0.f);
+            if (fm >= 0) {
+                fx = sh[fm];
+                fy = sh[a.ld_src + fm];
+                fz = sh[2 * a.ld_src + fm];
+                if (a.n_beam == 1)
+                    for (int c = 0; c < NC; c++) fw[c] = Bm[(int64_t)c * a.ld_src + fm];
+            }
+        };
+        auto stash = [&](int stage) {  // publish them (wave 0)
+            SrcEntry<NC> &e = src[stage & 1][tid];
+            e.x = fx;
+            e.y = fy;
+            e.z = fz;
+            for (int c = 0; c < NC; c++) e.w[c] = fw[c];
+            e.m = fm;
+        };
+        // Z rows of every antenna for one stage (as in k_herk_fused's producers)
+        auto produce = [&](unsigned char *buf, int stage) {
+            const SrcEntry<NC> &se = src[stage & 1][msl];
+            const int64_t m = se.m;
+            const bool lv = m >= 0;
+            const double x0 = se.x, x1 = se.y, x2 = se.z;
+            float2 wl[NC];
+            for (int c = 0; c < NC; c++) wl[c] = se.w[c];
+            const bool multi_beam = a.n_beam != 1;
+            int cur_b = multi_beam ? -1 : 0;
+            // not unrolled: the accumulators stay live across this loop
+#pragma unroll 1
+            for (int as = g; as < NA; as += NG) {
+                const AntEntry e = tab[as];
+                if (multi_beam && lv && e.b >= 0 && e.b != cur_b) {
+                    for (int c = 0; c < NC; c++) wl[c] = Bm[((int64_t)e.b * NC + c) * a.ld_src + m];
+                    cur_b = e.b;
+                }
+                const double p = e.ux * x0 + e.uy * x1 + e.uz * x2;
+                const float r = (float)(p - rint(p));
+                const float msk = (lv && e.b >= 0) ? 1.0f : 0.0f;
+                const float sn = msk * __builtin_amdgcn_sinf(-r);
+                const float cs = msk * __builtin_amdgcn_cosf(-r);
+                float2 z[NC];
+                for (int c = 0; c < NC; c++) {
+                    z[c].x = wl[c].x * cs - wl[c].y * sn;
+                    z[c].y = wl[c].x * sn + wl[c].y * cs;
+                }
+#pragma unroll
+                for (int p = 0; p < NF; p++) {
+                    unsigned char *row = buf + (as * NF + p) * RS;
+                    if constexpr (NX == 2) {
+                        uint32_t h0, l0, h1, l1;
+                        split2(z[2 * p].x, z[2 * p].y, h0, l0);
+                        split2(z[2 * p + 1].x, z[2 * p + 1].y, h1, l1);
+                        *(uint2 *)(row + msl * 8) = make_uint2(h0, h1);
+                        *(uint2 *)(row + L::PLANEB + msl * 8) = make_uint2(l0, l1);
+                    } else {
+                        uint32_t h0, l0;
+                        split2(z[p].x, z[p].y, h0, l0);
+                        *(uint32_t *)(row + msl * 4) = h0;
+                        *(uint32_t *)(row + L::PLANEB + msl * 4) = l0;
+                    }
+                }
+            }
+        };
+
+        f32x4 acc_re[18], acc_im[18];
+        for (int t = 0; t < 18; t++)
+            for (int e = 0; e < 4; e++) {
+                acc_re[t][e] = 0.f;
+                acc_im[t][e] = 0.f;
+            }
+        auto consume = [&](const unsigned char *buf) {
+            if (sq)
+                consume_sq_b3(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
+            else if (tri_s == 0)
+                consume_tri_b3<0>(buf, tri_o, l16, lk, acc_re, acc_im);
+            else
+                consume_tri_b3<1>(buf, tri_o, l16, lk, acc_re, acc_im);
+        };
+
+        if (fetcher) {
+            fetch(0);
+            stash(0);
+            fetch(1);
+            stash(1);
+        }
+        __syncthreads();  // antenna table and the first two stages' sources ready
+        produce(lds, 0);
+        __syncthreads();
+        for (int stg = 0; stg < n_stage; stg++) {
+            unsigned char *cur = lds + (stg & 1) * L::BUF;
+            unsigned char *nxt = lds + ((stg + 1) & 1) * L::BUF;
+            const bool more = stg + 1 < n_stage;
+            if (fetcher && stg + 2 < n_stage) fetch(stg + 2);
+            if (sq) consume(cur);
+            if (more) produce(nxt, stg + 1);
+            if (!sq) consume(cur);
+            // src[stg & 1] was last read by the producers of stage stg (one stage ago)
+            if (fetcher && stg + 2 < n_stage) stash(stg + 2);
+            __syncthreads();
+        }
+
+        // the write-out offsets are recomputed here rather than kept live across the item
+        int ld = Np;
+        asm volatile("" : "+v"(ld));
+        float2 *P = (float2 *)a.part + ((int64_t)inst * a.max_splits + s) * (int64_t)Np * Np;
+        if (sq) {
+            const int r0 = 16 * sq_rb + 4 * lk, c0 = 16 * sq_cb + l16;
+#pragma unroll
+            for (int i = 0; i < kTI; i++)
+#pragma unroll
+                for (int j = 0; j < kTI; j++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        P[(int64_t)(r0 + 16 * i + e) * ld + c0 + 16 * j] =
+                            make_float2(acc_re[i * kTI + j][e], acc_im[i * kTI + j][e]);
+        } else {
+            // slot t: row k of the set with base[k] <= t < base[k] + r[k] + 1, column t - base[k]
+            const int rows[4] = {tri_s == 0 ? 0 : 2, tri_s == 0 ? 7 : 5, tri_s == 0 ? 1 : 3, tri_s == 0 ? 6 : 4};
+#pragma unroll
+            for (int t = 0; t < 18; t++) {
+                int k = 0, b = 0;
+                while (t >= b + rows[k] + 1) {
+                    b += rows[k] + 1;
+                    k++;
+                }
+                const int R = rows[k], C = t - b;
+                const int r0 = tri_o + 16 * R + 4 * lk, c0 = tri_o + 16 * C + l16;
+#pragma unroll
+                for (int e = 0; e < 4; e++) P[(int64_t)(r0 + e) * ld + c0] = make_float2(acc_re[t][e], acc_im[t][e]);
+            }
+        }
+    }
+}
+
 template <int PREC, bool DIAG>
 hipError_t launch_kind(const FusedArgs &a, hipStream_t s) {
     if (a.n_feed == 2 && a.n_ax == 2)
@@ -506,8 +840,21 @@ hipError_t launch_prec(const FusedArgs &a, hipStream_t s) {
 
 }  // namespace
 
+hipError_t launch_pair(const FusedArgs &a, hipStream_t s) {
+    if (a.n_feed == 2 && a.n_ax == 2)
+        k_herk_b3_pair<2, 2><<<a.grid, 512, 0, s>>>(a);
+    else if (a.n_feed == 2)
+        k_herk_b3_pair<2, 1><<<a.grid, 512, 0, s>>>(a);
+    else if (a.n_ax == 2)
+        k_herk_b3_pair<1, 2><<<a.grid, 512, 0, s>>>(a);
+    else
+        k_herk_b3_pair<1, 1><<<a.grid, 512, 0, s>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s) {
     if (a.n_inst <= 0) return hipSuccess;
+    if (prec == PB3 && a.n_rows_pad == 2 * kST) return launch_pair(a, s);  // two row blocks: one item per split
     if (prec == P32) return launch_prec<P32>(a, s);
     if (prec == PB3) return launch_prec<PB3>(a, s);
     return hipErrorInvalidValue;
