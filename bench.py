@@ -13,10 +13,13 @@ step of Alg. 2 for the whole batch, replayed from its captured hipGraph.
 metric: src * ant-pair * (t, nu) / s = n_src * n_ant (n_ant + 1) / 2 * n_t * n_nu / T.
 
 Also reported on the same JSON line:
-* roofline: the Z Z^H product kernel, timed live with HIP events around each
-  of its launches (a separate profiled pass over the same steps), algorithmic
-  flops 4 N (N + 1) K per instance (x 3 products on BF16X3) against the MFMA
-  peak of the arithmetic's dtype;
+* roofline: the product kernel, timed live with HIP events around each of its
+  launches (a separate profiled pass over the same steps), against the MFMA
+  peak of the arithmetic's dtype.  Algorithmic flops per instance, x 3
+  products on BF16X3: 4 N (N + 1) K for Z Z^H over the lower triangle (N rows,
+  K = n_ax x visible columns), and half that, 2 N (N + 1) K, on the path that
+  sums the two axes per source first (three 128-antenna feed blocks over the
+  visible sources);
 * cpu_baseline: the FP64 direct-sum oracle on one full (t, nu) instance on the
   host cores, and the error of the GPU result on that instance.
 """
@@ -118,7 +121,9 @@ def main():
     counts = count.cpu().numpy().astype(np.int64)
     N = wl.n_ant * wl.n_feed
     K = wl.n_ax * counts  # per time
-    useful_flops_step = float(np.sum(4.0 * N * (N + 1) * K) * wl.n_freq)
+    path = ctx.product_path
+    per_col = 2.0 if path == "sources" else 4.0
+    useful_flops_step = float(np.sum(per_col * N * (N + 1) * K) * wl.n_freq)
     herk_ms, herk_n = prof["herk"]
     herk_ms_launch = herk_ms / max(herk_n, 1)
     flops_launch = useful_flops_step * PRODUCTS[prec] * args.profile_steps / max(herk_n, 1)
@@ -167,10 +172,12 @@ def main():
                                "100-200 MHz, dipole Jones beam 0.5 deg grid bicubic",
                    "n_ant": wl.n_ant, "n_feed": wl.n_feed, "n_ax": wl.n_ax, "n_src": wl.n_src,
                    "n_time": wl.n_time, "n_freq": wl.n_freq, "precision": prec,
-                   "z_in_hbm": bool(prec == "fp64" or args.unfused)},
+                   "product_path": path},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
-                     "kernel": "k_herk" if (prec == "fp64" or args.unfused) else "k_herk_fused", "launch_ms": herk_ms_launch, "flops_per_launch": flops_launch,
+                     "kernel": {"z_in_hbm": "k_herk", "fused": "k_herk_fused", "fused_rows": "k_herk_b3_pair",
+                                "sources": "k_herk_b3_coh"}[path],
+                     "launch_ms": herk_ms_launch, "flops_per_launch": flops_launch,
                      "useful_tflops": achieved / PRODUCTS[prec]},
         "zform": {"achieved_GBps": z_bytes_step * args.profile_steps / (zform_ms / 1e3) / 1e9 if zform_ms else None,
                   "peak_GBps": HBM_GBS},

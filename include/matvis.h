@@ -246,6 +246,28 @@ typedef enum {
 matvis_status matvis_profile_enable(matvis_ctx *ctx, int32_t enable);
 matvis_status matvis_profile_read(matvis_ctx *ctx, double *ms, int64_t *launches);
 
+/* Which kernel forms the product of Eq. zz for this context (fixed at init):
+ *   MATVIS_PATH_Z_IN_HBM   Z is written to device memory by its own step and
+ *                          V = Z Z^H reads it (FP64, or MATVIS_FLAG_UNFUSED);
+ *   MATVIS_PATH_FUSED      Z formed in LDS per 128-row super-tile pair;
+ *   MATVIS_PATH_FUSED_ROWS Z formed once per (instance, k-split) for all of
+ *                          129..256 rows (BF16X3);
+ *   MATVIS_PATH_SOURCES    2 feeds x 2 axes with one shared beam, 65..128
+ *                          antennas (BF16X3): the axis sum is taken per source
+ *                          first, V[(a,p),(b,q)] = sum_m F_a conj(F_b) C_pq(m),
+ *                          so the product runs over sources, not over the
+ *                          (source, axis) columns of Z -- half the
+ *                          multiply-adds for the same V.
+ * Returns the path, or a negative status for a NULL context. */
+typedef enum {
+    MATVIS_PATH_Z_IN_HBM = 0,
+    MATVIS_PATH_FUSED = 1,
+    MATVIS_PATH_FUSED_ROWS = 2,
+    MATVIS_PATH_SOURCES = 3
+} matvis_product_path;
+
+int32_t matvis_product_path_of(const matvis_ctx *ctx);
+
 /* ---------------------------------------------------------------------------
  * Step entry points: one hot-path step on caller buffers, using the context's
  * geometry and precision.  They exist so each kernel can be checked on its

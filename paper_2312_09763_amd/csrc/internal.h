@@ -144,6 +144,8 @@ struct FusedArgs {
 };
 hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s);
 int herk_fused_occupancy(int prec);
+// product kernel launch_herk_fused picks (a matvis_product_path value, never Z_IN_HBM)
+int fused_path(int prec, int n_feed, int n_ax, int n_beam, int n_ant, int n_rows_pad);
 
 struct ReduceArgs {
     const void *part;

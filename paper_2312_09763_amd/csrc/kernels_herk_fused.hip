@@ -23,6 +23,7 @@
 // Per source the item reads 24 B of direction and 8 n_feed n_ax B of beam;
 // everything else is arithmetic.  Partials go to the same slots as the
 // unfused product and are summed by k_reduce.
+#include "matvis.h"
 #include "internal.h"
 
 namespace mv {
@@ -511,12 +512,21 @@ __device__ __forceinline__ void mfma_pair(const u32x4 &a, const u32x4 &b, const 
                                                  0);
 }
 
+// Staged-row geometry of the two-block kernels: RS bytes per row, hi plane
+// then lo plane of PLANEB bytes each, NKS k-steps of 16 complex per stage.
+template <int RS_, int PLANEB_, int NKS_>
+struct RowGeom {
+    static constexpr int RS = RS_, PLANEB = PLANEB_, NKS = NKS_;
+};
+typedef RowGeom<FL<PB3>::RS, FL<PB3>::PLANEB, kKC / 16> GeomPair;  // 32 complex per stage
+typedef RowGeom<16 * 4 * 2 + 16, 16 * 4, 1> GeomCoh;               // 16 complex per stage
+
 // Off-diagonal block: rows 16 (rb + i), columns 16 (cb + j), i, j < 4.
+template <typename L>
 __device__ __forceinline__ void consume_sq_b3(const unsigned char *buf, int rb, int cb, int l16, int lk,
                                               f32x4 (&re)[18], f32x4 (&im)[18]) {
-    typedef FL<PB3> L;
 #pragma unroll
-    for (int ks = 0; ks < kKC / 16; ks++) {
+    for (int ks = 0; ks < L::NKS; ks++) {
         u32x4 ah[kTI], al[kTI];
 #pragma unroll
         for (int i = 0; i < kTI; i++) {
@@ -558,13 +568,12 @@ struct TriSet {
 };
 
 // One 128-row diagonal triangle starting at LDS row o: tiles (r, c), c <= r, r in the set.
-template <int S>
+template <typename L, int S>
 __device__ __forceinline__ void consume_tri_b3(const unsigned char *buf, int o, int l16, int lk, f32x4 (&re)[18],
                                                f32x4 (&im)[18]) {
-    typedef FL<PB3> L;
     typedef TriSet<S> T;
 #pragma unroll
-    for (int ks = 0; ks < kKC / 16; ks++) {
+    for (int ks = 0; ks < L::NKS; ks++) {
         u32x4 ah[4], al[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
@@ -756,11 +765,11 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_pair(FusedArgs a) {
             }
         auto consume = [&](const unsigned char *buf) {
             if (sq)
-                consume_sq_b3(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
+                consume_sq_b3<GeomPair>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
             else if (tri_s == 0)
-                consume_tri_b3<0>(buf, tri_o, l16, lk, acc_re, acc_im);
+                consume_tri_b3<GeomPair, 0>(buf, tri_o, l16, lk, acc_re, acc_im);
             else
-                consume_tri_b3<1>(buf, tri_o, l16, lk, acc_re, acc_im);
+                consume_tri_b3<GeomPair, 1>(buf, tri_o, l16, lk, acc_re, acc_im);
         };
 
         if (fetcher) {
@@ -818,6 +827,249 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_pair(FusedArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Polarised products with one shared beam (BF16X3, 2 feeds x 2 axes, 65..128
+// antennas).  With Z[(a,p),(m,k)] = B_pk(m) F_a(m) (F the fringe factor of
+// antenna a, B = sqrt(I) A the same for every antenna), the sum over the
+// axis index k can be taken per source first:
+//   V[(a,p),(b,q)] = sum_m F_a(m) conj(F_b(m)) C_pq(m),
+//   C_pq(m) = sum_k B_pk(m) conj(B_qk(m))   (the 2 x 2 coherency seen through the beam).
+// With s0 = sqrt(C_00), s1 = sqrt(C_11), l = C_10 / s0 (|l| <= s1 by
+// Cauchy-Schwarz; l = 0 where s0 = 0, where C_10 = 0 too) and three operand
+// planes over the antennas
+//   P0 = s0 F,  P1 = s1 F,  L = l F,
+// the three independent feed blocks are V^00 = P0 P0^H, V^11 = P1 P1^H (lower
+// triangles) and V^10 = L P0^H (full), and V^01 = (V^10)^H.  The product runs
+// over the sources instead of the (source, axis) columns of Z: half the
+// multiply-adds of Z Z^H for the same result.
+//
+// Layout: 384 staged rows per stage (plane * 128 + antenna), 16 sources per
+// stage.  The waves and tiles are those of k_herk_b3_pair: the square waves
+// take V^10 (rows of L against rows of P0), the triangle waves V^00 and V^11.
+// V^10 elements with a < b are stored, conjugated, at the transposed lower
+// position of the (a, p) x (b, q) matrix, which is where the reduction reads
+// them.
+// ---------------------------------------------------------------------------
+struct CohSrc {
+    double x, y, z;  // s_hat
+    float s0, s1;    // sqrt C00, sqrt C11
+    float lx, ly;    // C10 / sqrt C00
+    int m;           // source index, -1 past the split
+};
+
+__global__ void __launch_bounds__(512, 1) k_herk_b3_coh(FusedArgs a) {
+    typedef GeomCoh L;
+    constexpr int RS = L::RS;
+    constexpr int SPS = 16;                 // sources per stage
+    constexpr int ROWS = 3 * kST;           // planes P0, P1, L of 128 antennas
+    constexpr int BUF = ROWS * RS;
+    // Antennas formed by the square waves (the rest by the triangle waves, which
+    // have more products per stage): the split evens out the two waves of a SIMD.
+    constexpr int SQ_ANT = 96;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
+    __shared__ AntEntry tab[kST];
+    __shared__ CohSrc src[2][SPS];
+
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid / kWave;
+    const bool sq = wave < 4;
+    const int l16 = lane & 15, lk = lane >> 4;
+    const int Np = a.n_rows_pad;
+    const int total = a.work[a.n_inst];
+    const int per_xcd = a.grid / 8;
+    const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int mp = tid % (SPS / 2);  // source pair
+    // this thread's antennas: a0, a0 + 32, ... below a1
+    const int a0 = sq ? tid / (SPS / 2) : SQ_ANT + (tid - 256) / (SPS / 2);
+    const int a1 = sq ? SQ_ANT : kST;
+    // square waves: V^10 rows 16 (sq_rb + i) of L against 16 (sq_cb + j) of P0 (block units)
+    const int sq_r0 = 4 * (wave >> 1), sq_c0 = 4 * (wave & 1);
+    const int sq_rb = 2 * 8 + sq_r0, sq_cb = sq_c0;
+    // triangle waves: plane T (V^TT), row set S
+    const int tri_t = (wave - 4) >> 1, tri_s = (wave - 4) & 1;
+    const int tri_o = tri_t * kST;
+
+    for (int item = slot_x; item < total; item += a.grid) {
+        int lo = 0, hi = a.n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.work[mid] <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int inst = lo;
+        const int s = item - a.work[inst];
+        const int tslot = inst / a.nfb;
+        const int f = a.f0 + inst % a.nfb;
+        const int64_t M = a.count[tslot];
+        const int64_t ms_per_split = a.ksplit / 2;
+        const int64_t m_begin = (int64_t)s * ms_per_split;
+        const int64_t m_end = m_begin + ms_per_split < M ? m_begin + ms_per_split : M;
+        const int n_stage = (int)((m_end - m_begin + SPS - 1) / SPS);
+        const double *sh = a.s_hat + (int64_t)tslot * 3 * a.ld_src;
+        const float2 *Bm = (const float2 *)a.B + (int64_t)inst * 4 * a.ld_src;
+
+        {
+            const double nu_c = a.freqs[f] / kSpeedOfLight;
+            for (int as = tid; as < kST; as += 512) {
+                AntEntry e;
+                if (as < a.n_ant) {
+                    e.ux = nu_c * a.antc[3 * as];
+                    e.uy = nu_c * a.antc[3 * as + 1];
+                    e.uz = nu_c * a.antc[3 * as + 2];
+                    e.b = 0;
+                } else {
+                    e.ux = e.uy = e.uz = 0.0;
+                    e.b = -1;
+                }
+                e.pad = 0;
+                tab[as] = e;
+            }
+        }
+
+        // per-source direction and coherency factors, loaded and formed one stage
+        // ahead by the first SPS lanes of wave 0
+        const bool fetcher = tid < SPS;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        float2 fb[4];
+        int fm = -1;
+        auto fetch = [&](int stage) {
+            const int64_t m = m_begin + (int64_t)stage * SPS + tid;
+            fm = (stage < n_stage && m < m_end) ? (int)m : -1;
+            fx = fy = fz = 0.0;
+            for (int c = 0; c < 4; c++) fb[c] = make_float2(0.f, 0.f);
+            if (fm >= 0) {
+                fx = sh[fm];
+                fy = sh[a.ld_src + fm];
+                fz = sh[2 * a.ld_src + fm];
+                for (int c = 0; c < 4; c++) fb[c] = Bm[(int64_t)c * a.ld_src + fm];
+            }
+        };
+        auto stash = [&](int stage) {
+            // B components c = 2 p + k
+            const float c00 = fb[0].x * fb[0].x + fb[0].y * fb[0].y + fb[1].x * fb[1].x + fb[1].y * fb[1].y;
+            const float c11 = fb[2].x * fb[2].x + fb[2].y * fb[2].y + fb[3].x * fb[3].x + fb[3].y * fb[3].y;
+            // C10 = B10 conj(B00) + B11 conj(B01)
+            const float c10x = fb[2].x * fb[0].x + fb[2].y * fb[0].y + fb[3].x * fb[1].x + fb[3].y * fb[1].y;
+            const float c10y = fb[2].y * fb[0].x - fb[2].x * fb[0].y + fb[3].y * fb[1].x - fb[3].x * fb[1].y;
+            const float s0 = sqrtf(c00);
+            CohSrc &e = src[stage & 1][tid];
+            e.x = fx;
+            e.y = fy;
+            e.z = fz;
+            e.s0 = s0;
+            e.s1 = sqrtf(c11);
+            e.lx = s0 > 0.f ? c10x / s0 : 0.f;
+            e.ly = s0 > 0.f ? c10y / s0 : 0.f;
+            e.m = fm;
+        };
+        // the three planes of this thread's two sources for its antennas
+        auto produce = [&](unsigned char *buf, int stage) {
+            CohSrc w[2];
+            w[0] = src[stage & 1][2 * mp];
+            w[1] = src[stage & 1][2 * mp + 1];
+#pragma unroll 1
+            for (int as = a0; as < a1; as += 256 / (SPS / 2)) {
+                const AntEntry e = tab[as];
+                uint32_t h[3][2], l[3][2];
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    const double p = e.ux * w[q].x + e.uy * w[q].y + e.uz * w[q].z;
+                    const float r = (float)(p - rint(p));
+                    const float msk = (w[q].m >= 0 && e.b >= 0) ? 1.0f : 0.0f;
+                    const float fi = msk * __builtin_amdgcn_sinf(-r);
+                    const float fr = msk * __builtin_amdgcn_cosf(-r);
+                    split2(w[q].s0 * fr, w[q].s0 * fi, h[0][q], l[0][q]);
+                    split2(w[q].s1 * fr, w[q].s1 * fi, h[1][q], l[1][q]);
+                    split2(w[q].lx * fr - w[q].ly * fi, w[q].lx * fi + w[q].ly * fr, h[2][q], l[2][q]);
+                }
+#pragma unroll
+                for (int pl = 0; pl < 3; pl++) {
+                    unsigned char *row = buf + (pl * kST + as) * RS + mp * 8;
+                    *(uint2 *)row = make_uint2(h[pl][0], h[pl][1]);
+                    *(uint2 *)(row + L::PLANEB) = make_uint2(l[pl][0], l[pl][1]);
+                }
+            }
+        };
+
+        f32x4 acc_re[18], acc_im[18];
+        for (int t = 0; t < 18; t++)
+            for (int e = 0; e < 4; e++) {
+                acc_re[t][e] = 0.f;
+                acc_im[t][e] = 0.f;
+            }
+        auto consume = [&](const unsigned char *buf) {
+            if (sq)
+                consume_sq_b3<L>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
+            else if (tri_s == 0)
+                consume_tri_b3<L, 0>(buf, tri_o, l16, lk, acc_re, acc_im);
+            else
+                consume_tri_b3<L, 1>(buf, tri_o, l16, lk, acc_re, acc_im);
+        };
+
+        if (fetcher) {
+            fetch(0);
+            stash(0);
+            fetch(1);
+            stash(1);
+        }
+        __syncthreads();  // antenna table and the first two stages' sources ready
+        produce(lds, 0);
+        __syncthreads();
+        for (int stg = 0; stg < n_stage; stg++) {
+            unsigned char *cur = lds + (stg & 1) * BUF;
+            unsigned char *nxt = lds + ((stg + 1) & 1) * BUF;
+            const bool more = stg + 1 < n_stage;
+            if (fetcher && stg + 2 < n_stage) fetch(stg + 2);
+            if (sq) consume(cur);
+            if (more) produce(nxt, stg + 1);
+            if (!sq) consume(cur);
+            // src[stg & 1] was last read by the producers of stage stg (one stage ago)
+            if (fetcher && stg + 2 < n_stage) stash(stg + 2);
+            __syncthreads();
+        }
+
+        int ld = Np;
+        asm volatile("" : "+v"(ld));
+        float2 *P = (float2 *)a.part + ((int64_t)inst * a.max_splits + s) * (int64_t)Np * Np;
+        if (sq) {
+#pragma unroll
+            for (int i = 0; i < kTI; i++)
+#pragma unroll
+                for (int j = 0; j < kTI; j++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int ra = 16 * (sq_r0 + i) + 4 * lk + e, cb = 16 * (sq_c0 + j) + l16;
+                        const float vr = acc_re[i * kTI + j][e], vi = acc_im[i * kTI + j][e];
+                        if (ra >= a.n_ant || cb >= a.n_ant) continue;
+                        if (ra >= cb)
+                            P[(int64_t)(2 * ra + 1) * ld + 2 * cb] = make_float2(vr, vi);
+                        else
+                            P[(int64_t)(2 * cb) * ld + 2 * ra + 1] = make_float2(vr, -vi);
+                    }
+        } else {
+            const int rows[4] = {tri_s == 0 ? 0 : 2, tri_s == 0 ? 7 : 5, tri_s == 0 ? 1 : 3, tri_s == 0 ? 6 : 4};
+#pragma unroll
+            for (int t = 0; t < 18; t++) {
+                int k = 0, b = 0;
+                while (t >= b + rows[k] + 1) {
+                    b += rows[k] + 1;
+                    k++;
+                }
+                const int R = rows[k], C = t - b;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int ra = 16 * R + 4 * lk + e, cb = 16 * C + l16;
+                    if (ra >= a.n_ant || cb >= a.n_ant) continue;
+                    P[(int64_t)(2 * ra + tri_t) * ld + 2 * cb + tri_t] = make_float2(acc_re[t][e], acc_im[t][e]);
+                }
+            }
+        }
+    }
+}
+
 template <int PREC, bool DIAG>
 hipError_t launch_kind(const FusedArgs &a, hipStream_t s) {
     if (a.n_feed == 2 && a.n_ax == 2)
@@ -852,9 +1104,21 @@ hipError_t launch_pair(const FusedArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+int fused_path(int prec, int n_feed, int n_ax, int n_beam, int n_ant, int n_rows_pad) {
+    if (prec == PB3 && n_feed == 2 && n_ax == 2 && n_beam == 1 && n_ant > kST / 2 && n_ant <= kST)
+        return MATVIS_PATH_SOURCES;  // shared polarised beam: product over sources
+    if (prec == PB3 && n_rows_pad == 2 * kST) return MATVIS_PATH_FUSED_ROWS;  // two row blocks: one item per split
+    return MATVIS_PATH_FUSED;
+}
+
 hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s) {
     if (a.n_inst <= 0) return hipSuccess;
-    if (prec == PB3 && a.n_rows_pad == 2 * kST) return launch_pair(a, s);  // two row blocks: one item per split
+    const int path = fused_path(prec, a.n_feed, a.n_ax, a.n_beam, a.n_ant, a.n_rows_pad);
+    if (path == MATVIS_PATH_SOURCES) {
+        k_herk_b3_coh<<<a.grid, 512, 0, s>>>(a);
+        return hipGetLastError();
+    }
+    if (path == MATVIS_PATH_FUSED_ROWS) return launch_pair(a, s);
     if (prec == P32) return launch_prec<P32>(a, s);
     if (prec == PB3) return launch_prec<PB3>(a, s);
     return hipErrorInvalidValue;

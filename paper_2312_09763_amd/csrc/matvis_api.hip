@@ -566,6 +566,14 @@ matvis_status matvis_set_surrogate(matvis_ctx *c, const float *params, double nu
     return MATVIS_OK;
 }
 
+int32_t matvis_product_path_of(const matvis_ctx *c) {
+    if (!c) return MATVIS_EINVAL;
+    if (!c->fused) return MATVIS_PATH_Z_IN_HBM;
+    const matvis_config &g = c->cfg;
+    return fused_path(g.precision == MATVIS_FP32 ? P32 : g.precision == MATVIS_BF16X3 ? PB3 : P64, g.n_feed, g.n_ax,
+                      g.n_beam, g.n_ant, c->Np);
+}
+
 matvis_status matvis_profile_enable(matvis_ctx *c, int32_t enable) {
     if (!c) return MATVIS_EINVAL;
     c->err.clear();

@@ -30,6 +30,7 @@ STEPS = ("sky", "beam", "zform", "herk", "reduce", "other")
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 BEAM_MODES = {"bilinear": BILINEAR, "bicubic": BICUBIC, "surrogate": SURROGATE}
 MLP_N_PARAMS = 83848  # learned-beam parameter count (include/matvis.h)
+PRODUCT_PATHS = ("z_in_hbm", "fused", "fused_rows", "sources")  # matvis_product_path
 
 
 class MatvisError(RuntimeError):
@@ -102,6 +103,8 @@ def load_library():
     L.matvis_train_surrogate.restype = ctypes.c_int
     L.matvis_set_surrogate.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double]
     L.matvis_set_surrogate.restype = ctypes.c_int
+    L.matvis_product_path_of.argtypes = [_P]
+    L.matvis_product_path_of.restype = ctypes.c_int32
     _lib = L
     return L
 
@@ -181,6 +184,14 @@ class Context:
         if st != OK:
             raise MatvisError(st, "matvis_init failed (details on stderr)")
         self._h = h
+
+    @property
+    def product_path(self) -> str:
+        """Which product kernel this context runs (matvis_product_path_of)."""
+        v = self._L.matvis_product_path_of(self._h)
+        if v < 0:
+            self._check(v)
+        return PRODUCT_PATHS[v]
 
     @property
     def complex_dtype(self):
