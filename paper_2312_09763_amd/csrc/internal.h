@@ -115,12 +115,17 @@ struct HerkArgs {
     int32_t max_splits;      // partial slots per instance
     void *part;              // [n_inst][max_splits][n_rows_pad][n_rows_pad] complex partials
     int32_t *work;           // [n_inst + 1] item prefix
+    int32_t *nsplit;         // [n_inst] k-splits of each instance (built with work)
+    int32_t *kcols;          // [n_inst] columns per k-split of each instance (a multiple of 64)
+    int32_t balance_grid;    // > 0: add k-splits so the items fill whole waves of this many workgroups
     int32_t grid;            // persistent grid size (multiple of 8)
 };
 int herk_super_tile(int prec);
 int herk_occupancy(int prec);  // resident workgroups per CU
 // Item prefix over the batch (k_worklist), then the persistent product kernel.
 // unit != 0 counts k-splits only (the fused product multiplies by its item kinds).
+// Instance i gets nsplit[i] k-splits of kcols[i] <= ksplit columns (the last
+// one partial); without balancing that is ceil(K_i / ksplit) of ksplit.
 hipError_t launch_worklist(int prec, const HerkArgs &a, int unit, hipStream_t s);
 hipError_t launch_herk(int prec, const HerkArgs &a, hipStream_t s);
 
@@ -136,7 +141,7 @@ struct FusedArgs {
     int32_t n_ant, n_feed, n_ax, n_beam;
     int32_t n_rows_pad;
     int32_t f0, nfb, n_inst;
-    int64_t ksplit;          // columns per work item (a multiple of 64)
+    const int32_t *kcols;    // [n_inst] columns per k-split (launch_worklist)
     int32_t max_splits;
     void *part;
     int32_t *work;           // built by launch_worklist
@@ -154,6 +159,7 @@ struct ReduceArgs {
     int64_t fixed_k;
     int32_t n_ax, nfb, n_inst;
     int64_t ksplit;
+    const int32_t *nsplit;   // [n_inst] k-splits per instance, or null: ceil(K / ksplit)
     double *vacc;            // [n_inst][n_rows][n_rows] complex128 running sums (multi-chunk)
     int32_t first, last;     // first chunk: assign; last chunk: write the output
     void *out;               // output base

@@ -61,24 +61,56 @@ struct HD {
 
 __device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
-// Items of instance i: ceil(K_i / ksplit) * n_st.
+// Items of instance i: nsplit_i * n_st, with K_i = n_ax * visible count.
 __device__ inline int64_t inst_k(const int32_t *count, int64_t fixed_k, int n_ax, int nfb, int i) {
     return count ? (int64_t)n_ax * count[i / nfb] : fixed_k;
 }
 
+// k-splits per instance and the item prefix.  nsplit_i starts at
+// ceil(K_i / ksplit); with balancing, extra splits are spread over the
+// instances until the total is a multiple of the persistent grid (capped by
+// max_splits and by 64 columns per split), and each instance's splits are made
+// equal: kcols_i = 64 ceil(K_i / (64 nsplit_i)).  Every workgroup then takes
+// the same number of items of nearly the same size.
 __global__ void __launch_bounds__(1024) k_worklist(const int32_t *count, int64_t fixed_k, int n_ax, int nfb, int n_inst,
-                                                   int64_t ksplit, int n_st, int32_t *work) {
+                                                   int64_t ksplit, int n_st, int balance_grid, int max_splits,
+                                                   int32_t *work, int32_t *nsplit, int32_t *kcols) {
     __shared__ int wtot[1024 / kWave];
-    __shared__ int carry_s;
-    if (threadIdx.x == 0) carry_s = 0;
+    __shared__ int carry_s, total_s;
+    if (threadIdx.x == 0) {
+        carry_s = 0;
+        total_s = 0;
+    }
     __syncthreads();
     const int lane = lane_id(), w = threadIdx.x / kWave;
+    int extra_all = 0;
+    if (balance_grid > 0) {
+        int part = 0;
+        for (int i = threadIdx.x; i < n_inst; i += 1024) {
+            const int64_t k = inst_k(count, fixed_k, n_ax, nfb, i);
+            part += (int)((k + ksplit - 1) / ksplit);
+        }
+        atomicAdd(&total_s, part);
+        __syncthreads();
+        const int t = total_s;
+        extra_all = (t + balance_grid - 1) / balance_grid * balance_grid - t;
+    }
     for (int base = 0; base < n_inst; base += 1024) {
         int i = base + threadIdx.x;
         int v = 0;
         if (i < n_inst) {
-            int64_t k = inst_k(count, fixed_k, n_ax, nfb, i);
-            v = (int)((k + ksplit - 1) / ksplit) * n_st;
+            const int64_t k = inst_k(count, fixed_k, n_ax, nfb, i);
+            int n = (int)((k + ksplit - 1) / ksplit);
+            int64_t kc = ksplit;
+            if (balance_grid > 0 && k > 0) {
+                const int extra = extra_all / n_inst + (i < extra_all % n_inst ? 1 : 0);
+                n = (int)min<int64_t>(min<int64_t>(n + extra, max_splits), (k + 63) / 64);
+                kc = ((k + n - 1) / n + 63) / 64 * 64;
+                n = (int)((k + kc - 1) / kc);
+            }
+            nsplit[i] = n;
+            kcols[i] = (int32_t)kc;
+            v = n * n_st;
         }
         int x = v;
         for (int d = 1; d < kWave; d <<= 1) {
@@ -309,58 +341,78 @@ __global__ void __launch_bounds__(256, 2) k_herk(HerkArgs a) {
     }
 }
 
-// Fixed-order sum of the k-split partials (and of earlier source chunks),
-// Hermitian fill, and the write of the output layout.  One thread per output
-// element; entries above the diagonal are the conjugates of the same sums.
+// Fixed-order sum of the k-split partials, Hermitian fill and the write of the
+// output layout, over 32 x 32 tiles of the lower triangle: partial rows are
+// read coalesced, each lower element is summed once (in FP64, splits in
+// order), and both it and its conjugate mirror above the diagonal are written,
+// the mirror through an LDS transpose.  Earlier source chunks are carried in vacc at the
+// lower positions only.
 template <int PREC>
-__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
+__global__ void __launch_bounds__(256) k_reduce_tiles(ReduceArgs a) {
     typedef typename std::conditional<PREC == P64, double2, float2>::type PartT;
     typedef typename std::conditional<PREC == P64, double2, float2>::type OutT;
+    __shared__ double2 sm[32][33];
     const int inst = blockIdx.y;
     const int N = a.n_rows, Np = a.n_rows_pad, nf = a.n_feed, na = a.n_ant;
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= (int64_t)N * N) return;
-    int r, c;
-    if (a.out_kind == 0) {
-        const int q = (int)(o % nf), p = (int)((o / nf) % nf);
-        const int b = (int)((o / (nf * nf)) % na), aa = (int)(o / ((int64_t)nf * nf * na));
-        r = aa * nf + p;
-        c = b * nf + q;
-    } else {
-        r = (int)(o / N);
-        c = (int)(o % N);
+    // tile (R, C), R >= C, from the linear lower-triangle index
+    int R = 0, t = blockIdx.x;
+    while (t > R) {
+        t -= R + 1;
+        R++;
     }
+    const int C = t;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const int64_t K = a.count ? (int64_t)a.n_ax * a.count[inst / a.nfb] : a.fixed_k;
-    const int ns = (int)((K + a.ksplit - 1) / a.ksplit);
-    const bool lower = r >= c;
-    const int rr = lower ? r : c, cc = lower ? c : r;
-    const PartT *P = (const PartT *)a.part + (int64_t)inst * a.max_splits * Np * Np + (int64_t)rr * Np + cc;
-    double sr = 0.0, si = 0.0;
-    for (int s = 0; s < ns; s++) {
-        const PartT v = P[(int64_t)s * Np * Np];
-        sr += (double)v.x;
-        si += (double)v.y;
-    }
-    if (!lower) si = -si;
-    if (r == c) si = 0.0;
-    double2 *acc = a.vacc ? (double2 *)a.vacc + ((int64_t)inst * N + r) * N + c : nullptr;
-    if (!a.first) {
-        const double2 prev = *acc;
-        sr += prev.x;
-        si += prev.y;
-    }
-    if (!a.last) {
-        *acc = make_double2(sr, si);
-        return;
-    }
-    OutT v;
-    v.x = sr;
-    v.y = si;
+    const int ns = a.nsplit ? a.nsplit[inst] : (int)((K + a.ksplit - 1) / a.ksplit);
+    const PartT *P = (const PartT *)a.part + (int64_t)inst * a.max_splits * Np * Np;
+    double2 *acc = a.vacc ? (double2 *)a.vacc + (int64_t)inst * N * N : nullptr;
+    OutT *out = (OutT *)a.out;
     if (a.out_kind == 0) {
-        const int t = a.bt.t0 + inst / a.bt.nfb, f = a.bt.f0 + inst % a.bt.nfb;
-        ((OutT *)a.out)[((int64_t)t * a.n_freq_total + f) * (int64_t)N * N + o] = v;
-    } else {
-        ((OutT *)a.out)[o] = v;
+        const int tt = a.bt.t0 + inst / a.bt.nfb, f = a.bt.f0 + inst % a.bt.nfb;
+        out += ((int64_t)tt * a.n_freq_total + f) * (int64_t)N * N;
+    }
+    auto out_index = [&](int r, int c) -> int64_t {
+        if (a.out_kind != 0) return (int64_t)r * N + c;
+        const int aa = r / nf, p = r % nf, b = c / nf, q = c % nf;
+        return (((int64_t)aa * na + b) * nf + p) * nf + q;
+    };
+    for (int i = 0; i < 4; i++) {
+        const int rl = ty + 8 * i, r = 32 * R + rl, c = 32 * C + tx;
+        if (r >= N || c >= N || r < c) continue;
+        const PartT *pp = P + (int64_t)r * Np + c;
+        double sr = 0.0, si = 0.0;
+        for (int s = 0; s < ns; s++) {
+            const PartT v = pp[(int64_t)s * Np * Np];
+            sr += (double)v.x;
+            si += (double)v.y;
+        }
+        if (r == c) si = 0.0;
+        if (!a.first) {
+            const double2 prev = acc[(int64_t)r * N + c];
+            sr += prev.x;
+            si += prev.y;
+        }
+        if (!a.last) {
+            acc[(int64_t)r * N + c] = make_double2(sr, si);
+            continue;
+        }
+        sm[rl][tx] = make_double2(sr, si);
+        OutT v;
+        v.x = sr;
+        v.y = si;
+        out[out_index(r, c)] = v;
+    }
+    if (!a.last) return;
+    __syncthreads();
+    // mirror: element (32 C + ty + 8 i, 32 R + tx) = conj(lower (32 R + tx, 32 C + ty + 8 i))
+    for (int i = 0; i < 4; i++) {
+        const int cl = ty + 8 * i, r = 32 * C + cl, c = 32 * R + tx;
+        if (r >= N || c >= N || r >= c) continue;
+        const double2 w = sm[tx][cl];
+        OutT v;
+        v.x = w.x;
+        v.y = -w.y;
+        out[out_index(r, c)] = v;
     }
 }
 
@@ -389,7 +441,8 @@ hipError_t launch_worklist(int prec, const HerkArgs &a, int unit, hipStream_t s)
     const int st = herk_super_tile(prec);
     const int nb = a.n_rows_pad / st;
     const int n_st = unit ? 1 : nb * (nb + 1) / 2;
-    k_worklist<<<1, 1024, 0, s>>>(a.count, a.fixed_k, a.n_ax, a.nfb, a.n_inst, a.ksplit, n_st, a.work);
+    k_worklist<<<1, 1024, 0, s>>>(a.count, a.fixed_k, a.n_ax, a.nfb, a.n_inst, a.ksplit, n_st, a.balance_grid,
+                                  a.max_splits, a.work, a.nsplit, a.kcols);
     return hipGetLastError();
 }
 
@@ -406,11 +459,12 @@ hipError_t launch_herk(int prec, const HerkArgs &a, hipStream_t s) {
 
 hipError_t launch_reduce(int prec, const ReduceArgs &a, hipStream_t s) {
     if (a.n_inst <= 0 || a.n_rows <= 0) return hipSuccess;
-    dim3 g((unsigned)(((int64_t)a.n_rows * a.n_rows + 255) / 256), a.n_inst);
+    const int nt = (a.n_rows + 31) / 32;
+    dim3 g((unsigned)(nt * (nt + 1) / 2), a.n_inst);
     if (prec == P64)
-        k_reduce<P64><<<g, 256, 0, s>>>(a);
+        k_reduce_tiles<P64><<<g, 256, 0, s>>>(a);
     else
-        k_reduce<P32><<<g, 256, 0, s>>>(a);
+        k_reduce_tiles<P32><<<g, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
         const int tslot = inst / a.nfb;
         const int f = a.f0 + inst % a.nfb;
         const int64_t M = a.count[tslot];
-        const int64_t ms_per_split = a.ksplit / NX;
+        const int64_t ms_per_split = a.kcols[inst] / NX;
         const int64_t m_begin = (int64_t)s * ms_per_split;
         const int64_t m_end = m_begin + ms_per_split < M ? m_begin + ms_per_split : M;
         const int n_stage = (int)((m_end - m_begin + SPS - 1) / SPS);
@@ -657,7 +657,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_pair(FusedArgs a) {
         const int tslot = inst / a.nfb;
         const int f = a.f0 + inst % a.nfb;
         const int64_t M = a.count[tslot];
-        const int64_t ms_per_split = a.ksplit / NX;
+        const int64_t ms_per_split = a.kcols[inst] / NX;
         const int64_t m_begin = (int64_t)s * ms_per_split;
         const int64_t m_end = m_begin + ms_per_split < M ? m_begin + ms_per_split : M;
         const int n_stage = (int)((m_end - m_begin + SPS - 1) / SPS);
@@ -904,7 +904,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_coh(FusedArgs a) {
         const int tslot = inst / a.nfb;
         const int f = a.f0 + inst % a.nfb;
         const int64_t M = a.count[tslot];
-        const int64_t ms_per_split = a.ksplit / 2;
+        const int64_t ms_per_split = a.kcols[inst] / 2;
         const int64_t m_begin = (int64_t)s * ms_per_split;
         const int64_t m_end = m_begin + ms_per_split < M ? m_begin + ms_per_split : M;
         const int n_stage = (int)((m_end - m_begin + SPS - 1) / SPS);

@@ -233,12 +233,17 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     // Default k-split per precision: measured on the 128-antenna polarised workload,
     // err_CS grows about as sqrt(ksplit) (FP32: 3.1e-6 at 2048, 1.4e-5 at 8192;
     // BF16X3: 2.5e-6 at 4096, whose split error dominates below that).
-    c->ksplit = cfg->ksplit > 0 ? cfg->ksplit : (prec == P64 ? 8192 : prec == P32 ? 2048 : 4096);
+    // The product over sources (two axes summed per source) accumulates ksplit / 2
+    // sources per item, so it takes twice the BF16X3 k-split for the same rounding.
+    c->fused = prec != P64 && !(cfg->flags & MATVIS_FLAG_UNFUSED);
+    const bool over_sources =
+        c->fused && fused_path(prec, cfg->n_feed, cfg->n_ax, cfg->n_beam, cfg->n_ant, c->Np) == MATVIS_PATH_SOURCES;
+    c->ksplit = cfg->ksplit > 0 ? cfg->ksplit
+                                : (prec == P64 ? 8192 : prec == P32 ? 2048 : over_sources ? 8192 : 4096);
     c->max_splits = (int)((c->ldz + c->ksplit - 1) / c->ksplit);
     // batch: all channels of a few times, enough instances to fill the GPU with
     // work items while keeping Z within a fixed share of device memory
     c->nfb = cfg->batch_freq > 0 ? std::min(cfg->batch_freq, cfg->max_freq) : std::min(cfg->max_freq, 16);
-    c->fused = prec != P64 && !(cfg->flags & MATVIS_FLAG_UNFUSED);
     // per-instance scratch that scales with the batch: Z (unfused only) and the k-split partials
     size_t zinst = (c->fused ? 0 : (size_t)c->Np * c->ldz * cbytes(prec)) +
                    (size_t)c->max_splits * c->Np * c->Np * cbytes(prec);
@@ -283,7 +288,7 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     if (prec == PB3) ALLOC(c->Z_lo, zbytes);
     ALLOC(c->part, cbytes(prec) * B * (size_t)c->max_splits * c->Np * c->Np);
     if (c->chunk < cfg->max_src) ALLOC(c->vacc, sizeof(double) * 2 * B * (size_t)c->N * c->N);
-    ALLOC(c->work, sizeof(int32_t) * (B + 1));
+    ALLOC(c->work, sizeof(int32_t) * (3 * B + 1));  // item prefix, then k-splits and columns per split
     if (cfg->beam_mode == MATVIS_BEAM_SURROGATE) {
         ALLOC(c->sur_P, sizeof(float) * kNParams);
         ALLOC(c->sur_Wb, sizeof(__bf16) * mlp::kWbElems);
@@ -342,6 +347,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
     STEP(c, MATVIS_STEP_SKY, s, launch_rotmats(lsts, n_time, g.latitude_rad, c->rot, s));
     const int64_t n_chunks = std::max<int64_t>(1, (n_src + c->chunk - 1) / c->chunk);
     const int ncomp = g.n_feed * g.n_ax;
+    const int B_cap = c->ntb * c->nfb;  // instances the batch buffers hold
     for (int t0 = 0; t0 < n_time; t0 += c->ntb) {
         const int ntb = std::min(c->ntb, n_time - t0);
         for (int f0 = 0; f0 < n_freq; f0 += c->nfb) {
@@ -396,6 +402,9 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 ha.max_splits = c->max_splits;
                 ha.part = c->part;
                 ha.work = c->work;
+                ha.nsplit = c->work + B_cap + 1;
+                ha.kcols = c->work + 2 * B_cap + 1;
+                ha.balance_grid = c->fused ? c->fused_grid : 0;
                 ha.grid = c->herk_grid;
                 STEP(c, MATVIS_STEP_OTHER, s, launch_worklist(prec, ha, c->fused ? 1 : 0, s));
 
@@ -416,7 +425,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                     fa.f0 = f0;
                     fa.nfb = nfb;
                     fa.n_inst = bt.n_inst;
-                    fa.ksplit = c->ksplit;
+                    fa.kcols = ha.kcols;
                     fa.max_splits = c->max_splits;
                     fa.part = c->part;
                     fa.work = c->work;
@@ -459,6 +468,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 ra.nfb = nfb;
                 ra.n_inst = bt.n_inst;
                 ra.ksplit = c->ksplit;
+                ra.nsplit = ha.nsplit;
                 ra.vacc = c->vacc;
                 ra.first = ch == 0;
                 ra.last = ch == n_chunks - 1;
@@ -692,6 +702,9 @@ matvis_status matvis_step_herk(matvis_ctx *c, const void *Zin, int32_t n_row, in
     ha.max_splits = c->max_splits;
     ha.part = c->part;
     ha.work = c->work;
+    ha.nsplit = c->work + c->ntb * c->nfb + 1;
+    ha.kcols = c->work + 2 * c->ntb * c->nfb + 1;
+    ha.balance_grid = 0;
     ha.grid = c->herk_grid;
     HIPCHK(c, launch_worklist(prec, ha, 0, s));
     HIPCHK(c, launch_herk(prec, ha, s));
