@@ -72,6 +72,14 @@ struct InterpArgs {
     int64_t n_src;
 };
 hipError_t launch_interp(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s);
+// Channel-interleaved copy of the beam grids, T[b][za][az][f][c] (c = feed * n_ax + axis),
+// so one grid point's channels and components are one contiguous run.
+hipError_t launch_grid_interleave(int prec, const void *grid, int n_beam, int n_freq, int ncomp, int n_za, int n_az,
+                                  void *T, hipStream_t s);
+// The beam step on the interleaved grid: a.grid = T with a.n_freq_grid channels;
+// one thread per (visible source, time slot, group of 4 channels of the batch).
+// Needs n_za >= 4.
+hipError_t launch_interp_tf(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s);
 
 // ---- Z formation (kernels_z.hip) -------------------------------------------
 struct ZformArgs {

@@ -31,7 +31,169 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs a, Batch bt) {
     }
 }
 
+// [b][F][P] -> [b][P][F] with F = n_freq * ncomp and P = n_za * n_az, 64 x 64 tiles through LDS.
+template <typename C>
+__global__ void __launch_bounds__(256) k_grid_interleave(const C *__restrict__ in, int F, int64_t P, C *__restrict__ out) {
+    __shared__ C tile[64][65];
+    const int b = blockIdx.z;
+    const int64_t p0 = (int64_t)blockIdx.x * 64;
+    const int f0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const C *src = in + (int64_t)b * F * P;
+    C *dst = out + (int64_t)b * F * P;
+    for (int r = ty; r < 64; r += 4) {
+        const int f = f0 + r;
+        const int64_t p = p0 + tx;
+        if (f < F && p < P) tile[r][tx] = src[(int64_t)f * P + p];
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t p = p0 + r;
+        const int f = f0 + tx;
+        if (f < F && p < P) dst[p * F + f] = tile[tx][r];
+    }
+}
+
+// Row weights of the 4-row za stencil folded onto the grid rows base..base+3:
+// Keys' end rows (3 g0 - 3 g1 + g2 beyond either end) become weights on real rows.
+template <typename R>
+__device__ inline int za_rows_bicubic(int j0, int n_za, R t, R eff[4]) {
+    R wj[4];
+    keys_weights<R>(t, wj);
+    const int base = j0 - 1 < 0 ? 0 : (j0 - 1 > n_za - 4 ? n_za - 4 : j0 - 1);
+    for (int q = 0; q < 4; q++) eff[q] = R(0);
+    for (int dj = 0; dj < 4; dj++) {
+        const int j = j0 - 1 + dj;
+        if (j >= 0 && j < n_za) {
+            eff[j - base] += wj[dj];
+        } else {
+            const int e0 = j < 0 ? 0 : n_za - 1, step = j < 0 ? 1 : -1;
+            eff[e0 - base] += R(3) * wj[dj];
+            eff[e0 + step - base] -= R(3) * wj[dj];
+            eff[e0 + 2 * step - base] += wj[dj];
+        }
+    }
+    return base;
+}
+
+// One thread per (visible source, time slot of the batch, 4 channels of the batch).
+// Taps are read as the run T[b][j][k][f .. f + 3][0 .. ncomp) of 4 ncomp complex values.
+template <typename R, int MODE, int NCOMP>
+__global__ void __launch_bounds__(256) k_interp_tf(InterpArgs a, Batch bt) {
+    typedef typename CplxOf<R>::T C;
+    constexpr int FG = 4;  // channels per thread
+    const int slot = blockIdx.y;
+    const int fg = blockIdx.z * FG;  // first channel of the group, relative to the batch
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t M = a.count ? a.count[slot] : a.fixed_count;
+    if (m >= M || fg >= bt.nfb) return;
+    const int nf = bt.nfb - fg < FG ? bt.nfb - fg : FG;
+    const double za = a.za_az[(int64_t)slot * 2 * a.ld_src + m];
+    const double az = a.za_az[(int64_t)slot * 2 * a.ld_src + a.ld_src + m];
+    const double u = za / a.dza, v = az / a.daz;
+    int j0 = (int)floor(u);
+    j0 = j0 < 0 ? 0 : (j0 > a.n_za - 2 ? a.n_za - 2 : j0);
+    const R t = (R)(u - j0);
+    const double kf = floor(v);
+    const R sfr = (R)(v - kf);
+    int k0 = (int)kf % a.n_az;
+    if (k0 < 0) k0 += a.n_az;
+    constexpr int NT = MODE == BILINEAR ? 2 : 4;
+    R wr[NT], wc[NT];
+    int rbase, kc[NT];
+    if (MODE == BILINEAR) {
+        rbase = j0;
+        wr[0] = R(1) - t;
+        wr[1] = t;
+        wc[0] = R(1) - sfr;
+        wc[1] = sfr;
+        kc[0] = k0;
+        kc[1] = k0 + 1 == a.n_az ? 0 : k0 + 1;
+    } else {
+        rbase = za_rows_bicubic<R>(j0, a.n_za, t, wr);
+        keys_weights<R>(sfr, wc);
+        for (int d = 0; d < 4; d++) {
+            const int k = k0 - 1 + d;
+            kc[d] = k < 0 ? k + a.n_az : (k >= a.n_az ? k - a.n_az : k);
+        }
+    }
+    const int F = a.n_freq_grid * NCOMP;  // interleaved run length of one grid point
+    const int fabs0 = bt.f0 + fg;
+    R sq[FG];
+    for (int q = 0; q < FG; q++) {
+        sq[q] = R(1);
+        if (a.idx && q < nf)
+            sq[q] = (R)sqrt(a.flux[(int64_t)(fabs0 + q) * a.n_src + a.idx[(int64_t)slot * a.ld_src + m]]);
+    }
+    for (int b = 0; b < a.n_beam; b++) {
+        const C *T = (const C *)a.grid + (int64_t)b * a.n_za * a.n_az * F + (int64_t)fabs0 * NCOMP;
+        R ax[FG][NCOMP], ay[FG][NCOMP];
+        for (int q = 0; q < FG; q++)
+            for (int c = 0; c < NCOMP; c++) ax[q][c] = ay[q][c] = R(0);
+        for (int dr = 0; dr < NT; dr++) {
+            const int64_t row = (int64_t)(rbase + dr) * a.n_az;
+            for (int d = 0; d < NT; d++) {
+                const R w = wr[dr] * wc[d];
+                const C *tp = T + (row + kc[d]) * F;
+#pragma unroll
+                for (int q = 0; q < FG; q++) {
+                    if (q >= nf) break;
+#pragma unroll
+                    for (int c = 0; c < NCOMP; c++) {
+                        const C g = tp[q * NCOMP + c];
+                        ax[q][c] += w * g.x;
+                        ay[q][c] += w * g.y;
+                    }
+                }
+            }
+        }
+        for (int q = 0; q < nf; q++) {
+            const int inst = slot * bt.nfb + fg + q;
+            C *out = (C *)a.A + ((int64_t)inst * a.n_beam + b) * NCOMP * a.ld_src + m;
+            for (int c = 0; c < NCOMP; c++) {
+                C r;
+                r.x = sq[q] * ax[q][c];
+                r.y = sq[q] * ay[q][c];
+                out[(int64_t)c * a.ld_src] = r;
+            }
+        }
+    }
+}
+
+template <typename R, int MODE>
+hipError_t launch_tf_mode(const InterpArgs &a, const Batch &bt, hipStream_t s) {
+    const int ncomp = a.n_feed * a.n_ax;
+    dim3 g((unsigned)((a.max_m + 255) / 256), bt.n_inst / bt.nfb, (unsigned)((bt.nfb + 3) / 4));
+    if (ncomp == 4)
+        k_interp_tf<R, MODE, 4><<<g, 256, 0, s>>>(a, bt);
+    else if (ncomp == 2)
+        k_interp_tf<R, MODE, 2><<<g, 256, 0, s>>>(a, bt);
+    else
+        k_interp_tf<R, MODE, 1><<<g, 256, 0, s>>>(a, bt);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_grid_interleave(int prec, const void *grid, int n_beam, int n_freq, int ncomp, int n_za, int n_az,
+                                  void *T, hipStream_t s) {
+    const int F = n_freq * ncomp;
+    const int64_t P = (int64_t)n_za * n_az;
+    dim3 g((unsigned)((P + 63) / 64), (unsigned)((F + 63) / 64), (unsigned)n_beam);
+    if (prec == P64)
+        k_grid_interleave<double2><<<g, 256, 0, s>>>((const double2 *)grid, F, P, (double2 *)T);
+    else
+        k_grid_interleave<float2><<<g, 256, 0, s>>>((const float2 *)grid, F, P, (float2 *)T);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp_tf(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s) {
+    if (bt.n_inst <= 0 || a.max_m <= 0) return hipSuccess;
+    if (a.n_za < 4) return hipErrorInvalidValue;
+    if (prec == P64)
+        return mode == BILINEAR ? launch_tf_mode<double, BILINEAR>(a, bt, s) : launch_tf_mode<double, BICUBIC>(a, bt, s);
+    return mode == BILINEAR ? launch_tf_mode<float, BILINEAR>(a, bt, s) : launch_tf_mode<float, BICUBIC>(a, bt, s);
+}
 
 hipError_t launch_interp(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s) {
     if (bt.n_inst <= 0 || a.max_m <= 0) return hipSuccess;

@@ -73,6 +73,7 @@ struct matvis_ctx {
     // learned beam (beam_mode MATVIS_BEAM_SURROGATE)
     float *sur_P = nullptr;     // FP32 parameters
     __bf16 *sur_Wb = nullptr;   // bf16 W1..W4
+    void *gridT = nullptr;      // channel-interleaved beam grids (grid beam modes, n_za >= 4)
     double sur_nu0 = 0, sur_nu1 = 1;
     bool sur_set = false;
 };
@@ -289,6 +290,9 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     ALLOC(c->part, cbytes(prec) * B * (size_t)c->max_splits * c->Np * c->Np);
     if (c->chunk < cfg->max_src) ALLOC(c->vacc, sizeof(double) * 2 * B * (size_t)c->N * c->N);
     ALLOC(c->work, sizeof(int32_t) * (3 * B + 1));  // item prefix, then k-splits and columns per split
+    if (cfg->beam_mode != MATVIS_BEAM_SURROGATE && cfg->n_za >= 4)
+        ALLOC(c->gridT, cbytes(prec) * (size_t)cfg->n_beam * cfg->max_freq * cfg->n_feed * cfg->n_ax * cfg->n_za *
+                            cfg->n_az);
     if (cfg->beam_mode == MATVIS_BEAM_SURROGATE) {
         ALLOC(c->sur_P, sizeof(float) * kNParams);
         ALLOC(c->sur_Wb, sizeof(__bf16) * mlp::kWbElems);
@@ -344,6 +348,9 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
          launch_prep_inputs(antpos, g.n_ant, beam_idx, g.n_beam, flux, (int64_t)n_freq * n_src, c->antc, c->bidx,
                             c->flags, s));
     STEP(c, MATVIS_STEP_SKY, s, launch_xeq(radec, n_src, c->xeq, g.max_src, s));
+    if (c->gridT)
+        STEP(c, MATVIS_STEP_BEAM, s,
+             launch_grid_interleave(prec, grid, g.n_beam, n_freq, g.n_feed * g.n_ax, g.n_za, g.n_az, c->gridT, s));
     STEP(c, MATVIS_STEP_SKY, s, launch_rotmats(lsts, n_time, g.latitude_rad, c->rot, s));
     const int64_t n_chunks = std::max<int64_t>(1, (n_src + c->chunk - 1) / c->chunk);
     const int ncomp = g.n_feed * g.n_ax;
@@ -361,7 +368,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 if (n_chunks > 1 || f0 == 0) STEP(c, MATVIS_STEP_SKY, s, launch_sky(sb, t0, ntb, c0, ns, s));
 
                 InterpArgs ia{};
-                ia.grid = grid;
+                ia.grid = c->gridT ? c->gridT : grid;
                 ia.n_freq_grid = n_freq;
                 ia.n_beam = g.n_beam;
                 ia.n_feed = g.n_feed;
@@ -385,7 +392,9 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                          mlp::infer_sim(c->sur_P, c->sur_Wb, c->sur_nu0, c->sur_nu1, c->za_az, c->count, ia.idx, flux,
                                         n_src, freqs, c->chunk, ns, c->A, g.n_feed, g.n_ax, bt, s));
                 else
-                    STEP(c, MATVIS_STEP_BEAM, s, launch_interp(prec, g.beam_mode, ia, bt, s));
+                    STEP(c, MATVIS_STEP_BEAM, s,
+                         c->gridT ? launch_interp_tf(prec, g.beam_mode, ia, bt, s)
+                                  : launch_interp(prec, g.beam_mode, ia, bt, s));
 
                 HerkArgs ha{};
                 ha.Z = c->Z;
