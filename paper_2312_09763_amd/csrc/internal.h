@@ -44,10 +44,22 @@ struct SkyBufs {
     double *s_hat;      // [ntb][3][ld_src] (E, N, U)
     double *za_az;      // [ntb][2][ld_src]
     int64_t ld_src;     // row stride of the per-time arrays (>= chunk size)
+    const int32_t *perm; // [n_src] original number of the source at each sky position, or null
 };
 
 // ---- sky (kernels_sky.hip) -------------------------------------------------
 hipError_t launch_xeq(const double *radec, int64_t n_src, double *xeq, int64_t ld, hipStream_t s);
+// Eq. (xeq) with the sources put in sky-cell order (stable): xeq[.][pos] is
+// source perm[pos].  Scratch: xeq_in [3][ld] doubles, cell [ld] int16, hist
+// [sort_hist_entries(ld)] int32.
+struct SortBufs {
+    double *xeq_in;
+    int16_t *cell;
+    int32_t *hist;
+    int32_t *perm;
+};
+hipError_t launch_xeq_sorted(const double *radec, int64_t n_src, int64_t ld, SortBufs sb, double *xeq, hipStream_t s);
+int64_t sort_hist_entries(int64_t max_src);
 hipError_t launch_rotmats(const double *lsts, int32_t n_time, double latitude, double *rot, hipStream_t s);
 hipError_t launch_prep_inputs(const double *antpos, int32_t n_ant, const int32_t *beam_idx, int32_t n_beam,
                               const double *flux, int64_t n_flux, double *antc, int32_t *bidx, int32_t *flags,
@@ -73,9 +85,14 @@ struct InterpArgs {
 };
 hipError_t launch_interp(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s);
 // Channel-interleaved copy of the beam grids, T[b][za][az][f][c] (c = feed * n_ax + axis),
-// so one grid point's channels and components are one contiguous run.
+// so one grid point's channels and components are one contiguous run; runs are
+// (n_freq * ncomp) rounded up to even long, and the buffer needs
+// grid_interleave_elems(...) complex values (4 of slack at the end).
 hipError_t launch_grid_interleave(int prec, const void *grid, int n_beam, int n_freq, int ncomp, int n_za, int n_az,
                                   void *T, hipStream_t s);
+inline int64_t grid_interleave_elems(int n_beam, int n_freq, int ncomp, int n_za, int n_az) {
+    return (int64_t)n_beam * n_za * n_az * ((n_freq * ncomp + 1) & ~1) + 4;
+}
 // The beam step on the interleaved grid: a.grid = T with a.n_freq_grid channels;
 // one thread per (visible source, time slot, group of 4 channels of the batch).
 // Needs n_za >= 4.

@@ -31,16 +31,18 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs a, Batch bt) {
     }
 }
 
-// [b][F][P] -> [b][P][F] with F = n_freq * ncomp and P = n_za * n_az, 64 x 64 tiles through LDS.
+// [b][F][P] -> [b][P][Fs] with F = n_freq * ncomp, P = n_za * n_az and the run
+// stride Fs = F rounded up to even (16-byte aligned runs), 64 x 64 tiles through LDS.
 template <typename C>
 __global__ void __launch_bounds__(256) k_grid_interleave(const C *__restrict__ in, int F, int64_t P, C *__restrict__ out) {
+    const int Fs = (F + 1) & ~1;
     __shared__ C tile[64][65];
     const int b = blockIdx.z;
     const int64_t p0 = (int64_t)blockIdx.x * 64;
     const int f0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const C *src = in + (int64_t)b * F * P;
-    C *dst = out + (int64_t)b * F * P;
+    C *dst = out + (int64_t)b * Fs * P;
     for (int r = ty; r < 64; r += 4) {
         const int f = f0 + r;
         const int64_t p = p0 + tx;
@@ -50,7 +52,7 @@ __global__ void __launch_bounds__(256) k_grid_interleave(const C *__restrict__ i
     for (int r = ty; r < 64; r += 4) {
         const int64_t p = p0 + r;
         const int f = f0 + tx;
-        if (f < F && p < P) dst[p * F + f] = tile[tx][r];
+        if (f < F && p < P) dst[p * Fs + f] = tile[tx][r];
     }
 }
 
@@ -76,15 +78,21 @@ __device__ inline int za_rows_bicubic(int j0, int n_za, R t, R eff[4]) {
     return base;
 }
 
-// One thread per (visible source, time slot of the batch, 4 channels of the batch).
-// Taps are read as the run T[b][j][k][f .. f + 3][0 .. ncomp) of 4 ncomp complex values.
+// A group of LPS lanes per (visible source, time slot of the batch, 4 channels
+// of the batch): a tap's interleaved run T[b][j][k][f .. f + 3][0 .. ncomp) is
+// 4 ncomp complex values, and lane l of the group reads its l-th 16-byte piece
+// (two complex64 or one complex128), so a wave's load covers whole runs of
+// 64 / LPS sources.  Every lane of the group forms the same stencil weights.
 template <typename R, int MODE, int NCOMP>
 __global__ void __launch_bounds__(256) k_interp_tf(InterpArgs a, Batch bt) {
     typedef typename CplxOf<R>::T C;
-    constexpr int FG = 4;  // channels per thread
+    constexpr int FG = 4;                            // channels per group
+    constexpr int PER = 16 / sizeof(C);              // complex values per lane (16 bytes)
+    constexpr int LPS = FG * NCOMP / PER;            // lanes per source
     const int slot = blockIdx.y;
-    const int fg = blockIdx.z * FG;  // first channel of the group, relative to the batch
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int fg = blockIdx.z * FG;                  // first channel of the group, relative to the batch
+    const int l = threadIdx.x % LPS;
+    const int64_t m = (int64_t)blockIdx.x * (blockDim.x / LPS) + threadIdx.x / LPS;
     const int64_t M = a.count ? a.count[slot] : a.fixed_count;
     if (m >= M || fg >= bt.nfb) return;
     const int nf = bt.nfb - fg < FG ? bt.nfb - fg : FG;
@@ -117,45 +125,54 @@ __global__ void __launch_bounds__(256) k_interp_tf(InterpArgs a, Batch bt) {
             kc[d] = k < 0 ? k + a.n_az : (k >= a.n_az ? k - a.n_az : k);
         }
     }
-    const int F = a.n_freq_grid * NCOMP;  // interleaved run length of one grid point
+    const int F = (a.n_freq_grid * NCOMP + 1) & ~1;  // run stride of one grid point (all channels, even)
     const int fabs0 = bt.f0 + fg;
-    R sq[FG];
-    for (int q = 0; q < FG; q++) {
-        sq[q] = R(1);
+    // this lane's elements e = l PER + p of the group's run: channel q = e / NCOMP, component e % NCOMP
+    const int e0 = l * PER;
+    const bool live = e0 / NCOMP < nf;
+    R sq[PER];
+    for (int p = 0; p < PER; p++) {
+        const int q = (e0 + p) / NCOMP;
+        sq[p] = R(1);
         if (a.idx && q < nf)
-            sq[q] = (R)sqrt(a.flux[(int64_t)(fabs0 + q) * a.n_src + a.idx[(int64_t)slot * a.ld_src + m]]);
+            sq[p] = (R)sqrt(a.flux[(int64_t)(fabs0 + q) * a.n_src + a.idx[(int64_t)slot * a.ld_src + m]]);
     }
     for (int b = 0; b < a.n_beam; b++) {
-        const C *T = (const C *)a.grid + (int64_t)b * a.n_za * a.n_az * F + (int64_t)fabs0 * NCOMP;
-        R ax[FG][NCOMP], ay[FG][NCOMP];
-        for (int q = 0; q < FG; q++)
-            for (int c = 0; c < NCOMP; c++) ax[q][c] = ay[q][c] = R(0);
-        for (int dr = 0; dr < NT; dr++) {
-            const int64_t row = (int64_t)(rbase + dr) * a.n_az;
-            for (int d = 0; d < NT; d++) {
-                const R w = wr[dr] * wc[d];
-                const C *tp = T + (row + kc[d]) * F;
+        const C *T = (const C *)a.grid + (int64_t)b * a.n_za * a.n_az * F + (int64_t)fabs0 * NCOMP + e0;
+        R ax[PER], ay[PER];
+        for (int p = 0; p < PER; p++) ax[p] = ay[p] = R(0);
+        if (live) {
 #pragma unroll
-                for (int q = 0; q < FG; q++) {
-                    if (q >= nf) break;
+            for (int dr = 0; dr < NT; dr++) {
+                const int64_t row = (int64_t)(rbase + dr) * a.n_az;
 #pragma unroll
-                    for (int c = 0; c < NCOMP; c++) {
-                        const C g = tp[q * NCOMP + c];
-                        ax[q][c] += w * g.x;
-                        ay[q][c] += w * g.y;
+                for (int d = 0; d < NT; d++) {
+                    const R w = wr[dr] * wc[d];
+                    const C *tp = T + (row + kc[d]) * F;
+                    C g[PER];
+                    if constexpr (PER == 2) {
+                        const float4 q4 = *(const float4 *)tp;
+                        g[0] = make_float2(q4.x, q4.y);
+                        g[PER - 1] = make_float2(q4.z, q4.w);
+                    } else {
+                        g[0] = *tp;
+                    }
+#pragma unroll
+                    for (int p = 0; p < PER; p++) {
+                        ax[p] += w * g[p].x;
+                        ay[p] += w * g[p].y;
                     }
                 }
             }
         }
-        for (int q = 0; q < nf; q++) {
+        for (int p = 0; p < PER; p++) {
+            const int e = e0 + p, q = e / NCOMP, c = e % NCOMP;
+            if (q >= nf) continue;
             const int inst = slot * bt.nfb + fg + q;
-            C *out = (C *)a.A + ((int64_t)inst * a.n_beam + b) * NCOMP * a.ld_src + m;
-            for (int c = 0; c < NCOMP; c++) {
-                C r;
-                r.x = sq[q] * ax[q][c];
-                r.y = sq[q] * ay[q][c];
-                out[(int64_t)c * a.ld_src] = r;
-            }
+            C r;
+            r.x = sq[p] * ax[p];
+            r.y = sq[p] * ay[p];
+            ((C *)a.A)[(((int64_t)inst * a.n_beam + b) * NCOMP + c) * a.ld_src + m] = r;
         }
     }
 }
@@ -163,7 +180,10 @@ __global__ void __launch_bounds__(256) k_interp_tf(InterpArgs a, Batch bt) {
 template <typename R, int MODE>
 hipError_t launch_tf_mode(const InterpArgs &a, const Batch &bt, hipStream_t s) {
     const int ncomp = a.n_feed * a.n_ax;
-    dim3 g((unsigned)((a.max_m + 255) / 256), bt.n_inst / bt.nfb, (unsigned)((bt.nfb + 3) / 4));
+    const int lps = 4 * ncomp * (int)sizeof(typename CplxOf<R>::T) / 16;  // lanes per source
+    const int sources_per_block = 256 / lps;
+    dim3 g((unsigned)((a.max_m + sources_per_block - 1) / sources_per_block), bt.n_inst / bt.nfb,
+           (unsigned)((bt.nfb + 3) / 4));
     if (ncomp == 4)
         k_interp_tf<R, MODE, 4><<<g, 256, 0, s>>>(a, bt);
     else if (ncomp == 2)

@@ -8,6 +8,13 @@
 //             visible source at block offset + wave offset + mbcnt lane rank.
 // The result lists visible sources in ascending index order, so it is
 // deterministic and equal to a sequential filter.
+//
+// Before that, the catalogue is put into a spatially coherent order once per
+// call (a stable counting sort by sky cell: the face of the enclosing cube and
+// a 16 x 16 Morton cell on it), so that consecutive visible sources -- and the
+// threads that interpolate the beam for them -- fall on nearby grid points.
+// The sky arrays then follow that order; the index lists hold the original
+// source numbers, so fluxes are read unchanged.
 #include "internal.h"
 
 namespace mv {
@@ -21,6 +28,116 @@ __device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builti
 // Number of set bits of `mask` below this lane.
 __device__ inline int rank_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+constexpr int kCells = 6 * 256;  // cube faces x 16 x 16 Morton cells
+
+__device__ inline int spread4(int v) {  // 4 bits -> even bit positions
+    v = (v | (v << 2)) & 0x33;
+    v = (v | (v << 1)) & 0x55;
+    return v;
+}
+
+__device__ inline int sky_cell(double x, double y, double z) {
+    const double ax = fabs(x), ay = fabs(y), az = fabs(z);
+    int face;
+    double u, v, m;
+    if (ax >= ay && ax >= az) {
+        face = x >= 0 ? 0 : 1, u = y, v = z, m = ax;
+    } else if (ay >= az) {
+        face = y >= 0 ? 2 : 3, u = x, v = z, m = ay;
+    } else {
+        face = z >= 0 ? 4 : 5, u = x, v = y, m = az;
+    }
+    int iu = (int)((u / m + 1.0) * 8.0), iv = (int)((v / m + 1.0) * 8.0);
+    iu = iu < 0 ? 0 : (iu > 15 ? 15 : iu);
+    iv = iv < 0 ? 0 : (iv > 15 ? 15 : iv);
+    return face * 256 + (spread4(iu) | (spread4(iv) << 1));
+}
+
+// Eq. (xeq) in input order, each source's sky cell, and per-block cell counts.
+__global__ void __launch_bounds__(kSkyBlock) k_xeq_cells(const double *__restrict__ radec, int64_t n,
+                                                         double *__restrict__ xeq_in, int64_t ld,
+                                                         int16_t *__restrict__ cell, int32_t *__restrict__ hist) {
+    __shared__ int h[kCells];
+    for (int c = threadIdx.x; c < kCells; c += kSkyBlock) h[c] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kSkyBlock + threadIdx.x;
+    if (i < n) {
+        double sr, cr, sd, cd;
+        sincos(radec[i], &sr, &cr);
+        sincos(radec[n + i], &sd, &cd);
+        const double x = cr * cd, y = sr * cd, z = sd;
+        xeq_in[i] = x;
+        xeq_in[ld + i] = y;
+        xeq_in[2 * ld + i] = z;
+        const int c = sky_cell(x, y, z);
+        cell[i] = (int16_t)c;
+        atomicAdd(&h[c], 1);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < kCells; c += kSkyBlock) hist[(int64_t)blockIdx.x * kCells + c] = h[c];
+}
+
+// hist[b][c] -> first position of block b's cell-c sources in the cell-major order.
+__global__ void __launch_bounds__(1024) k_cell_offsets(int32_t *__restrict__ hist, int nblk) {
+    __shared__ int tot[kCells];
+    __shared__ int wsum[1024 / kWave];
+    for (int c = threadIdx.x; c < kCells; c += 1024) {
+        int run = 0;
+        for (int b = 0; b < nblk; b++) {
+            const int v = hist[(int64_t)b * kCells + c];
+            hist[(int64_t)b * kCells + c] = run;
+            run += v;
+        }
+        tot[c] = run;
+    }
+    __syncthreads();
+    // exclusive scan of the cell totals (kCells <= 2 x 1024)
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    int carry = 0;
+    for (int base = 0; base < kCells; base += 1024) {
+        const int c = base + threadIdx.x;
+        const int v = c < kCells ? tot[c] : 0;
+        int x = v;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int y = __shfl_up(x, d, kWave);
+            if (lane >= d) x += y;
+        }
+        if (lane == kWave - 1) wsum[w] = x;
+        __syncthreads();
+        int woff = 0;
+        for (int q = 0; q < w; q++) woff += wsum[q];
+        const int excl = carry + woff + x - v;
+        int block_total = 0;
+        for (int q = 0; q < 1024 / kWave; q++) block_total += wsum[q];
+        __syncthreads();
+        if (c < kCells) tot[c] = excl;
+        carry += block_total;
+        __syncthreads();
+    }
+    for (int c = threadIdx.x; c < kCells; c += 1024)
+        for (int b = 0; b < nblk; b++) hist[(int64_t)b * kCells + c] += tot[c];
+}
+
+// Stable scatter into cell order: rank among earlier sources of the same cell in the block.
+__global__ void __launch_bounds__(kSkyBlock) k_cell_scatter(const double *__restrict__ xeq_in, int64_t n, int64_t ld,
+                                                            const int16_t *__restrict__ cell,
+                                                            const int32_t *__restrict__ hist, double *__restrict__ xeq,
+                                                            int32_t *__restrict__ perm) {
+    __shared__ int16_t kc[kSkyBlock];
+    const int64_t i = (int64_t)blockIdx.x * kSkyBlock + threadIdx.x;
+    const int c = i < n ? cell[i] : -1;
+    kc[threadIdx.x] = (int16_t)c;
+    __syncthreads();
+    if (i >= n) return;
+    int rank = 0;
+    for (int j = 0; j < (int)threadIdx.x; j++) rank += kc[j] == c;
+    const int64_t pos = hist[(int64_t)blockIdx.x * kCells + c] + rank;
+    xeq[pos] = xeq_in[i];
+    xeq[ld + pos] = xeq_in[ld + i];
+    xeq[2 * ld + pos] = xeq_in[2 * ld + i];
+    perm[pos] = (int32_t)i;
 }
 
 __global__ void k_xeq(const double *__restrict__ radec, int64_t n, double *__restrict__ xeq, int64_t ld) {
@@ -189,7 +306,7 @@ __global__ void __launch_bounds__(kSkyBlock) k_sky_scatter(SkyBufs b, int t0, in
     for (int i = 0; i < w; i++) woff += wsum[i];
     if (vis) {
         int64_t o = b.blk_off[(int64_t)ts * nblk + blockIdx.x] + woff + rank_below(m);
-        b.idx[ts * ld + o] = (int32_t)(c0 + j);
+        b.idx[ts * ld + o] = b.perm ? b.perm[c0 + j] : (int32_t)(c0 + j);
         double *sh = b.s_hat + (int64_t)ts * 3 * ld;
         sh[o] = e;
         sh[ld + o] = nn;
@@ -211,6 +328,21 @@ hipError_t launch_xeq(const double *radec, int64_t n_src, double *xeq, int64_t l
     k_xeq<<<(unsigned)((n_src + 255) / 256), 256, 0, s>>>(radec, n_src, xeq, ld);
     return hipGetLastError();
 }
+
+hipError_t launch_xeq_sorted(const double *radec, int64_t n_src, int64_t ld, SortBufs sb, double *xeq, hipStream_t s) {
+    if (n_src <= 0) return hipSuccess;
+    const int nblk = (int)((n_src + kSkyBlock - 1) / kSkyBlock);
+    k_xeq_cells<<<nblk, kSkyBlock, 0, s>>>(radec, n_src, sb.xeq_in, ld, sb.cell, sb.hist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_cell_offsets<<<1, 1024, 0, s>>>(sb.hist, nblk);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_cell_scatter<<<nblk, kSkyBlock, 0, s>>>(sb.xeq_in, n_src, ld, sb.cell, sb.hist, xeq, sb.perm);
+    return hipGetLastError();
+}
+
+int64_t sort_hist_entries(int64_t max_src) { return ((max_src + kSkyBlock - 1) / kSkyBlock) * kCells; }
 
 hipError_t launch_rotmats(const double *lsts, int32_t n_time, double latitude, double *rot, hipStream_t s) {
     if (n_time <= 0) return hipSuccess;

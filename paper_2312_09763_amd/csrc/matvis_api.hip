@@ -53,6 +53,10 @@ struct matvis_ctx {
 
     // device scratch
     double *xeq = nullptr, *rot = nullptr, *antc = nullptr, *s_hat = nullptr, *za_az = nullptr, *vacc = nullptr;
+    double *xeq_in = nullptr;      // Eq. (xeq) in input order (before the sky-cell sort)
+    int16_t *cell = nullptr;       // sky cell of each source
+    int32_t *cell_hist = nullptr;  // per-block cell counts, then positions
+    int32_t *perm = nullptr;       // source number at each sorted position
     int32_t *bidx = nullptr, *flags = nullptr, *blk_count = nullptr, *blk_off = nullptr, *count = nullptr,
             *idx = nullptr, *work = nullptr;
     void *A = nullptr, *Z = nullptr, *Z_lo = nullptr, *part = nullptr;
@@ -273,6 +277,10 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
         }                                              \
     } while (0)
     ALLOC(c->xeq, sizeof(double) * 3 * cfg->max_src);
+    ALLOC(c->xeq_in, sizeof(double) * 3 * cfg->max_src);
+    ALLOC(c->cell, sizeof(int16_t) * cfg->max_src);
+    ALLOC(c->cell_hist, sizeof(int32_t) * sort_hist_entries(cfg->max_src));
+    ALLOC(c->perm, sizeof(int32_t) * cfg->max_src);
     ALLOC(c->rot, sizeof(double) * 9 * cfg->max_time);
     ALLOC(c->antc, sizeof(double) * 3 * cfg->n_ant);
     ALLOC(c->bidx, sizeof(int32_t) * cfg->n_ant);
@@ -291,8 +299,8 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     if (c->chunk < cfg->max_src) ALLOC(c->vacc, sizeof(double) * 2 * B * (size_t)c->N * c->N);
     ALLOC(c->work, sizeof(int32_t) * (3 * B + 1));  // item prefix, then k-splits and columns per split
     if (cfg->beam_mode != MATVIS_BEAM_SURROGATE && cfg->n_za >= 4)
-        ALLOC(c->gridT, cbytes(prec) * (size_t)cfg->n_beam * cfg->max_freq * cfg->n_feed * cfg->n_ax * cfg->n_za *
-                            cfg->n_az);
+        ALLOC(c->gridT, cbytes(prec) * (size_t)grid_interleave_elems(cfg->n_beam, cfg->max_freq,
+                                                                     cfg->n_feed * cfg->n_ax, cfg->n_za, cfg->n_az));
     if (cfg->beam_mode == MATVIS_BEAM_SURROGATE) {
         ALLOC(c->sur_P, sizeof(float) * kNParams);
         ALLOC(c->sur_Wb, sizeof(__bf16) * mlp::kWbElems);
@@ -347,7 +355,8 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
     STEP(c, MATVIS_STEP_OTHER, s,
          launch_prep_inputs(antpos, g.n_ant, beam_idx, g.n_beam, flux, (int64_t)n_freq * n_src, c->antc, c->bidx,
                             c->flags, s));
-    STEP(c, MATVIS_STEP_SKY, s, launch_xeq(radec, n_src, c->xeq, g.max_src, s));
+    STEP(c, MATVIS_STEP_SKY, s,
+         launch_xeq_sorted(radec, n_src, g.max_src, SortBufs{c->xeq_in, c->cell, c->cell_hist, c->perm}, c->xeq, s));
     if (c->gridT)
         STEP(c, MATVIS_STEP_BEAM, s,
              launch_grid_interleave(prec, grid, g.n_beam, n_freq, g.n_feed * g.n_ax, g.n_za, g.n_az, c->gridT, s));
@@ -363,8 +372,8 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
             for (int64_t ch = 0; ch < n_chunks; ch++) {
                 const int64_t c0 = ch * c->chunk;
                 const int64_t ns = std::min(c->chunk, n_src - c0);
-                SkyBufs sb{c->xeq, g.max_src, c->rot, c->blk_count, c->blk_off, c->count, c->idx, c->s_hat, c->za_az,
-                           c->chunk};
+                SkyBufs sb{c->xeq,   g.max_src, c->rot,   c->blk_count, c->blk_off, c->count,
+                           c->idx,   c->s_hat,  c->za_az, c->chunk,     c->perm};
                 if (n_chunks > 1 || f0 == 0) STEP(c, MATVIS_STEP_SKY, s, launch_sky(sb, t0, ntb, c0, ns, s));
 
                 InterpArgs ia{};
