@@ -46,6 +46,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(path: str):
+    """HBM bytes per launch of the product kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or None when no
+    summary exists for this path or the kernel source changed since it was taken."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", {"sources": "herk_b3_coh_workload2.json"}.get(path, "none.json"))
+    if not os.path.exists(f):
+        return None
+    rec = json.load(open(f))
+    src = os.path.join(ROOT, rec["kernel_source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +137,7 @@ def main():
     N = wl.n_ant * wl.n_feed
     K = wl.n_ax * counts  # per time
     path = ctx.product_path
+    traffic = measured_traffic(path)
     per_col = 2.0 if path == "sources" else 4.0
     useful_flops_step = float(np.sum(per_col * N * (N + 1) * K) * wl.n_freq)
     herk_ms, herk_n = prof["herk"]
@@ -174,7 +190,7 @@ def main():
                    "n_time": wl.n_time, "n_freq": wl.n_freq, "precision": prec,
                    "product_path": path},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS[prec], "traffic": traffic,
                      "kernel": {"z_in_hbm": "k_herk", "fused": "k_herk_fused", "fused_rows": "k_herk_b3_pair",
                                 "sources": "k_herk_b3_coh"}[path],
                      "launch_ms": herk_ms_launch, "flops_per_launch": flops_launch,
