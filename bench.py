@@ -21,7 +21,11 @@ Also reported on the same JSON line:
   sums the two axes per source first (three 128-antenna feed blocks over the
   visible sources);
 * cpu_baseline: the FP64 direct-sum oracle on one full (t, nu) instance on the
-  host cores, and the error of the GPU result on that instance.
+  host cores, and the error of the GPU result on that instance;
+* side_by_side: the same workload through the FP64 interpolated path, the FP32
+  path, and BF16X3 with the learned beam in place of interpolation (its
+  weights are a random initialisation: the time does not depend on them; the
+  trained network's accuracy is measured by the tests).
 """
 from __future__ import annotations
 
@@ -73,6 +77,8 @@ def main():
     ap.add_argument("--n-src", type=int, default=None, help="shrink the workload (smoke runs only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--side-steps", type=int, default=2,
+                    help="steps timed for each side-by-side variant (0 = skip them)")
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -149,6 +155,37 @@ def main():
     steps_ms = {k: round(v[0] / args.profile_steps, 4) for k, v in prof.items()}
     log("per-step device ms:", steps_ms)
 
+    # ---- side by side on the same workload: the FP64 interpolated path, FP32, and
+    # BF16X3 with the learned beam (random-init weights: its time does not depend on them)
+    side = {}
+    if args.side_steps > 0:
+        variants = [("fp64", "interpolated", {}), ("fp32", "interpolated", {}),
+                    ("bf16x3", "learned", {"beam_mode": "surrogate"})]
+        for vprec, beam, kw in variants:
+            vcfg = mv.config_for(wl, vprec, **kw)
+            vd = mv.device_inputs(wl, vprec)
+            with mv.Context(vcfg) as vctx:
+                if beam == "learned":
+                    params = torch.from_numpy(synth.surrogate_init(0)).cuda()
+                    vctx.set_surrogate(params, float(wl.freqs.min()), float(wl.freqs.max()))
+                vvis = torch.empty_like(vis, dtype=vctx.complex_dtype)
+                vctx.simulate(**vd, vis=vvis)
+                vctx.finish()
+                torch.cuda.synchronize()
+                v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                v0.record(stream)
+                for _ in range(args.side_steps):
+                    vctx.simulate(**vd, vis=vvis)
+                v1.record(stream)
+                torch.cuda.synchronize()
+                vctx.finish()
+                vms = v0.elapsed_time(v1) / args.side_steps
+                side[f"{vprec}+{beam}"] = {"ms_per_step": vms, "value": units / (vms / 1e3),
+                                           "product_path": vctx.product_path}
+                log(f"side by side {vprec} + {beam} beam: {vms:.2f} ms/step")
+                del vvis
+        side[f"{prec}+interpolated"] = {"ms_per_step": ms_step, "value": value, "product_path": ctx.product_path}
+
     # ---- CPU baseline: the FP64 oracle on one full instance, and the GPU error there
     cpu = None
     err = None
@@ -198,6 +235,7 @@ def main():
         "zform": {"achieved_GBps": z_bytes_step * args.profile_steps / (zform_ms / 1e3) / 1e9 if zform_ms else None,
                   "peak_GBps": HBM_GBS},
         "step_ms": steps_ms,
+        "side_by_side": side,
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
     }
