@@ -1,0 +1,70 @@
+"""The diffuse-sky and batched-uneven workloads against the oracle.
+
+Workload 4 runs at full size (128 polarised antennas, 200 000 sources whose
+post-horizon count swings between about 40 % and 60 % over the day, 16 LSTs x
+16 channels = 256 instances in one call): the GPU result is compared with the
+direct sum on sampled antenna pairs (with the autocorrelations the
+Cauchy-Schwarz error needs) of sampled instances, and checked for exact
+Hermitian symmetry everywhere.  Workload 3 (350 antennas, equal-area pixels
+with a log-normal sky) runs on a coarser pixelisation of the same kind.
+"""
+import numpy as np
+import pytest
+
+from paper_2312_09763_amd import matvis as mv
+from paper_2312_09763_amd import synth
+
+from helpers import sample_pairs, sampled_err_cs, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wl4():
+    return synth.workload(4)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_workload4_batched_uneven_full_size(wl4, precision):
+    import torch
+    wl = wl4
+    say(f"workload4 full size {precision}: {wl.n_src} sources, {wl.n_time} x {wl.n_freq} instances")
+    cfg = mv.config_for(wl, precision)
+    d = mv.device_inputs(wl, precision)
+    with mv.Context(cfg) as ctx:
+        V = ctx.simulate(**d)
+        ctx.finish()
+        _, count, _, _ = ctx.step_sky(d["lsts"], d["src_radec"])
+        counts = count.cpu().numpy() / wl.n_src
+        path = ctx.product_path
+        Vh = V.cpu().numpy()
+    say(f"  path {path}; visible fraction {counts.min():.3f}..{counts.max():.3f}")
+    # uneven instances in one call
+    assert counts.min() < 0.47 and counts.max() > 0.53
+    # exact Hermitian symmetry over every instance
+    assert np.array_equal(Vh, np.conj(np.transpose(Vh, (0, 1, 3, 2, 5, 4))))
+    instances = [(0, 0), (5, 9), (11, 3), (15, 15)]
+    pairs = sample_pairs(wl.n_ant, 40, 3)
+    ecs, ef = sampled_err_cs(Vh.astype(np.complex128), wl, precision, instances, pairs)
+    say(f"  sampled err_CS {ecs:.3e} err_F {ef:.3e} ({len(pairs)} pairs x {len(instances)} instances)")
+    tol = {"fp32": 1e-5, "bf16x3": 1e-5}[precision]
+    assert ecs <= tol and ef <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_workload3_diffuse_sky(precision):
+    # nside 64: 49 152 equal-area pixels with the log-normal sky, 350 antennas
+    wl = synth.workload(3, n_src=49152, n_time=2, n_freq=3)
+    say(f"workload3 {precision}: {wl.n_ant} antennas, {wl.n_src} pixels")
+    cfg = mv.config_for(wl, precision)
+    d = mv.device_inputs(wl, precision)
+    with mv.Context(cfg) as ctx:
+        V = ctx.simulate(**d)
+        ctx.finish()
+        Vh = V.cpu().numpy().astype(np.complex128)
+        say(f"  path {ctx.product_path}")
+    instances = [(0, 0), (1, 2)]
+    pairs = sample_pairs(wl.n_ant, 60, 5)
+    ecs, ef = sampled_err_cs(Vh, wl, precision, instances, pairs)
+    say(f"  sampled err_CS {ecs:.3e} err_F {ef:.3e}")
+    assert ecs <= 1e-5 and ef <= 1e-5
