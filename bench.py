@@ -180,11 +180,25 @@ def main():
                 torch.cuda.synchronize()
                 vctx.finish()
                 vms = v0.elapsed_time(v1) / args.side_steps
-                side[f"{vprec}+{beam}"] = {"ms_per_step": vms, "value": units / (vms / 1e3),
-                                           "product_path": vctx.product_path}
+                # the product kernel's own rate on this path, from one profiled step
+                vctx.profile(True)
+                vctx.simulate(**vd, vis=vvis)
+                vprof = vctx.profile_read()
+                vctx.profile(False)
+                vctx.finish()
+                vpath = vctx.product_path
+                vflops = float(np.sum((2.0 if vpath == "sources" else 4.0) * N * (N + 1) * K) * wl.n_freq) * \
+                    PRODUCTS[vprec]
+                vtf = vflops / (vprof["herk"][0] / 1e3) / 1e12 if vprof["herk"][0] > 0 else None
+                side[f"{vprec}+{beam}"] = {"ms_per_step": vms, "value": units / (vms / 1e3), "product_path": vpath,
+                                           "product_ms_per_step": vprof["herk"][0],
+                                           "product_tflops": vtf,
+                                           "product_frac_of_peak": vtf / PEAK_TFLOPS[vprec] if vtf else None}
                 log(f"side by side {vprec} + {beam} beam: {vms:.2f} ms/step")
                 del vvis
-        side[f"{prec}+interpolated"] = {"ms_per_step": ms_step, "value": value, "product_path": ctx.product_path}
+        side[f"{prec}+interpolated"] = {"ms_per_step": ms_step, "value": value, "product_path": ctx.product_path,
+                                        "product_ms_per_step": herk_ms / args.profile_steps,
+                                        "product_tflops": achieved, "product_frac_of_peak": achieved / PEAK_TFLOPS[prec]}
 
     # ---- CPU baseline: the FP64 oracle on one full instance, and the GPU error there
     cpu = None

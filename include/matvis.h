@@ -160,7 +160,8 @@ void matvis_destroy(matvis_ctx *ctx);
  * ------------------------------------------------------------------------- */
 #define MATVIS_MLP_N_PARAMS 83848
 
-/* out [n][8] = network(x [n][3]).  Allocates a bf16 copy of the weights. */
+/* out [n][8] = network(x [n][3]).  Allocates a bf16 copy of the weights.
+ * params and out must be 16-byte aligned (MATVIS_EINVAL otherwise). */
 matvis_status matvis_mlp_forward(const float *params, const float *x, int64_t n, float *out, void *stream);
 
 /* Mean squared error L = sum (out - y)^2 / (8 n) and its gradient with respect

@@ -7,9 +7,10 @@
 // and accumulate in FP32 (v_mfma_f32_16x16x32_bf16), or stay in FP32
 // (v_mfma_f32_16x16x4f32) in the FP32 check mode.
 //
-// Inference (k_mlp_infer) evaluates the whole network for 64 points per
-// workgroup with the activations kept in LDS (bf16) and the bf16 weights read
-// through L2, so only the inputs and the 8 outputs touch HBM.  In the
+// Inference (k_mlp_infer) is one persistent launch: every workgroup holds
+// the bf16 hidden weights in LDS and each wave runs the whole network on 64
+// points at a time with the activations in registers, so only the inputs and
+// the 8 outputs touch HBM.  In the
 // simulator it replaces beam interpolation: it reads the visible sources'
 // (za, az) and writes B = sqrt(I) J in the layout of the beam step.
 #include <algorithm>
@@ -260,43 +261,95 @@ __global__ void k_beam_samples(const float2 *__restrict__ grid, int n_feed, int 
 }
 
 // ---------------------------------------------------------------- fused inference
-constexpr int kRows = 64;              // points per workgroup
-constexpr int kLdF = kFeat + 8;        // LDS row strides (bf16 elements)
-constexpr int kLdH = kHid + 8;
-constexpr int kLdO = kHid + 4;         // FP32 row stride of the last hidden layer
-static_assert(kRows * kLdO * 4 <= kRows * kLdF * 2, "last hidden layer reuses the feature buffer");
+// The whole network per 64 points in one wave, activations in registers.
+// Layouts (v_mfma_f32_16x16x32_bf16, weights as the A operand, points as B):
+// accumulator tile (h, pt) holds pre-activations of hidden units
+// 16 h + 4 lk + e (e = 0..3) for point 16 pt + l16 in lane 16 lk + l16.  Two
+// tiles (2 kb, 2 kb + 1) after SiLU are the next product's B operand for k
+// block kb as they stand: lane (l16, lk) holds hidden units
+// 32 kb + {4 lk .. 4 lk + 3, 16 + 4 lk .. 16 + 4 lk + 3}, and the LDS image
+// of the next layer's weights permutes its columns the same way, so no
+// activation ever leaves the registers.  The image of W1..W4 (160 KB, bf16,
+// built by pack_weights) is resident in LDS for the whole persistent launch;
+// the head (W5, b5) runs in FP32 on v_mfma_f32_16x16x4f32.
+constexpr int kBlk = 512;                                    // bf16 per 1 KB operand block
+constexpr int kImgW1Blocks = (kHid / 16) * (kFeat / 32);     // 64: block h * 8 + kb
+constexpr int kImgLayerBlocks = (kHid / 16) * (kHid / 32);   // 32 per layer 2..4: block h * 4 + kb
+static_assert((int64_t)(kImgW1Blocks + 3 * kImgLayerBlocks) * kBlk == mlp::kWbElems, "image covers W1..W4");
+constexpr int kIPts = 64;    // points per wave task
+constexpr int kIWaves = 8;   // waves per workgroup (two per SIMD)
 
-// One hidden layer for 64 rows: out = SiLU(in W^T + b), in [64][K] bf16 in LDS,
-// W [128][K] bf16 in global memory; wave w owns output columns 32w..32w+31.
-// out is bf16 (the next product's operand) or FP32 (the head's input), row stride LDO.
-template <int K, int LDI, typename TO, int LDO>
-__device__ inline void mlp_layer(const __bf16 *in, const __bf16 *__restrict__ W, const float *__restrict__ b, TO *out,
-                                 int wave, int l16, int lk) {
-    f32x4 acc[4][2];
-    for (int i = 0; i < 4; i++)
-        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int c0 = wave * 32;
-#pragma unroll
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 bw[2];
-        for (int j = 0; j < 2; j++) bw[j] = *(const bf16x8 *)(W + (int64_t)(c0 + 16 * j + l16) * K + k0 + lk * 8);
-        for (int i = 0; i < 4; i++) {
-            const bf16x8 av = *(const bf16x8 *)(in + (16 * i + l16) * LDI + k0 + lk * 8);
-            for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[j], acc[i][j], 0, 0, 0);
-        }
+// column of W (row 16 h + l16) at element e of lane (l16, lk) in k block kb
+__device__ __host__ inline int image_col(bool first, int kb, int lk, int e) {
+    return first ? 32 * kb + 8 * lk + e : 32 * kb + (e < 4 ? 4 * lk + e : 12 + 4 * lk + e);
+}
+
+__global__ void k_pack_image(const float *__restrict__ P, __bf16 *__restrict__ img) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int)mlp::kWbElems) return;
+    const int blk = i / kBlk, r = i % kBlk, L = r / 8, e = r % 8, l16 = L & 15, lk = L >> 4;
+    int h, kb, K, col;
+    const float *W;
+    if (blk < kImgW1Blocks) {
+        W = P + kOffW1;
+        K = kFeat;
+        h = blk / 8;
+        kb = blk % 8;
+        col = image_col(true, kb, lk, e);
+    } else {
+        const int l = (blk - kImgW1Blocks) / kImgLayerBlocks, b = (blk - kImgW1Blocks) % kImgLayerBlocks;
+        W = P + (l == 0 ? kOffW2 : l == 1 ? kOffW3 : kOffW4);
+        K = kHid;
+        h = b / 4;
+        kb = b % 4;
+        col = image_col(false, kb, lk, e);
     }
-    for (int i = 0; i < 4; i++)
-        for (int j = 0; j < 2; j++)
-            for (int e = 0; e < 4; e++) {
-                const int r = 16 * i + 4 * lk + e, c = c0 + 16 * j + l16;
-                out[r * LDO + c] = (TO)silu(acc[i][j][e] + b[c]);
+    img[i] = (__bf16)W[(int64_t)(16 * h + l16) * K + col];
+}
+
+// SiLU with the hardware reciprocal (one rounding more than the division)
+__device__ inline float silu_fast(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+__device__ inline bf16x8 lds_block(const __bf16 *img, int blk, int lane) {
+    return *(const bf16x8 *)(img + blk * kBlk + lane * 8);
+}
+
+// Hidden layer 2..4 (image blocks from blk0): out = SiLU(W in + b) as B operands.
+__device__ inline void hidden_layer(const __bf16 *img, int blk0, const float *__restrict__ b, const bf16x8 (&in)[4][4],
+                                    bf16x8 (&out)[4][4], int lane, int lk) {
+#pragma unroll
+    for (int hh = 0; hh < 2; hh++) {
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const f32x4 bv = *(const f32x4 *)(b + 16 * (4 * hh + i) + 4 * lk);
+#pragma unroll
+            for (int pt = 0; pt < 4; pt++) acc[i][pt] = bv;
+        }
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const bf16x8 w = lds_block(img, blk0 + (4 * hh + i) * 4 + kb, lane);
+#pragma unroll
+                for (int pt = 0; pt < 4; pt++)
+                    acc[i][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, in[kb][pt], acc[i][pt], 0, 0, 0);
             }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int pt = 0; pt < 4; pt++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) out[2 * hh + i / 2][pt][4 * (i % 2) + e] = (__bf16)silu_fast(acc[i][pt][e]);
+    }
 }
 
 struct InferArgs {
     const float *P;        // FP32 parameters (Fourier matrix, biases, output layer)
-    const __bf16 *Wb;      // bf16 W1 [128][256], W2..W4 [128][128], contiguous
+    const __bf16 *Wb;      // LDS image of the bf16 W1..W4 (pack_weights)
     double nu0, nu1;
+    int64_t n_tasks;       // 64-point tasks
+    int64_t tiles;         // simulator mode: tasks per instance
     // plain mode: x [n][3] normalised inputs, out [n][8]
     const float *x;
     float *out;
@@ -315,85 +368,175 @@ struct InferArgs {
 };
 
 template <bool SIM>
-__global__ void __launch_bounds__(256) k_mlp_infer(InferArgs a) {
-    __shared__ __attribute__((aligned(16))) __bf16 feat[kRows * kLdF];
-    __shared__ __attribute__((aligned(16))) __bf16 h0[kRows * kLdH];
-    __shared__ __attribute__((aligned(16))) __bf16 h1[kRows * kLdH];
-    __shared__ float xin[kRows][3];
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+__global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
+    __shared__ __attribute__((aligned(16))) __bf16 img[mlp::kWbElems];
+    const int tid = threadIdx.x, lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int l16 = lane & 15, lk = lane >> 4;
-    const int64_t r0 = (int64_t)blockIdx.x * kRows;
-    int64_t nrow;
-    int inst = 0, slot = 0, f = 0;
-    if (SIM) {
-        inst = blockIdx.y;
-        slot = inst / a.bt.nfb;
-        f = a.bt.f0 + inst % a.bt.nfb;
-        nrow = a.count[slot];
-    } else {
-        nrow = a.n;
-    }
-    if (r0 >= nrow) return;
-    if (tid < kRows) {
-        const int64_t m = r0 + tid;
-        float u = 0.f, v = 0.f, w = 0.f;
-        if (m < nrow) {
-            if (SIM) {
-                const double za = a.za_az[(int64_t)slot * 2 * a.ld_src + m];
-                const double az = a.za_az[(int64_t)slot * 2 * a.ld_src + a.ld_src + m];
-                u = (float)(az / (2.0 * M_PI));
-                v = (float)(za / (0.5 * M_PI));
-                w = (float)((a.freqs[f] - a.nu0) / (a.nu1 - a.nu0));
-            } else {
-                u = a.x[3 * m];
-                v = a.x[3 * m + 1];
-                w = a.x[3 * m + 2];
+    for (int i = tid; i < (int)(mlp::kWbElems / 8); i += kIWaves * kWave)
+        ((u32x4 *)img)[i] = ((const u32x4 *)a.Wb)[i];
+    __syncthreads();
+    const int64_t nw = (int64_t)gridDim.x * kIWaves;
+#pragma unroll 1
+    for (int64_t t = (int64_t)blockIdx.x * kIWaves + wave; t < a.n_tasks; t += nw) {
+        int inst = 0, slot = 0, f = 0;
+        int64_t m0, nrow;
+        if (SIM) {
+            inst = (int)(t / a.tiles);
+            m0 = (t % a.tiles) * kIPts;
+            slot = inst / a.bt.nfb;
+            f = a.bt.f0 + inst % a.bt.nfb;
+            nrow = a.count[slot];
+            if (m0 >= nrow) continue;
+        } else {
+            m0 = t * kIPts;
+            nrow = a.n;
+        }
+        // Parameters are re-read per task through L1: hoisted out of the loop
+        // they would pin ~160 registers, so the pointer is made opaque here.
+        const float *P = a.P;
+        asm volatile("" : "+s"(P));
+        // inputs of this lane's four points (16 pt + l16)
+        float xu[4], xv[4], xw[4];
+#pragma unroll
+        for (int pt = 0; pt < 4; pt++) {
+            const int64_t m = m0 + 16 * pt + l16;
+            xu[pt] = xv[pt] = xw[pt] = 0.f;
+            if (m < nrow) {
+                if (SIM) {
+                    const double za = a.za_az[(int64_t)slot * 2 * a.ld_src + m];
+                    const double az = a.za_az[(int64_t)slot * 2 * a.ld_src + a.ld_src + m];
+                    xu[pt] = (float)(az / (2.0 * M_PI));
+                    xv[pt] = (float)(za / (0.5 * M_PI));
+                    xw[pt] = (float)((a.freqs[f] - a.nu0) / (a.nu1 - a.nu0));
+                } else {
+                    xu[pt] = a.x[3 * m];
+                    xv[pt] = a.x[3 * m + 1];
+                    xw[pt] = a.x[3 * m + 2];
+                }
             }
         }
-        xin[tid][0] = u;
-        xin[tid][1] = v;
-        xin[tid][2] = w;
-    }
-    __syncthreads();
-    for (int e = tid; e < kRows * kFreq; e += 256) {
-        const int r = e / kFreq, j = e % kFreq;
-        const float *b = a.P + kOffBff + 3 * j;
-        float s, c;
-        sincos_rev(b[0] * xin[r][0] + b[1] * xin[r][1] + b[2] * xin[r][2], s, c);
-        feat[r * kLdF + j] = (__bf16)s;
-        feat[r * kLdF + kFreq + j] = (__bf16)c;
-    }
-    __syncthreads();
-    const __bf16 *W1 = a.Wb, *W2 = W1 + kHid * kFeat, *W3 = W2 + kHid * kHid, *W4 = W3 + kHid * kHid;
-    mlp_layer<kFeat, kLdF, __bf16, kLdH>(feat, W1, a.P + kOffB1, h0, wave, l16, lk);
-    __syncthreads();
-    mlp_layer<kHid, kLdH, __bf16, kLdH>(h0, W2, a.P + kOffB2, h1, wave, l16, lk);
-    __syncthreads();
-    mlp_layer<kHid, kLdH, __bf16, kLdH>(h1, W3, a.P + kOffB3, h0, wave, l16, lk);
-    __syncthreads();
-    float *h4 = (float *)feat;  // the features are dead after the first layer
-    mlp_layer<kHid, kLdH, float, kLdO>(h0, W4, a.P + kOffB4, h4, wave, l16, lk);
-    __syncthreads();
-    // output layer in FP32: two (row, output) pairs per thread
-    for (int e = tid; e < kRows * kOut; e += 256) {
-        const int r = e / kOut, o = e % kOut;
-        const float *w5 = a.P + kOffW5 + o * kHid;
-        float s = a.P[kOffB5 + o];
-        for (int k = 0; k < kHid; k++) s += h4[r * kLdO + k] * w5[k];
-        const int64_t m = r0 + r;
-        if (m >= nrow) continue;
-        if (SIM) {
-            // (re, im) pairs of J[p][k]; the simulator's components are (p, k) of n_feed x n_ax
-            const int c = o / 2, p = c / 2, k = c % 2;
-            if (p >= a.n_feed || k >= a.n_ax) continue;
-            const float sq =
-                a.idx ? (float)sqrt(a.flux[(int64_t)f * a.n_src + a.idx[(int64_t)slot * a.ld_src + m]]) : 1.0f;
-            float *dst = (float *)((float2 *)a.A + ((int64_t)inst * a.n_feed * a.n_ax + p * a.n_ax + k) * a.ld_src + m);
-            dst[o & 1] = sq * s;
-        } else {
-            a.out[m * kOut + o] = s;
+        // layer 1: features formed per k block (sin in kb, cos in kb + 4)
+        f32x4 acc1[8][4];
+#pragma unroll
+        for (int h = 0; h < 8; h++) {
+            const f32x4 bv = *(const f32x4 *)(P + kOffB1 + 16 * h + 4 * lk);
+#pragma unroll
+            for (int pt = 0; pt < 4; pt++) acc1[h][pt] = bv;
+        }
+#pragma unroll 1
+        for (int kb = 0; kb < 4; kb++) {
+            float bf[24];
+            const f32x4 *bsrc = (const f32x4 *)(P + kOffBff + 3 * (32 * kb + 8 * lk));
+#pragma unroll
+            for (int q = 0; q < 6; q++) {
+                const f32x4 v = bsrc[q];
+                bf[4 * q] = v[0];
+                bf[4 * q + 1] = v[1];
+                bf[4 * q + 2] = v[2];
+                bf[4 * q + 3] = v[3];
+            }
+            bf16x8 S[4], C[4];
+#pragma unroll
+            for (int pt = 0; pt < 4; pt++)
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    float s, c;
+                    sincos_rev(bf[3 * e] * xu[pt] + bf[3 * e + 1] * xv[pt] + bf[3 * e + 2] * xw[pt], s, c);
+                    S[pt][e] = (__bf16)s;
+                    C[pt][e] = (__bf16)c;
+                }
+#pragma unroll
+            for (int h = 0; h < 8; h++) {
+                const bf16x8 ws = lds_block(img, h * 8 + kb, lane), wc = lds_block(img, h * 8 + kb + 4, lane);
+#pragma unroll
+                for (int pt = 0; pt < 4; pt++) {
+                    acc1[h][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ws, S[pt], acc1[h][pt], 0, 0, 0);
+                    acc1[h][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wc, C[pt], acc1[h][pt], 0, 0, 0);
+                }
+            }
+        }
+        bf16x8 hA[4][4], hB[4][4];
+#pragma unroll
+        for (int h = 0; h < 8; h++)
+#pragma unroll
+            for (int pt = 0; pt < 4; pt++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) hA[h / 2][pt][4 * (h % 2) + e] = (__bf16)silu_fast(acc1[h][pt][e]);
+        hidden_layer(img, kImgW1Blocks, P + kOffB2, hA, hB, lane, lk);
+        hidden_layer(img, kImgW1Blocks + kImgLayerBlocks, P + kOffB3, hB, hA, lane, lk);
+        // layer 4 in FP32 after SiLU, fed half by half to the FP32 head
+        f32x4 D[4];
+        {
+            const f32x4 b5 = lk < 2 ? *(const f32x4 *)(P + kOffB5 + 4 * lk) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int pt = 0; pt < 4; pt++) D[pt] = b5;
+        }
+        const int blk4 = kImgW1Blocks + 2 * kImgLayerBlocks;
+#pragma unroll
+        for (int hh = 0; hh < 2; hh++) {
+            f32x4 acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const f32x4 bv = *(const f32x4 *)(P + kOffB4 + 16 * (4 * hh + i) + 4 * lk);
+#pragma unroll
+                for (int pt = 0; pt < 4; pt++) acc[i][pt] = bv;
+            }
+#pragma unroll
+            for (int kb = 0; kb < 4; kb++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const bf16x8 w = lds_block(img, blk4 + (4 * hh + i) * 4 + kb, lane);
+#pragma unroll
+                    for (int pt = 0; pt < 4; pt++)
+                        acc[i][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, hA[kb][pt], acc[i][pt], 0, 0, 0);
+                }
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                // head operand: W5[o = l16][16 h + 4 lk + e] for k slot lk of block (h, e)
+                const int h = 4 * hh + i;
+                const f32x4 w5 = l16 < kOut ? *(const f32x4 *)(P + kOffW5 + l16 * kHid + 16 * h + 4 * lk)
+                                            : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int pt = 0; pt < 4; pt++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        D[pt] = __builtin_amdgcn_mfma_f32_16x16x4f32(w5[e], silu_fast(acc[i][pt][e]), D[pt], 0, 0, 0);
+            }
+        }
+        // outputs 4 lk + e (lk = 0, 1) of point 16 pt + l16: (re, im) of components 2 lk, 2 lk + 1
+        if (lk < 2) {
+#pragma unroll
+            for (int pt = 0; pt < 4; pt++) {
+                const int64_t m = m0 + 16 * pt + l16;
+                if (m >= nrow) continue;
+                if (SIM) {
+                    const float sq =
+                        a.idx ? (float)sqrt(a.flux[(int64_t)f * a.n_src + a.idx[(int64_t)slot * a.ld_src + m]]) : 1.0f;
+                    // component (p, k) = (lk, cc) of the n_feed x n_ax Jones matrix
+#pragma unroll
+                    for (int cc = 0; cc < 2; cc++) {
+                        if (lk >= a.n_feed || cc >= a.n_ax) continue;
+                        float2 *dst = (float2 *)a.A + ((int64_t)inst * a.n_feed * a.n_ax + lk * a.n_ax + cc) * a.ld_src + m;
+                        *dst = make_float2(sq * D[pt][2 * cc], sq * D[pt][2 * cc + 1]);
+                    }
+                } else {
+                    *(f32x4 *)(a.out + m * kOut + 4 * lk) = D[pt];
+                }
+            }
         }
     }
+}
+
+int infer_grid(int64_t n_tasks) {
+    static int n_cu = 0;
+    if (n_cu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
+            n_cu = 256;
+    }
+    return (int)std::min<int64_t>(n_cu, (n_tasks + kIWaves - 1) / kIWaves);
 }
 
 }  // namespace
@@ -479,11 +622,8 @@ hipError_t to_bf16(const float *in, __bf16 *out, int64_t n, hipStream_t s) {
 }
 
 hipError_t pack_weights(const float *P, __bf16 *Wb, hipStream_t s) {
-    hipError_t e = to_bf16(P + kOffW1, Wb, (int64_t)kHid * kFeat, s);
-    const int64_t off[3] = {kOffW2, kOffW3, kOffW4};
-    for (int l = 0; l < 3 && e == hipSuccess; l++)
-        e = to_bf16(P + off[l], Wb + (int64_t)kHid * kFeat + l * (int64_t)kHid * kHid, (int64_t)kHid * kHid, s);
-    return e;
+    k_pack_image<<<(unsigned)((kWbElems + 255) / 256), 256, 0, s>>>(P, Wb);
+    return hipGetLastError();
 }
 
 hipError_t beam_samples(const void *grid, int n_feed, int n_ax, int n_za, int n_az, double dza, double daz,
@@ -508,7 +648,8 @@ hipError_t infer_plain(const float *P, const __bf16 *Wb, const float *x, int64_t
     a.x = x;
     a.out = out;
     a.n = n;
-    k_mlp_infer<false><<<(unsigned)((n + kRows - 1) / kRows), 256, 0, s>>>(a);
+    a.n_tasks = (n + kIPts - 1) / kIPts;
+    k_mlp_infer<false><<<infer_grid(a.n_tasks), kIWaves * kWave, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -516,6 +657,7 @@ hipError_t infer_sim(const float *P, const __bf16 *Wb, double nu0, double nu1, c
                      const int32_t *count, const int32_t *idx, const double *flux, int64_t n_src, const double *freqs,
                      int64_t ld_src, int64_t max_m, void *A, int n_feed, int n_ax, const Batch &bt, hipStream_t s) {
     if (bt.n_inst <= 0 || max_m <= 0) return hipSuccess;
+    if (n_feed > 2 || n_ax > 2) return hipErrorInvalidValue;
     InferArgs a{};
     a.P = P;
     a.Wb = Wb;
@@ -532,8 +674,9 @@ hipError_t infer_sim(const float *P, const __bf16 *Wb, double nu0, double nu1, c
     a.n_feed = n_feed;
     a.n_ax = n_ax;
     a.bt = bt;
-    dim3 g((unsigned)((max_m + kRows - 1) / kRows), bt.n_inst);
-    k_mlp_infer<true><<<g, 256, 0, s>>>(a);
+    a.tiles = (max_m + kIPts - 1) / kIPts;
+    a.n_tasks = a.tiles * bt.n_inst;
+    k_mlp_infer<true><<<infer_grid(a.n_tasks), kIWaves * kWave, 0, s>>>(a);
     return hipGetLastError();
 }
 

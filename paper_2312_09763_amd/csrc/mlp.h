@@ -55,7 +55,9 @@ hipError_t loss_grad(const float *out, const float *y, int64_t n, float *dout, f
 hipError_t colsum(const float *dZ, int64_t M, int N, float *db, float *ws, int64_t ws_elems, hipStream_t s);
 hipError_t adam(float *p, const float *g, float *m1, float *m2, int64_t n, int64_t step, float lr, hipStream_t s);
 hipError_t to_bf16(const float *in, __bf16 *out, int64_t n, hipStream_t s);
-// bf16 copies of W1..W4 packed back to back (kWbElems values) for inference
+// bf16 W1..W4 (kWbElems values, 160 KB) in the inference kernel's LDS image:
+// 1 KB MFMA A-operand blocks per (layer, 16-row tile, 32-deep k block), the
+// columns of W2..W4 permuted to the accumulator order of the layer before.
 constexpr int64_t kWbElems = (int64_t)kHid * kFeat + 3 * (int64_t)kHid * kHid;
 hipError_t pack_weights(const float *P, __bf16 *Wb, hipStream_t s);
 hipError_t beam_samples(const void *grid, int n_feed, int n_ax, int n_za, int n_az, double dza, double daz,

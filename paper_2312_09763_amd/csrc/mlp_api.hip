@@ -112,6 +112,7 @@ extern "C" {
 
 matvis_status matvis_mlp_forward(const float *params, const float *x, int64_t n, float *out, void *stream) {
     if (!params || (n > 0 && (!x || !out)) || n < 0) return MATVIS_EINVAL;
+    if ((uintptr_t)params % 16 || (uintptr_t)out % 16) return MATVIS_EINVAL;  // read / written as float4
     if (n == 0) return MATVIS_OK;
     hipStream_t s = (hipStream_t)stream;
     __bf16 *wb = nullptr;
