@@ -25,6 +25,7 @@
 // unfused product and are summed by k_reduce.
 #include "matvis.h"
 #include "internal.h"
+#include <type_traits>
 
 namespace mv {
 
@@ -560,11 +561,24 @@ __device__ __forceinline__ void consume_sq_b3(const unsigned char *buf, int rb, 
 }
 
 // Row sets of the triangle waves and the first accumulator slot of each row
-// (row r of a set holds columns 0..r in consecutive slots).
+// (row r of a set holds columns 0..r in consecutive slots).  On a diagonal
+// block the column operand of column c is the row operand of row c (same
+// rows, same lane layout), so a wave loads only the columns that are not its
+// own rows, and none right of its last row.  order[] interleaves loaded and
+// reused columns so every load has at least one column of products to hide in.
 template <int S>
 struct TriSet {
     static constexpr int r[4] = {S == 0 ? 0 : 2, S == 0 ? 7 : 5, S == 0 ? 1 : 3, S == 0 ? 6 : 4};
     static constexpr int base[4] = {0, r[0] + 1, r[0] + r[1] + 2, r[0] + r[1] + r[2] + 3};
+    static constexpr int ncol = S == 0 ? 8 : 6;
+    static constexpr int order[8] = {S == 0 ? 0 : 2, S == 0 ? 2 : 0, S == 0 ? 1 : 3, S == 0 ? 3 : 1,
+                                     S == 0 ? 6 : 4, S == 0 ? 4 : 5, S == 0 ? 7 : -1, S == 0 ? 5 : -1};
+    // row slot holding column c, or -1 when the column is loaded
+    static constexpr int slot(int c) { return r[0] == c ? 0 : r[1] == c ? 1 : r[2] == c ? 2 : r[3] == c ? 3 : -1; }
+    // first position at or after p whose column is loaded, or -1
+    static constexpr int next_loaded(int p) {
+        return p >= ncol ? -1 : slot(order[p]) < 0 ? p : next_loaded(p + 1);
+    }
 };
 
 // One 128-row diagonal triangle starting at LDS row o: tiles (r, c), c <= r, r in the set.
@@ -574,22 +588,35 @@ __device__ __forceinline__ void consume_tri_b3(const unsigned char *buf, int o, 
     typedef TriSet<S> T;
 #pragma unroll
     for (int ks = 0; ks < L::NKS; ks++) {
+        const unsigned char *p0 = buf + (o + l16) * L::RS + ks * 64 + lk * 16;  // row / column 0 of this lane
         u32x4 ah[4], al[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const unsigned char *p = buf + (o + 16 * T::r[k] + l16) * L::RS + ks * 64 + lk * 16;
-            ah[k] = *(const u32x4 *)p;
-            al[k] = *(const u32x4 *)(p + L::PLANEB);
+            ah[k] = *(const u32x4 *)(p0 + 16 * T::r[k] * L::RS);
+            al[k] = *(const u32x4 *)(p0 + 16 * T::r[k] * L::RS + L::PLANEB);
         }
-        const unsigned char *pc = buf + (o + l16) * L::RS + ks * 64 + lk * 16;
-        u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
+        u32x4 nh = {0u, 0u, 0u, 0u}, nl = {0u, 0u, 0u, 0u};
+        constexpr int f0 = T::next_loaded(0);
+        if (f0 >= 0) {
+            nh = *(const u32x4 *)(p0 + 16 * T::order[f0] * L::RS);
+            nl = *(const u32x4 *)(p0 + 16 * T::order[f0] * L::RS + L::PLANEB);
+        }
 #pragma unroll
-        for (int c = 0; c < 8; c++) {
-            const u32x4 bh = nh, bl = nl;
-            if (c + 1 < 8) {
-                const unsigned char *p = pc + 16 * (c + 1) * L::RS;
-                nh = *(const u32x4 *)p;
-                nl = *(const u32x4 *)(p + L::PLANEB);
+        for (int q = 0; q < T::ncol; q++) {
+            const int c = T::order[q];
+            const int kc = T::slot(c);
+            u32x4 bh, bl;
+            if (kc >= 0) {
+                bh = ah[kc];
+                bl = al[kc];
+            } else {
+                bh = nh;
+                bl = nl;
+                const int qn = T::next_loaded(q + 1);
+                if (qn >= 0) {
+                    nh = *(const u32x4 *)(p0 + 16 * T::order[qn] * L::RS);
+                    nl = *(const u32x4 *)(p0 + 16 * T::order[qn] * L::RS + L::PLANEB);
+                }
             }
             __builtin_amdgcn_sched_barrier(0);
             const u32x4 wh = bf16_rot_col(bh), wl = bf16_rot_col(bl);
@@ -853,8 +880,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_pair(FusedArgs a) {
 struct CohSrc {
     double x, y, z;  // s_hat
     float s0, s1;    // sqrt C00, sqrt C11
-    float lx, ly;    // C10 / sqrt C00
-    int m;           // source index, -1 past the split
+    float lx, ly;    // C10 / sqrt C00 (all four 0 past the split)
 };
 
 __global__ void __launch_bounds__(512, 1) k_herk_b3_coh(FusedArgs a) {
@@ -866,6 +892,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_coh(FusedArgs a) {
     // Antennas formed by the square waves (the rest by the triangle waves, which
     // have more products per stage): the split evens out the two waves of a SIMD.
     constexpr int SQ_ANT = 96;
+    static_assert(SQ_ANT % 32 == 0 && (kST - SQ_ANT) % 32 == 0, "32 antennas per pass of a wave group");
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
     __shared__ AntEntry tab[kST];
     __shared__ CohSrc src[2][SPS];
@@ -880,9 +907,8 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_coh(FusedArgs a) {
     const int per_xcd = a.grid / 8;
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int mp = tid % (SPS / 2);  // source pair
-    // this thread's antennas: a0, a0 + 32, ... below a1
+    // this thread's antennas: a0, a0 + 32, ... (SQ_ANT / 32 of them, or (kST - SQ_ANT) / 32)
     const int a0 = sq ? tid / (SPS / 2) : SQ_ANT + (tid - 256) / (SPS / 2);
-    const int a1 = sq ? SQ_ANT : kST;
     // square waves: V^10 rows 16 (sq_rb + i) of L against 16 (sq_cb + j) of P0 (block units)
     const int sq_r0 = 4 * (wave >> 1), sq_c0 = 4 * (wave & 1);
     const int sq_rb = 2 * 8 + sq_r0, sq_cb = sq_c0;
@@ -963,24 +989,29 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_coh(FusedArgs a) {
             e.s1 = sqrtf(c11);
             e.lx = s0 > 0.f ? c10x / s0 : 0.f;
             e.ly = s0 > 0.f ? c10y / s0 : 0.f;
-            e.m = fm;
         };
-        // the three planes of this thread's two sources for its antennas
-        auto produce = [&](unsigned char *buf, int stage) {
+        // The three planes of this thread's two sources for its NA antennas.  No
+        // masks: a source past the split has zero coherency factors, and rows of
+        // padding antennas (u = 0) only reach outputs that are never stored.
+        auto produce_n = [&](unsigned char *buf, int stage, auto na) {
+            constexpr int NA = decltype(na)::value;
             CohSrc w[2];
             w[0] = src[stage & 1][2 * mp];
             w[1] = src[stage & 1][2 * mp + 1];
-#pragma unroll 1
-            for (int as = a0; as < a1; as += 256 / (SPS / 2)) {
-                const AntEntry e = tab[as];
+            AntEntry ee[NA];
+#pragma unroll
+            for (int k = 0; k < NA; k++) ee[k] = tab[a0 + 32 * k];
+#pragma unroll
+            for (int k = 0; k < NA; k++) {
+                const int as = a0 + 32 * k;
+                const AntEntry &e = ee[k];
                 uint32_t h[3][2], l[3][2];
 #pragma unroll
                 for (int q = 0; q < 2; q++) {
                     const double p = e.ux * w[q].x + e.uy * w[q].y + e.uz * w[q].z;
-                    const float r = (float)(p - rint(p));
-                    const float msk = (w[q].m >= 0 && e.b >= 0) ? 1.0f : 0.0f;
-                    const float fi = msk * __builtin_amdgcn_sinf(-r);
-                    const float fr = msk * __builtin_amdgcn_cosf(-r);
+                    const float r = (float)__builtin_amdgcn_fract(p);
+                    const float fi = __builtin_amdgcn_sinf(-r);
+                    const float fr = __builtin_amdgcn_cosf(-r);
                     split2(w[q].s0 * fr, w[q].s0 * fi, h[0][q], l[0][q]);
                     split2(w[q].s1 * fr, w[q].s1 * fi, h[1][q], l[1][q]);
                     split2(w[q].lx * fr - w[q].ly * fi, w[q].lx * fi + w[q].ly * fr, h[2][q], l[2][q]);
@@ -992,6 +1023,12 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_coh(FusedArgs a) {
                     *(uint2 *)(row + L::PLANEB) = make_uint2(l[pl][0], l[pl][1]);
                 }
             }
+        };
+        auto produce = [&](unsigned char *buf, int stage) {
+            if (sq)
+                produce_n(buf, stage, std::integral_constant<int, SQ_ANT / 32>{});
+            else
+                produce_n(buf, stage, std::integral_constant<int, (kST - SQ_ANT) / 32>{});
         };
 
         f32x4 acc_re[18], acc_im[18];
