@@ -239,12 +239,14 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     // err_CS grows about as sqrt(ksplit) (FP32: 3.1e-6 at 2048, 1.4e-5 at 8192;
     // BF16X3: 2.5e-6 at 4096, whose split error dominates below that).
     // The product over sources (two axes summed per source) accumulates ksplit / 2
-    // sources per item, so it takes twice the BF16X3 k-split for the same rounding.
+    // sources per item: err_CS 3.5e-6 at 8192, 4.9e-6 at 16384, 7.0e-6 at 32768 on
+    // the same workload; 16384 keeps a factor 2 to 1e-5 and halves the partials
+    // the reduction reads.
     c->fused = prec != P64 && !(cfg->flags & MATVIS_FLAG_UNFUSED);
     const bool over_sources =
         c->fused && fused_path(prec, cfg->n_feed, cfg->n_ax, cfg->n_beam, cfg->n_ant, c->Np) == MATVIS_PATH_SOURCES;
     c->ksplit = cfg->ksplit > 0 ? cfg->ksplit
-                                : (prec == P64 ? 8192 : prec == P32 ? 2048 : over_sources ? 8192 : 4096);
+                                : (prec == P64 ? 8192 : prec == P32 ? 2048 : over_sources ? 16384 : 4096);
     c->max_splits = (int)((c->ldz + c->ksplit - 1) / c->ksplit);
     // batch: all channels of a few times, enough instances to fill the GPU with
     // work items while keeping Z within a fixed share of device memory
@@ -254,7 +256,7 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
                    (size_t)c->max_splits * c->Np * c->Np * cbytes(prec);
     size_t budget = (size_t)12 << 30;
     int ntb_auto = (int)std::max<size_t>(1, budget / std::max<size_t>(1, zinst * c->nfb));
-    c->ntb = cfg->batch_time > 0 ? cfg->batch_time : std::min(ntb_auto, 8);
+    c->ntb = cfg->batch_time > 0 ? cfg->batch_time : std::min(ntb_auto, 16);
     c->ntb = std::max(1, std::min(c->ntb, cfg->max_time));
     const int B = c->ntb * c->nfb;
     c->nblk_cap = std::max<int64_t>((c->chunk + 255) / 256, 1);
