@@ -53,14 +53,19 @@ def log(*a):
 def measured_traffic(path: str):
     """HBM bytes per launch of the product kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or None when no
-    summary exists for this path or the kernel source changed since it was taken."""
+    summary exists for this path or a source it depends on (the kernel, and the host
+    code that sizes its launches) changed since it was taken."""
     import hashlib
     f = os.path.join(ROOT, "profiles", {"sources": "herk_b3_coh_workload2.json"}.get(path, "none.json"))
     if not os.path.exists(f):
         return None
     rec = json.load(open(f))
-    src = os.path.join(ROOT, rec["kernel_source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["source_sha256_16"]:
+    if "sources" not in rec or "sources_sha256_16" not in rec:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
         return None
     return rec["traffic_bytes_per_launch"]
 
