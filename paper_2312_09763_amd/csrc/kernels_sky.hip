@@ -80,15 +80,20 @@ __global__ void __launch_bounds__(kSkyBlock) k_xeq_cells(const double *__restric
 }
 
 // hist[b][c] -> first position of block b's cell-c sources in the cell-major order.
+// Each thread walks its cell's column of blocks kU entries at a time, so the
+// loads of a group are in flight together (the walk is latency-bound).
 __global__ void __launch_bounds__(1024) k_cell_offsets(int32_t *__restrict__ hist, int nblk) {
+    constexpr int kU = 16;
     __shared__ int tot[kCells];
     __shared__ int wsum[1024 / kWave];
     for (int c = threadIdx.x; c < kCells; c += 1024) {
         int run = 0;
-        for (int b = 0; b < nblk; b++) {
-            const int v = hist[(int64_t)b * kCells + c];
-            hist[(int64_t)b * kCells + c] = run;
-            run += v;
+        for (int b0 = 0; b0 < nblk; b0 += kU) {
+            int v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; u++) v[u] = b0 + u < nblk ? hist[(int64_t)(b0 + u) * kCells + c] : 0;
+#pragma unroll
+            for (int u = 0; u < kU; u++) run += v[u];
         }
         tot[c] = run;
     }
@@ -116,8 +121,20 @@ __global__ void __launch_bounds__(1024) k_cell_offsets(int32_t *__restrict__ his
         carry += block_total;
         __syncthreads();
     }
-    for (int c = threadIdx.x; c < kCells; c += 1024)
-        for (int b = 0; b < nblk; b++) hist[(int64_t)b * kCells + c] += tot[c];
+    for (int c = threadIdx.x; c < kCells; c += 1024) {
+        int run = tot[c];
+        for (int b0 = 0; b0 < nblk; b0 += kU) {
+            int v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; u++) v[u] = b0 + u < nblk ? hist[(int64_t)(b0 + u) * kCells + c] : 0;
+#pragma unroll
+            for (int u = 0; u < kU; u++)
+                if (b0 + u < nblk) {
+                    hist[(int64_t)(b0 + u) * kCells + c] = run;
+                    run += v[u];
+                }
+        }
+    }
 }
 
 // Stable scatter into cell order: rank among earlier sources of the same cell in the block.
