@@ -89,10 +89,20 @@ __global__ void __launch_bounds__(256) k_interp_tf(InterpArgs a, Batch bt) {
     constexpr int FG = 4;                            // channels per group
     constexpr int PER = 16 / sizeof(C);              // complex values per lane (16 bytes)
     constexpr int LPS = FG * NCOMP / PER;            // lanes per source
-    const int slot = blockIdx.y;
-    const int fg = blockIdx.z * FG;                  // first channel of the group, relative to the batch
+    // XCD-aware block order: workgroups go to the 8 XCDs round-robin by linear id,
+    // so each XCD is given one contiguous range of (channel group, slot, source
+    // block) work; neighbouring (sky-cell ordered) sources then share one L2 and
+    // the grid lines they have in common are fetched into it once.
+    const int64_t gx = gridDim.x, gy = gridDim.y;
+    const int64_t total = gx * gy * gridDim.z;
+    const int64_t lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int64_t xq = total / 8, xr = total % 8, xcd = lin % 8;
+    const int64_t task = xcd * xq + (xcd < xr ? xcd : xr) + lin / 8;
+    const int64_t bx = task % gx;
+    const int slot = (int)((task / gx) % gy);
+    const int fg = (int)(task / (gx * gy)) * FG;    // first channel of the group, relative to the batch
     const int l = threadIdx.x % LPS;
-    const int64_t m = (int64_t)blockIdx.x * (blockDim.x / LPS) + threadIdx.x / LPS;
+    const int64_t m = bx * (blockDim.x / LPS) + threadIdx.x / LPS;
     const int64_t M = a.count ? a.count[slot] : a.fixed_count;
     if (m >= M || fg >= bt.nfb) return;
     const int nf = bt.nfb - fg < FG ? bt.nfb - fg : FG;
