@@ -73,6 +73,9 @@ def _declare(L):
     L.orc_simulate_pairs.argtypes = [ctypes.POINTER(Geom), _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P,
                                      _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]
     L.orc_simulate_pairs.restype = ctypes.c_int
+    L.orc_simulate_pol.argtypes = [ctypes.POINTER(Geom), _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P,
+                                   _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]
+    L.orc_simulate_pol.restype = ctypes.c_int
     L.orc_simulate_given_beam.argtypes = [ctypes.POINTER(Geom), _P, _P, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_int64, _P, _P, _P, _P, _P]
     L.orc_simulate_given_beam.restype = ctypes.c_int64
@@ -163,8 +166,13 @@ def simulate(antpos, freqs, lsts, ra, dec, flux, beam_grid, latitude: float, dza
 
     ``instances`` is a list of (t, f) pairs; default: every (t, f) in
     t-major order.  beam_grid is [n_beam][n_freq][n_feed][n_ax][n_za][n_az].
+    flux is Stokes I [n_freq][n_src], or a polarised sky [4][n_freq][n_src]
+    (I, Q, U, V; needs n_ax = 2).
     """
     antpos, freqs, lsts, ra, dec, flux = map(_f64, (antpos, freqs, lsts, ra, dec, flux))
+    if flux.ndim == 3:
+        return _simulate_pol(antpos, freqs, lsts, ra, dec, flux, beam_grid, latitude, dza, daz, interp_mode,
+                             instances, None, beam_idx)
     beam_grid = _c128(beam_grid)
     nb, nfreq, nf, nx, nza, naz = beam_grid.shape
     na = antpos.shape[0]
@@ -185,8 +193,12 @@ def simulate(antpos, freqs, lsts, ra, dec, flux, beam_grid, latitude: float, dza
 
 def simulate_pairs(antpos, freqs, lsts, ra, dec, flux, beam_grid, latitude: float, dza: float, daz: float,
                    interp_mode: str, instances: Sequence, pairs: Sequence, beam_idx=None) -> np.ndarray:
-    """Direct sum for selected antenna pairs only: V[inst][pair][p][q] (complex128)."""
+    """Direct sum for selected antenna pairs only: V[inst][pair][p][q] (complex128).
+    flux as in simulate (Stokes I, or [4][n_freq][n_src] for a polarised sky)."""
     antpos, freqs, lsts, ra, dec, flux = map(_f64, (antpos, freqs, lsts, ra, dec, flux))
+    if flux.ndim == 3:
+        return _simulate_pol(antpos, freqs, lsts, ra, dec, flux, beam_grid, latitude, dza, daz, interp_mode,
+                             instances, pairs, beam_idx)
     beam_grid = _c128(beam_grid)
     nb, nfreq, nf, nx, nza, naz = beam_grid.shape
     na = antpos.shape[0]
@@ -200,6 +212,37 @@ def simulate_pairs(antpos, freqs, lsts, ra, dec, flux, beam_grid, latitude: floa
     rc = lib().orc_simulate_pairs(ctypes.byref(G), _ptr(antpos), _ptr(bi), _ptr(freqs), freqs.size, _ptr(lsts),
                                   ra.size, _ptr(ra), _ptr(dec), _ptr(flux), _ptr(beam_grid), len(instances),
                                   _ptr(it), _ptr(iff), len(pairs), _ptr(pa), _ptr(pb), _ptr(V))
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    return V
+
+
+def _simulate_pol(antpos, freqs, lsts, ra, dec, stokes, beam_grid, latitude, dza, daz, interp_mode, instances, pairs,
+                  beam_idx):
+    """Polarised-sky direct sum (Sec. 2.1 brightness matrix from I, Q, U, V)."""
+    beam_grid = _c128(beam_grid)
+    nb, nfreq, nf, nx, nza, naz = beam_grid.shape
+    if nx != 2 or stokes.shape[0] != 4:
+        raise ValueError("a polarised sky needs two E-field axes and stokes [4][n_freq][n_src]")
+    na = antpos.shape[0]
+    if instances is None:
+        instances = [(t, f) for t in range(lsts.size) for f in range(freqs.size)]
+    it = _i32([i[0] for i in instances])
+    iff = _i32([i[1] for i in instances])
+    bi = None if beam_idx is None else _i32(beam_idx)
+    G = _geom(na, nf, nx, nb, nza, naz, dza, daz, latitude, interp_mode)
+    if pairs is None:
+        V = np.zeros((len(instances), na, na, nf, nf), dtype=np.complex128)
+        pa = pb = None
+        npair = -1
+    else:
+        V = np.zeros((len(instances), len(pairs), nf, nf), dtype=np.complex128)
+        pa = _i32([p[0] for p in pairs])
+        pb = _i32([p[1] for p in pairs])
+        npair = len(pairs)
+    rc = lib().orc_simulate_pol(ctypes.byref(G), _ptr(antpos), _ptr(bi), _ptr(freqs), freqs.size, _ptr(lsts),
+                                ra.size, _ptr(ra), _ptr(dec), _ptr(_f64(stokes)), _ptr(beam_grid), len(instances),
+                                _ptr(it), _ptr(iff), npair, _ptr(pa), _ptr(pb), _ptr(V))
     if rc != 0:
         raise MemoryError("oracle allocation failed")
     return V

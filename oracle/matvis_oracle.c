@@ -20,6 +20,8 @@
  *   - the Gram matrix Z Z^H                              Eq. (zz); Alg. 2 step (v)
  *   - the end-to-end visibilities as a direct sum over
  *     sources for every antenna pair (not via Z)         Eq. (matvisrime), (matvisdelay)
+ *   - the same direct sum for a polarised sky, with the
+ *     brightness matrix built from I, Q, U, V            Sec. 2.1; Eq. (matvisrime)
  *
  * Readings taken where the paper is silent or ambiguous:
  *   - the hour angle in Eq. (rotation) is H = -LST; with it R X_eq equals the
@@ -402,6 +404,84 @@ int64_t orc_simulate_given_beam(const orc_geom *G, const double *antpos, const i
     direct_sum(G, antpos, beam_idx, freq, m, xvis, fvis, A, n_src, V);
     free(xeq); free(xall); free(xvis); free(fvis); free(idx); free(A);
     return m;
+}
+
+/* Polarised sky, Eq. (matvisrime) with the source brightness matrix of Sec. 2.1
+ * written from the Stokes parameters,
+ *   C = [[I + Q, U + iV], [U - iV, I - Q]]  (indices: the beam's E-field axes k, k'),
+ *   V[a][b][p][q] = sum_{n visible} sum_{k,k'} A_{beam(a),p,k}(n) C_{kk'}(n) conj(A_{beam(b),q,k'}(n))
+ *                    * exp(-2 pi i nu (x_a - x_b) . s_n / c),
+ * summed in ascending n.  stokes is [4][n_freq][n_src] (I, Q, U, V per channel);
+ * needs n_ax = 2.  n_pair < 0 evaluates every (a, b) into V[inst][a][b][p][q];
+ * otherwise the listed pairs into V[inst][j][p][q].  Returns 0, -1 on
+ * allocation failure, -2 when n_ax != 2. */
+int orc_simulate_pol(const orc_geom *G, const double *antpos, const int32_t *beam_idx, const double *freqs,
+                     int32_t n_freq, const double *lsts, int64_t n_src, const double *ra, const double *dec,
+                     const double *stokes, const cplx *beam_grid, int32_t n_inst, const int32_t *inst_t,
+                     const int32_t *inst_f, int32_t n_pair, const int32_t *pair_a, const int32_t *pair_b,
+                     cplx *V) {
+    if (G->n_ax != 2) return -2;
+    const int64_t ns1 = n_src ? n_src : 1;
+    double *xeq = malloc(sizeof(double) * 3 * ns1);
+    double *xall = malloc(sizeof(double) * 3 * ns1);
+    double *xvis = malloc(sizeof(double) * 3 * ns1);
+    double *svis = malloc(sizeof(double) * 4 * ns1);
+    int32_t *idx = malloc(sizeof(int32_t) * ns1);
+    int64_t plane = (int64_t)G->n_za * G->n_az;
+    int64_t per_freq = (int64_t)G->n_feed * G->n_ax * plane;
+    cplx *A = malloc(sizeof(cplx) * (size_t)G->n_beam * G->n_feed * G->n_ax * ns1);
+    cplx *slice = malloc(sizeof(cplx) * (size_t)G->n_beam * per_freq);
+    if (!xeq || !xall || !xvis || !svis || !idx || !A || !slice) {
+        free(xeq); free(xall); free(xvis); free(svis); free(idx); free(A); free(slice);
+        return -1;
+    }
+    orc_xeq(n_src, ra, dec, xeq);
+    const int na = G->n_ant, nf = G->n_feed, nx = G->n_ax;
+    const int64_t npair = n_pair < 0 ? (int64_t)na * na : n_pair;
+    for (int32_t i = 0; i < n_inst; i++) {
+        int t = inst_t[i], f = inst_f[i];
+        for (int b = 0; b < G->n_beam; b++)
+            memcpy(slice + b * per_freq, beam_grid + ((int64_t)b * n_freq + f) * per_freq, sizeof(cplx) * per_freq);
+        int64_t m = instance_sky(G, lsts[t], n_src, xeq, slice, idx, xall, xvis, A);
+        for (int st = 0; st < 4; st++)
+            for (int64_t n = 0; n < m; n++) svis[st * ns1 + n] = stokes[((int64_t)st * n_freq + f) * n_src + idx[n]];
+        double freq = freqs[f];
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t j = 0; j < npair; j++) {
+            int a = n_pair < 0 ? (int)(j / na) : pair_a[j];
+            int b = n_pair < 0 ? (int)(j % na) : pair_b[j];
+            double bx = antpos[3 * a + 0] - antpos[3 * b + 0];
+            double by = antpos[3 * a + 1] - antpos[3 * b + 1];
+            double bz = antpos[3 * a + 2] - antpos[3 * b + 2];
+            int ia = beam_idx ? beam_idx[a] : 0;
+            int ib = beam_idx ? beam_idx[b] : 0;
+            for (int p = 0; p < nf; p++)
+                for (int q = 0; q < nf; q++) {
+                    cplx acc = 0.0;
+                    for (int64_t n = 0; n < m; n++) {
+                        const double *s = xvis + 3 * n;
+                        double tau = (bx * s[0] + by * s[1] + bz * s[2]) / SPEED_OF_LIGHT;
+                        double ph = -2.0 * M_PI * freq * tau;
+                        cplx fringe = cos(ph) + I * sin(ph);
+                        double si = svis[n], sq = svis[ns1 + n], su = svis[2 * ns1 + n], sv = svis[3 * ns1 + n];
+                        cplx C[2][2];
+                        C[0][0] = si + sq;
+                        C[0][1] = su + I * sv;
+                        C[1][0] = su - I * sv;
+                        C[1][1] = si - sq;
+                        cplx beams = 0.0;
+                        for (int k = 0; k < nx; k++)
+                            for (int k2 = 0; k2 < nx; k2++)
+                                beams += A[(((int64_t)ia * nf + p) * nx + k) * n_src + n] * C[k][k2] *
+                                         conj(A[(((int64_t)ib * nf + q) * nx + k2) * n_src + n]);
+                        acc += beams * fringe;
+                    }
+                    V[(((int64_t)i * npair + j) * nf + p) * nf + q] = acc;
+                }
+        }
+    }
+    free(xeq); free(xall); free(xvis); free(svis); free(idx); free(A); free(slice);
+    return 0;
 }
 
 /* Step references used by per-kernel tests.

@@ -99,6 +99,41 @@ def spectral_fluxes(s150: np.ndarray, freqs: np.ndarray, alpha: Optional[np.ndar
     return s150[None, :] * (freqs[:, None] / 150e6) ** alpha[None, :]
 
 
+def polarised_stokes(flux: np.ndarray, freqs: np.ndarray, seed: int = 0, frac_full: float = 0.05,
+                     frac_minus_q: float = 0.01) -> np.ndarray:
+    """A physical polarised sky [4][n_freq][n_src] (I, Q, U, V) on top of Stokes I.
+
+    Per source: linear polarisation fraction p ~ U(0, 0.6), circular fraction
+    v ~ U(-0.05, 0.05), angle chi(nu) = chi0 + RM (c / nu)^2 with chi0 ~ U(0, pi)
+    and a rotation measure RM ~ N(0, 20) rad m^-2 (Faraday rotation), so
+    Q = I p cos 2 chi, U = I p sin 2 chi, V = I v.  A fraction frac_full of the
+    sources is fully polarised (p^2 + v^2 = 1) and a fraction frac_minus_q has
+    Q = -I, U = V = 0 exactly (the I + Q = 0 edge of the brightness matrix's
+    square root).  Every source satisfies Q^2 + U^2 + V^2 <= I^2.
+    """
+    flux = np.asarray(flux, dtype=np.float64)
+    n_freq, n_src = flux.shape
+    rng = np.random.Generator(np.random.PCG64(1000 + seed))
+    p = rng.uniform(0.0, 0.6, n_src)
+    v = rng.uniform(-0.05, 0.05, n_src)
+    full = rng.uniform(size=n_src) < frac_full
+    p[full] = np.sqrt(1.0 - v[full] ** 2)
+    chi0 = rng.uniform(0.0, math.pi, n_src)
+    rm = rng.normal(0.0, 20.0, n_src)
+    lam2 = (299792458.0 / np.asarray(freqs, dtype=np.float64)) ** 2
+    chi = chi0[None, :] + rm[None, :] * lam2[:, None]
+    st = np.empty((4, n_freq, n_src))
+    st[0] = flux
+    st[1] = flux * p[None, :] * np.cos(2.0 * chi)
+    st[2] = flux * p[None, :] * np.sin(2.0 * chi)
+    st[3] = flux * v[None, :]
+    minus_q = rng.uniform(size=n_src) < frac_minus_q
+    st[1][:, minus_q] = -flux[:, minus_q]
+    st[2][:, minus_q] = 0.0
+    st[3][:, minus_q] = 0.0
+    return st
+
+
 def dipole_modulated_sphere(rng: np.random.Generator, n: int, amp: float):
     """Directions drawn by rejection from a density proportional to 1 + amp * x.
 
