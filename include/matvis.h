@@ -96,6 +96,12 @@ typedef struct {
 #define MATVIS_FLAG_NO_GRAPH 1 /* launch kernels directly instead of replaying a captured hipGraph */
 #define MATVIS_FLAG_UNFUSED 2  /* FP32 / BF16X3: write Z to device memory in a separate step
                                   (Alg. 2 step (iv)) instead of forming it inside the product */
+#define MATVIS_FLAG_POLARISED_SKY 4 /* src_flux holds all four Stokes parameters per source and
+                                       channel: the brightness matrix of Sec. 2.1,
+                                       C = [[I + Q, U + iV], [U - iV, I - Q]] over the beam's two
+                                       E-field axes, enters Eq. (matvistensorprod) through
+                                       Z = A F M with M M^H = C (Eq. fullz; M is the lower
+                                       Cholesky factor).  Needs n_ax = 2. */
 
 /* Create a context on the current HIP device and allocate all scratch for the
  * capacities in *cfg.  Returns MATVIS_EINVAL for inconsistent sizes (n_feed or
@@ -113,7 +119,10 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out);
  *             Eq. (rotation) is built on the device with hour angle H = -LST.
  *   src_radec [2][n_src] double: row 0 right ascension, row 1 declination
  *             (Eq. xeq is evaluated on the device).  n_src <= max_src.
- *   src_flux  [n_freq][n_src] double, Stokes I per channel, >= 0 (input I).
+ *   src_flux  [n_freq][n_src] double, Stokes I per channel, >= 0 (input I);
+ *             with MATVIS_FLAG_POLARISED_SKY [4][n_freq][n_src]: I, Q, U, V per
+ *             channel, physical (I >= sqrt(Q^2 + U^2 + V^2), checked on the
+ *             device to a relative 1e-9 and reported as MATVIS_EDATA).
  *   beam_grid [n_beam][n_freq][n_feed][n_ax][n_za][n_az] complex, complex128
  *             when precision is FP64 else complex64; NULL for the surrogate.
  *   vis       [n_time][n_freq][n_ant][n_ant][n_feed][n_feed] complex,

@@ -32,6 +32,42 @@ struct Batch {
     int32_t n_inst;            // ntb * nfb
 };
 
+// Lower-triangular square root M (M M^H = C) of a source's brightness matrix
+// C = [[I + Q, U + iV], [U - iV, I - Q]] (Sec. 2.1): the Cholesky factor
+//   M = [[sqrt(I + Q), 0], [(U - iV) / sqrt(I + Q), sqrt(I - Q - (U^2 + V^2) / (I + Q))]],
+// and M = [[0, 0], [0, sqrt(I - Q)]] when I + Q = 0.  Unlike the closed form of
+// App. B (which divides by U - iV and by T) it exists for every physical source,
+// unpolarised and fully polarised ones included; an unpolarised source gives
+// M = sqrt(I) 1 exactly.  Rounding below zero under the last root is clamped.
+struct PolSqrt {
+    double m00, m10x, m10y, m11;
+};
+__device__ inline PolSqrt pol_sqrt(double si, double sq, double su, double sv) {
+    PolSqrt r;
+    const double c00 = si + sq;
+    if (c00 > 0.0) {
+        r.m00 = sqrt(c00);
+        r.m10x = su / r.m00;
+        r.m10y = -sv / r.m00;
+        const double d = (si - sq) - (su * su + sv * sv) / c00;
+        r.m11 = d > 0.0 ? sqrt(d) : 0.0;
+    } else {
+        r.m00 = r.m10x = r.m10y = 0.0;
+        const double d = si - sq;
+        r.m11 = d > 0.0 ? sqrt(d) : 0.0;
+    }
+    return r;
+}
+// One feed's row of A M (Eq. fullz): (a0, a1) = A[p][0], A[p][1] -> (A M)[p][0], (A M)[p][1].
+template <typename R>
+__device__ inline void apply_pol_sqrt(const PolSqrt &m, R a0x, R a0y, R a1x, R a1y, R &o0x, R &o0y, R &o1x, R &o1y) {
+    const R m00 = (R)m.m00, m10x = (R)m.m10x, m10y = (R)m.m10y, m11 = (R)m.m11;
+    o0x = a0x * m00 + (a1x * m10x - a1y * m10y);
+    o0y = a0y * m00 + (a1x * m10y + a1y * m10x);
+    o1x = a1x * m11;
+    o1y = a1y * m11;
+}
+
 // Device-side sky buffers of one time batch and one source chunk.
 struct SkyBufs {
     const double *xeq;  // [3][ld_xeq] unit vectors, Eq. (xeq)
@@ -61,9 +97,11 @@ struct SortBufs {
 hipError_t launch_xeq_sorted(const double *radec, int64_t n_src, int64_t ld, SortBufs sb, double *xeq, hipStream_t s);
 int64_t sort_hist_entries(int64_t max_src);
 hipError_t launch_rotmats(const double *lsts, int32_t n_time, double latitude, double *rot, hipStream_t s);
+// n_flux values of Stokes I are checked (>= 0, finite); with pol the four planes
+// [4][n_flux] are checked for a physical brightness matrix.
 hipError_t launch_prep_inputs(const double *antpos, int32_t n_ant, const int32_t *beam_idx, int32_t n_beam,
-                              const double *flux, int64_t n_flux, double *antc, int32_t *bidx, int32_t *flags,
-                              hipStream_t s);
+                              const double *flux, int64_t n_flux, int pol, double *antc, int32_t *bidx,
+                              int32_t *flags, hipStream_t s);
 hipError_t launch_sky(const SkyBufs &b, int32_t t0, int32_t ntb, int64_t c0, int64_t nsrc_chunk, hipStream_t s);
 
 // ---- beam (kernels_beam.hip) -----------------------------------------------
@@ -80,8 +118,12 @@ struct InterpArgs {
     int64_t max_m;           // grid size along sources
     // optional: multiply by sqrt(I) of the source (B = sqrt(I) A for the fused product)
     const int32_t *idx;      // [nslots][ld_src] absolute source indices, or null
-    const double *flux;      // [n_freq][n_src]
+    const double *flux;      // [n_freq][n_src], or the Stokes planes [4][n_freq][n_src] when pol
     int64_t n_src;
+    // polarised sky: B = A M with M of pol_sqrt (needs n_ax = 2 and idx set);
+    // Stokes plane s starts at flux + s * stokes_stride
+    int32_t pol;
+    int64_t stokes_stride;
 };
 hipError_t launch_interp(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s);
 // Channel-interleaved copy of the beam grids, T[b][za][az][f][c] (c = feed * n_ax + axis),
@@ -103,7 +145,7 @@ struct ZformArgs {
     const double *antc;      // [n_ant][3] centred ENU
     const int32_t *bidx;     // [n_ant] sanitised beam index
     const double *freqs;     // [n_freq]
-    const double *flux;      // [n_freq][n_src]
+    const double *flux;      // [n_freq][n_src], or null when A already carries the sky (B = sqrt(I) A or A M)
     int64_t n_src;
     const int32_t *idx;      // [nslots][ld_src]
     const double *s_hat;     // [nslots][3][ld_src]

@@ -23,11 +23,28 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs a, Batch bt) {
     const int ncomp = a.n_feed * a.n_ax;
     const int64_t plane = (int64_t)a.n_za * a.n_az;
     C *out = (C *)a.A + (int64_t)inst * a.n_beam * ncomp * a.ld_src + m;
-    const R sq = a.idx ? (R)sqrt(a.flux[(int64_t)f * a.n_src + a.idx[(int64_t)slot * a.ld_src + m]]) : R(1);
+    R sq = R(1);
+    PolSqrt pm{};
+    if (a.idx) {
+        const int64_t o = (int64_t)f * a.n_src + a.idx[(int64_t)slot * a.ld_src + m];
+        if (a.pol)
+            pm = pol_sqrt(a.flux[o], a.flux[o + a.stokes_stride], a.flux[o + 2 * a.stokes_stride],
+                          a.flux[o + 3 * a.stokes_stride]);
+        else
+            sq = (R)sqrt(a.flux[o]);
+    }
     for (int b = 0; b < a.n_beam; b++) {
         const C *g = (const C *)a.grid + (int64_t)(b * a.n_freq_grid + f) * ncomp * plane;
-        interp_point<R, MODE>(g, plane, ncomp, a.n_za, a.n_az, a.dza, a.daz, za, az, sq, out + (int64_t)b * ncomp * a.ld_src,
-                              a.ld_src);
+        C *ob = out + (int64_t)b * ncomp * a.ld_src;
+        interp_point<R, MODE>(g, plane, ncomp, a.n_za, a.n_az, a.dza, a.daz, za, az, sq, ob, a.ld_src);
+        if (a.pol)  // B = A M, feed by feed (n_ax = 2: components 2 p and 2 p + 1)
+            for (int p = 0; p < a.n_feed; p++) {
+                const C a0 = ob[(int64_t)(2 * p) * a.ld_src], a1 = ob[(int64_t)(2 * p + 1) * a.ld_src];
+                C o0, o1;
+                apply_pol_sqrt<R>(pm, a0.x, a0.y, a1.x, a1.y, o0.x, o0.y, o1.x, o1.y);
+                ob[(int64_t)(2 * p) * a.ld_src] = o0;
+                ob[(int64_t)(2 * p + 1) * a.ld_src] = o1;
+            }
     }
 }
 
@@ -144,8 +161,16 @@ __global__ void __launch_bounds__(256) k_interp_tf(InterpArgs a, Batch bt) {
     for (int p = 0; p < PER; p++) {
         const int q = (e0 + p) / NCOMP;
         sq[p] = R(1);
-        if (a.idx && q < nf)
+        if (a.idx && q < nf && !a.pol)
             sq[p] = (R)sqrt(a.flux[(int64_t)(fabs0 + q) * a.n_src + a.idx[(int64_t)slot * a.ld_src + m]]);
+    }
+    // polarised sky: the square root of this lane's channel's brightness matrix
+    // (NCOMP is even then, so a lane's elements belong to one channel)
+    PolSqrt pm{};
+    if (a.pol && e0 / NCOMP < nf) {
+        const int64_t o = (int64_t)(fabs0 + e0 / NCOMP) * a.n_src + a.idx[(int64_t)slot * a.ld_src + m];
+        pm = pol_sqrt(a.flux[o], a.flux[o + a.stokes_stride], a.flux[o + 2 * a.stokes_stride],
+                      a.flux[o + 3 * a.stokes_stride]);
     }
     for (int b = 0; b < a.n_beam; b++) {
         const C *T = (const C *)a.grid + (int64_t)b * a.n_za * a.n_az * F + (int64_t)fabs0 * NCOMP + e0;
@@ -174,6 +199,31 @@ __global__ void __launch_bounds__(256) k_interp_tf(InterpArgs a, Batch bt) {
                     }
                 }
             }
+        }
+        if (a.pol) {
+            // B = A M per feed: components 2 p + k, k = 0, 1 of one channel
+            if constexpr (PER == 2) {
+                R o0x, o0y, o1x, o1y;
+                apply_pol_sqrt<R>(pm, ax[0], ay[0], ax[1], ay[1], o0x, o0y, o1x, o1y);
+                ax[0] = o0x;
+                ay[0] = o0y;
+                ax[1] = o1x;
+                ay[1] = o1y;
+            } else {
+                // one component per lane: the other axis of the feed is in the neighbouring lane
+                const R px = __shfl_xor(ax[0], 1), py = __shfl_xor(ay[0], 1);
+                R o0x, o0y, o1x, o1y;
+                if ((e0 & 1) == 0) {
+                    apply_pol_sqrt<R>(pm, ax[0], ay[0], px, py, o0x, o0y, o1x, o1y);
+                    ax[0] = o0x;
+                    ay[0] = o0y;
+                } else {
+                    apply_pol_sqrt<R>(pm, px, py, ax[0], ay[0], o0x, o0y, o1x, o1y);
+                    ax[0] = o1x;
+                    ay[0] = o1y;
+                }
+            }
+            for (int p = 0; p < PER; p++) sq[p] = R(1);
         }
         for (int p = 0; p < PER; p++) {
             const int e = e0 + p, q = e / NCOMP, c = e % NCOMP;

@@ -360,6 +360,8 @@ struct InferArgs {
     const int32_t *idx;
     const double *flux;
     int64_t n_src;
+    int32_t pol;           // polarised sky: flux holds the Stokes planes stokes_stride apart
+    int64_t stokes_stride;
     const double *freqs;
     int64_t ld_src;
     void *A;               // complex64 [inst][1][n_feed][n_ax][ld_src] = sqrt(I) J
@@ -511,14 +513,26 @@ __global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
                 const int64_t m = m0 + 16 * pt + l16;
                 if (m >= nrow) continue;
                 if (SIM) {
-                    const float sq =
-                        a.idx ? (float)sqrt(a.flux[(int64_t)f * a.n_src + a.idx[(int64_t)slot * a.ld_src + m]]) : 1.0f;
+                    float sq = 1.0f;
+                    f32x4 J = D[pt];  // (re, im) of J[lk][0], J[lk][1]
+                    if (a.idx) {
+                        const int64_t o = (int64_t)f * a.n_src + a.idx[(int64_t)slot * a.ld_src + m];
+                        if (a.pol) {
+                            const PolSqrt pm = pol_sqrt(a.flux[o], a.flux[o + a.stokes_stride],
+                                                        a.flux[o + 2 * a.stokes_stride], a.flux[o + 3 * a.stokes_stride]);
+                            float o0x, o0y, o1x, o1y;
+                            apply_pol_sqrt<float>(pm, J[0], J[1], J[2], J[3], o0x, o0y, o1x, o1y);
+                            J = f32x4{o0x, o0y, o1x, o1y};
+                        } else {
+                            sq = (float)sqrt(a.flux[o]);
+                        }
+                    }
                     // component (p, k) = (lk, cc) of the n_feed x n_ax Jones matrix
 #pragma unroll
                     for (int cc = 0; cc < 2; cc++) {
                         if (lk >= a.n_feed || cc >= a.n_ax) continue;
                         float2 *dst = (float2 *)a.A + ((int64_t)inst * a.n_feed * a.n_ax + lk * a.n_ax + cc) * a.ld_src + m;
-                        *dst = make_float2(sq * D[pt][2 * cc], sq * D[pt][2 * cc + 1]);
+                        *dst = make_float2(sq * J[2 * cc], sq * J[2 * cc + 1]);
                     }
                 } else {
                     *(f32x4 *)(a.out + m * kOut + 4 * lk) = D[pt];
@@ -654,8 +668,9 @@ hipError_t infer_plain(const float *P, const __bf16 *Wb, const float *x, int64_t
 }
 
 hipError_t infer_sim(const float *P, const __bf16 *Wb, double nu0, double nu1, const double *za_az,
-                     const int32_t *count, const int32_t *idx, const double *flux, int64_t n_src, const double *freqs,
-                     int64_t ld_src, int64_t max_m, void *A, int n_feed, int n_ax, const Batch &bt, hipStream_t s) {
+                     const int32_t *count, const int32_t *idx, const double *flux, int64_t n_src, int pol,
+                     int64_t stokes_stride, const double *freqs, int64_t ld_src, int64_t max_m, void *A, int n_feed,
+                     int n_ax, const Batch &bt, hipStream_t s) {
     if (bt.n_inst <= 0 || max_m <= 0) return hipSuccess;
     if (n_feed > 2 || n_ax > 2) return hipErrorInvalidValue;
     InferArgs a{};
@@ -668,6 +683,8 @@ hipError_t infer_sim(const float *P, const __bf16 *Wb, double nu0, double nu1, c
     a.idx = idx;
     a.flux = flux;
     a.n_src = n_src;
+    a.pol = pol;
+    a.stokes_stride = stokes_stride;
     a.freqs = freqs;
     a.ld_src = ld_src;
     a.A = A;

@@ -227,11 +227,17 @@ __global__ void k_prep_ant(const double *__restrict__ antpos, int n_ant, const i
     if (bad) atomicOr(flags, bad);
 }
 
-__global__ void k_check_flux(const double *__restrict__ flux, int64_t n, int32_t *flags) {
+__global__ void k_check_flux(const double *__restrict__ flux, int64_t n, int pol, int32_t *flags) {
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double f = flux[i];
         if (!(f >= 0.0) || !isfinite(f)) bad = true;
+        if (pol) {
+            // a physical brightness matrix: Q^2 + U^2 + V^2 <= I^2 (relative 1e-9)
+            const double q = flux[n + i], u = flux[2 * n + i], v = flux[3 * n + i];
+            if (!isfinite(q) || !isfinite(u) || !isfinite(v) || !(q * q + u * u + v * v <= f * f * (1.0 + 1e-9)))
+                bad = true;
+        }
     }
     unsigned long long m = __ballot(bad);
     if (m && lane_id() == __ffsll((long long)m) - 1) atomicOr(flags, FLAG_BAD_FLUX);
@@ -368,14 +374,14 @@ hipError_t launch_rotmats(const double *lsts, int32_t n_time, double latitude, d
 }
 
 hipError_t launch_prep_inputs(const double *antpos, int32_t n_ant, const int32_t *beam_idx, int32_t n_beam,
-                              const double *flux, int64_t n_flux, double *antc, int32_t *bidx, int32_t *flags,
-                              hipStream_t s) {
+                              const double *flux, int64_t n_flux, int pol, double *antc, int32_t *bidx,
+                              int32_t *flags, hipStream_t s) {
     k_prep_ant<<<1, kSkyBlock, 0, s>>>(antpos, n_ant, beam_idx, n_beam, antc, bidx, flags);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || n_flux <= 0 || !flux) return e;
     int64_t blocks = (n_flux + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    k_check_flux<<<(unsigned)blocks, 256, 0, s>>>(flux, n_flux, flags);
+    k_check_flux<<<(unsigned)blocks, 256, 0, s>>>(flux, n_flux, pol, flags);
     return hipGetLastError();
 }
 

@@ -66,8 +66,11 @@ __global__ void __launch_bounds__(256) k_zform(ZformArgs a, Batch bt) {
         sx = sh[m];
         sy = sh[ld + m];
         sz = sh[2 * ld + m];
-        const int32_t n = a.idx[(int64_t)slot * ld + m];
-        sq = sqrt(a.flux[(int64_t)f * a.n_src + n]);
+        sq = 1.0;
+        if (a.flux) {  // else the beam step already carries the sky (polarised: A M)
+            const int32_t n = a.idx[(int64_t)slot * ld + m];
+            sq = sqrt(a.flux[(int64_t)f * a.n_src + n]);
+        }
     }
     const double nu_c = a.freqs[f] / kSpeedOfLight;
     const int ncomp = nf * nx;

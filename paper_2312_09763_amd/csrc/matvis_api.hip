@@ -149,6 +149,8 @@ matvis_status validate_cfg(const matvis_config *c, std::string &why) {
     if (c->n_ant <= 0) return why = "n_ant must be positive", MATVIS_EINVAL;
     if (c->n_feed != 1 && c->n_feed != 2) return why = "n_feed must be 1 or 2", MATVIS_EINVAL;
     if (c->n_ax != 1 && c->n_ax != 2) return why = "n_ax must be 1 or 2", MATVIS_EINVAL;
+    if ((c->flags & MATVIS_FLAG_POLARISED_SKY) && c->n_ax != 2)
+        return why = "a polarised sky needs the beam's two E-field axes (n_ax = 2)", MATVIS_EINVAL;
     if (c->n_beam <= 0) return why = "n_beam must be positive", MATVIS_EINVAL;
     if (c->max_src <= 0 || c->max_src > (int64_t)1 << 31) return why = "max_src out of range", MATVIS_EINVAL;
     if (c->max_time <= 0 || c->max_freq <= 0) return why = "max_time and max_freq must be positive", MATVIS_EINVAL;
@@ -354,9 +356,10 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                                const double *flux, const void *grid, void *vis, hipStream_t s) {
     const matvis_config &g = c->cfg;
     const int prec = g.precision;
+    const int pol = (g.flags & MATVIS_FLAG_POLARISED_SKY) ? 1 : 0;
     STEP(c, MATVIS_STEP_OTHER, s,
-         launch_prep_inputs(antpos, g.n_ant, beam_idx, g.n_beam, flux, (int64_t)n_freq * n_src, c->antc, c->bidx,
-                            c->flags, s));
+         launch_prep_inputs(antpos, g.n_ant, beam_idx, g.n_beam, flux, (int64_t)n_freq * n_src, pol, c->antc,
+                            c->bidx, c->flags, s));
     STEP(c, MATVIS_STEP_SKY, s,
          launch_xeq_sorted(radec, n_src, g.max_src, SortBufs{c->xeq_in, c->cell, c->cell_hist, c->perm}, c->xeq, s));
     if (c->gridT)
@@ -393,15 +396,20 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 ia.ld_src = c->chunk;
                 ia.A = c->A;
                 ia.max_m = ns;
-                if (c->fused) {
+                // The beam step carries the sky into B (sqrt(I) A, or A M for a polarised sky)
+                // whenever the product forms Z itself, and always for a polarised sky.
+                if (c->fused || pol) {
                     ia.idx = c->idx;
                     ia.flux = flux;
                     ia.n_src = n_src;
+                    ia.pol = pol;
+                    ia.stokes_stride = (int64_t)n_freq * n_src;
                 }
                 if (g.beam_mode == MATVIS_BEAM_SURROGATE)
                     STEP(c, MATVIS_STEP_BEAM, s,
                          mlp::infer_sim(c->sur_P, c->sur_Wb, c->sur_nu0, c->sur_nu1, c->za_az, c->count, ia.idx, flux,
-                                        n_src, freqs, c->chunk, ns, c->A, g.n_feed, g.n_ax, bt, s));
+                                        n_src, pol, ia.stokes_stride, freqs, c->chunk, ns, c->A, g.n_feed, g.n_ax,
+                                        bt, s));
                 else
                     STEP(c, MATVIS_STEP_BEAM, s,
                          c->gridT ? launch_interp_tf(prec, g.beam_mode, ia, bt, s)
@@ -457,7 +465,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 za.antc = c->antc;
                 za.bidx = c->bidx;
                 za.freqs = freqs;
-                za.flux = flux;
+                za.flux = pol ? nullptr : flux;  // a polarised sky is already in A
                 za.n_src = n_src;
                 za.idx = c->idx;
                 za.s_hat = c->s_hat;

@@ -25,6 +25,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 BILINEAR, BICUBIC, SURROGATE = 0, 1, 2
 FLAG_NO_GRAPH = 1
 FLAG_UNFUSED = 2
+FLAG_POLARISED_SKY = 4
 
 STEPS = ("sky", "beam", "zform", "herk", "reduce", "other")
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
@@ -139,12 +140,14 @@ class Config:
     use_graph: bool = True
     unfused: bool = False  # FP32 / BF16X3: separate Z-formation step (Z in device memory)
     ksplit: int = 0        # columns per product work item (multiple of 64); 0 = automatic
+    polarised_sky: bool = False  # src_flux is [4][n_freq][n_src] (I, Q, U, V); needs n_ax = 2
 
     def _c(self) -> _Config:
         return _Config(self.n_ant, self.n_feed, self.n_ax, self.n_beam, self.max_src, self.max_time, self.max_freq,
                        self.latitude_rad, PRECISIONS[self.precision], BEAM_MODES[self.beam_mode], self.n_za,
                        self.n_az, self.dza_rad, self.daz_rad, self.src_chunk, self.batch_time, self.batch_freq,
-                       (0 if self.use_graph else FLAG_NO_GRAPH) | (FLAG_UNFUSED if self.unfused else 0),
+                       (0 if self.use_graph else FLAG_NO_GRAPH) | (FLAG_UNFUSED if self.unfused else 0) |
+                       (FLAG_POLARISED_SKY if self.polarised_sky else 0),
                        self.ksplit)
 
 
@@ -211,7 +214,7 @@ class Context:
         _need(freqs, torch.float64, (n_freq,), "freqs")
         _need(lsts, torch.float64, (n_time,), "lsts")
         _need(src_radec, torch.float64, (2, n_src), "src_radec")
-        _need(src_flux, torch.float64, (n_freq, n_src), "src_flux")
+        _need(src_flux, torch.float64, (4, n_freq, n_src) if c.polarised_sky else (n_freq, n_src), "src_flux")
         if c.beam_mode == "surrogate":
             beam_grid = None  # the learned beam replaces the grid
         else:
@@ -419,11 +422,13 @@ def config_for(wl, precision: str = "fp32", **kw) -> Config:
     return Config(**args)
 
 
-def device_inputs(wl, precision: str = "fp32", device: str = "cuda"):
-    """Move a synthetic workload's arrays to the device in the ABI's dtypes."""
+def device_inputs(wl, precision: str = "fp32", device: str = "cuda", stokes=None):
+    """Move a synthetic workload's arrays to the device in the ABI's dtypes
+    (src_flux = stokes [4][n_freq][n_src] for a polarised sky when given)."""
     import numpy as np
     import torch
     cd = np.complex128 if precision == "fp64" else np.complex64
     t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(device)
     return dict(antpos=t(wl.antpos, np.float64), freqs=t(wl.freqs, np.float64), lsts=t(wl.lsts, np.float64),
-                src_radec=t(wl.radec, np.float64), src_flux=t(wl.flux, np.float64), beam_grid=t(wl.beam, cd))
+                src_radec=t(wl.radec, np.float64), src_flux=t(wl.flux if stokes is None else stokes, np.float64),
+                beam_grid=t(wl.beam, cd))
