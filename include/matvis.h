@@ -135,6 +135,56 @@ matvis_status matvis_simulate(matvis_ctx *ctx, const double *antpos, const int32
                               int32_t n_freq, const double *lsts, int32_t n_time, const double *src_radec,
                               int64_t n_src, const double *src_flux, const void *beam_grid, void *vis, void *stream);
 
+/* ---- Redundancy-aware product (App. A) ----------------------------------
+ * For arrays with many redundant baselines, only one representative pair per
+ * redundant group is needed.  V'_x = A_x B_x^H (Eq. Vpx) over a few
+ * sub-matrices whose rows A_x (first antennas) and B_x (second antennas) are
+ * chosen by the appendix's density heuristic covers every requested pair at a
+ * fraction of the full product's size.
+ *
+ * matvis_redundant_groups (host only, no device work): baselines are the
+ * pairs (i, j), i <= j, in lexicographic order, n_ant (n_ant + 1) / 2 of
+ * them; two are redundant when their antennas carry the same beams
+ * (beam_idx, NULL = all 0) and x_i - x_j agree to within tol_m metres in every
+ * component.  group[p] is the group of pair p (pair order), rep_a / rep_b the
+ * first pair of each group (capacity n_ant (n_ant + 1) / 2), *n_unique the
+ * number of groups.  Host pointers.  MATVIS_EINVAL for NULL pointers,
+ * n_ant outside [1, 8192], tol_m <= 0 or non-finite positions. */
+matvis_status matvis_redundant_groups(const double *antpos, const int32_t *beam_idx, int32_t n_ant, double tol_m,
+                                      int32_t *group, int32_t *rep_a, int32_t *rep_b, int32_t *n_unique);
+
+/* The appendix's heuristic for n_sub sub-matrices over the pairs (pair_a[u],
+ * pair_b[u]) (host only): alpha [n_ant] receives the first antennas ordered
+ * by multiplicity (descending, ties by index; *n_alpha of them), sizes
+ * [n_sub] the number of them in each sub-matrix and density [n_sub] each
+ * sub-matrix's covered-pair density; *n_sub_out <= n_sub is the count used
+ * (at most *n_alpha). */
+matvis_status matvis_submatrix_plan(const int32_t *pair_a, const int32_t *pair_b, int32_t n_pair, int32_t n_ant,
+                                    int32_t n_sub, int32_t *alpha, int32_t *sizes, double *density, int32_t *n_alpha,
+                                    int32_t *n_sub_out);
+
+/* Plan the sub-matrix product for the pairs (pair_a[u], pair_b[u]) (host
+ * arrays, antennas in [0, n_ant); any pairs, usually the representatives of
+ * matvis_redundant_groups) with n_sub sub-matrices, and upload the plan to
+ * the context's device.  Needs Z in device memory (precision FP64, or FP32
+ * with MATVIS_FLAG_UNFUSED): MATVIS_EUNSUPPORTED otherwise.  Allocates the
+ * plan's scratch (so call it outside graph capture); replaces an earlier
+ * plan.  *size_out (may be NULL) receives the total sub-matrix size
+ * sum_x |A_x| |B_x| in antenna pairs. */
+matvis_status matvis_set_pairs(matvis_ctx *ctx, const int32_t *pair_a, const int32_t *pair_b, int32_t n_pair,
+                               int32_t n_sub, int64_t *size_out);
+
+/* matvis_simulate for the planned pairs only: the same inputs, and
+ *   vis_pairs [n_time][n_freq][n_pair][n_feed][n_feed] complex (complex128 on
+ *             FP64, else complex64), vis_pairs[t][f][u][p][q] = V[(a_u,p),(b_u,q)]
+ *             of matvis_simulate.
+ * Steps (i)-(iv) as in matvis_simulate, then the sub-matrix product and a
+ * fixed-order FP64 sum of its k-splits.  MATVIS_ESTATE without a plan. */
+matvis_status matvis_simulate_pairs(matvis_ctx *ctx, const double *antpos, const int32_t *beam_idx,
+                                    const double *freqs, int32_t n_freq, const double *lsts, int32_t n_time,
+                                    const double *src_radec, int64_t n_src, const double *src_flux,
+                                    const void *beam_grid, void *vis_pairs, void *stream);
+
 /* Synchronise the last stream used and report deferred device-side errors:
  * MATVIS_EDATA for invalid input values, MATVIS_EHIP for asynchronous HIP
  * failures.  Clears the device error flags. */

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace mv {
 
@@ -218,6 +219,51 @@ hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s);
 int herk_fused_occupancy(int prec);
 // product kernel launch_herk_fused picks (a matvis_product_path value, never Z_IN_HBM)
 int fused_path(int prec, int n_feed, int n_ax, int n_beam, int n_ant, int n_rows_pad);
+
+// Redundancy-aware sub-matrix product (App. A, Eq. Vpx) on Z in device memory,
+// FP64 and FP32 (kernels_herk.hip).  Tiles are herk_super_tile(prec) square.
+struct SubmatArgs {
+    const void *Z;           // [n_inst][Np][ldz] as written by launch_zform
+    int64_t ldz;
+    int64_t inst_stride;     // elements between instances
+    const int32_t *rows;     // [n_tiles][2][ST]: the tile's A rows then B rows of Z, -1 = padding
+    int32_t n_tiles;
+    const int32_t *count;    // [nslots] visible counts (K = n_ax * count)
+    int64_t fixed_k;
+    int32_t n_ax, nfb, n_inst;
+    int64_t ksplit;          // columns per k-split (multiple of 16)
+    int32_t max_splits;
+    void *part;              // [n_inst][max_splits][n_tiles][ST][ST] complex partials
+};
+hipError_t launch_submat(int prec, const SubmatArgs &a, hipStream_t s);
+struct SubmatReduceArgs {
+    const void *part;
+    int32_t n_tiles, max_splits, st;
+    const int32_t *loc;      // [n_pair][n_feed][n_feed][2]: tile, r * ST + c
+    int32_t n_pair, n_feed;
+    const int32_t *count;
+    int64_t fixed_k;
+    int32_t n_ax, nfb, n_inst;
+    int64_t ksplit;
+    double *vacc;            // [n_inst][n_pair][n_feed][n_feed] complex128 running sums
+    int32_t first, last;
+    void *out;               // [n_time][n_freq][n_pair][n_feed][n_feed]
+    int32_t n_freq_total;
+    Batch bt;
+};
+hipError_t launch_submat_reduce(int prec, const SubmatReduceArgs &a, hipStream_t s);
+
+// Host side (redundancy.hip): baseline redundancy groups and the App. A plan.
+namespace red {
+int64_t groups(const double *antpos, const int32_t *beam_idx, int n_ant, double tol, int32_t *group, int32_t *rep_a,
+               int32_t *rep_b);
+struct Plan {
+    std::vector<int> alpha, sizes;           // ordered first antennas, sub-matrix sizes
+    std::vector<std::vector<int>> A, B;      // antennas of A_x (alpha order), of B_x (ascending)
+    std::vector<double> density;
+};
+Plan plan(const int32_t *pa, const int32_t *pb, int n_pair, int n_ant, int n_sub);
+}  // namespace red
 
 struct ReduceArgs {
     const void *part;

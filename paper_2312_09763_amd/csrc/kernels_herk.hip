@@ -144,6 +144,88 @@ __device__ inline u32x4 bf16_rot(u32x4 v) {
     return r;
 }
 
+// One KC-deep stage of a WT x WT wave tile: rows arow.. of the staged A block
+// against rows brow.. of the staged B block (both in LDS, row stride RS).
+template <int PREC, typename Acc>
+__device__ __forceinline__ void mma_stage(const unsigned char *lds, int arow, int brow, int l16, int lk, bool on_diag,
+                                          Acc (&acc_re)[HD<PREC>::TI][HD<PREC>::TI],
+                                          Acc (&acc_im)[HD<PREC>::TI][HD<PREC>::TI]) {
+    typedef HD<PREC> D;
+    constexpr int KC = D::KC, RS = D::RS, TI = D::TI;
+    if constexpr (PREC == PB3) {
+        u32x4 ah[TI], al[TI], bh[TI], bl[TI];
+#pragma unroll
+        for (int i = 0; i < TI; i++) {
+            const unsigned char *p = lds + (arow + 16 * i + l16) * RS + lk * 16;
+            ah[i] = *(const u32x4 *)p;
+            al[i] = *(const u32x4 *)(p + KC * 4);
+        }
+#pragma unroll
+        for (int j = 0; j < TI; j++) {
+            const unsigned char *p = lds + (brow + 16 * j + l16) * RS + lk * 16;
+            bh[j] = *(const u32x4 *)p;
+            bl[j] = *(const u32x4 *)(p + KC * 4);
+        }
+#pragma unroll
+        for (int i = 0; i < TI; i++) {
+            const u32x4 wh = bf16_rot(ah[i]), wl = bf16_rot(al[i]);
+            const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah[i]);
+            const bf16x8 Al = __builtin_bit_cast(bf16x8, al[i]);
+            const bf16x8 Wh = __builtin_bit_cast(bf16x8, wh);
+            const bf16x8 Wl = __builtin_bit_cast(bf16x8, wl);
+#pragma unroll
+            for (int j = 0; j < TI; j++) {
+                const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[j]);
+                const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl[j]);
+                acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh, acc_re[i][j], 0, 0, 0);
+                acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl, acc_re[i][j], 0, 0, 0);
+                acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, acc_re[i][j], 0, 0, 0);
+                acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wh, Bh, acc_im[i][j], 0, 0, 0);
+                acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wh, Bl, acc_im[i][j], 0, 0, 0);
+                acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wl, Bh, acc_im[i][j], 0, 0, 0);
+                // On the output diagonal the dropped lo lo^H term is a sum of
+                // |lo|^2, a one-signed bias of relative size ~2^-16; add it
+                // there (elsewhere it averages out and is left out).
+                if (on_diag && i == j) {
+                    acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bl, acc_re[i][j], 0, 0, 0);
+                    acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wl, Bl, acc_im[i][j], 0, 0, 0);
+                }
+            }
+        }
+    } else {
+        typedef typename std::conditional<PREC == P64, double2, float2>::type C;
+        typedef typename std::conditional<PREC == P64, double, float>::type R;
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            C av[TI], bv[TI];
+#pragma unroll
+            for (int i = 0; i < TI; i++)
+                av[i] = *(const C *)(lds + (arow + 16 * i + l16) * RS + (kk + lk) * D::EB);
+#pragma unroll
+            for (int j = 0; j < TI; j++)
+                bv[j] = *(const C *)(lds + (brow + 16 * j + l16) * RS + (kk + lk) * D::EB);
+#pragma unroll
+            for (int i = 0; i < TI; i++) {
+                const R nre = -av[i].x;
+#pragma unroll
+                for (int j = 0; j < TI; j++) {
+                    if constexpr (PREC == P64) {
+                        acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, acc_re[i][j], 0, 0, 0);
+                        acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].y, acc_re[i][j], 0, 0, 0);
+                        acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, acc_im[i][j], 0, 0, 0);
+                        acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nre, bv[j].y, acc_im[i][j], 0, 0, 0);
+                    } else {
+                        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, acc_re[i][j], 0, 0, 0);
+                        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, acc_re[i][j], 0, 0, 0);
+                        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].x, acc_im[i][j], 0, 0, 0);
+                        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nre, bv[j].y, acc_im[i][j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <int PREC>
 __global__ void __launch_bounds__(256, 2) k_herk(HerkArgs a) {
     typedef HD<PREC> D;
@@ -241,80 +323,7 @@ __global__ void __launch_bounds__(256, 2) k_herk(HerkArgs a) {
             store();
             __syncthreads();
             if (k0 + KC < ke) load(k0 + KC);
-            if (active) {
-                if constexpr (PREC == PB3) {
-                    u32x4 ah[TI], al[TI], bh[TI], bl[TI];
-#pragma unroll
-                    for (int i = 0; i < TI; i++) {
-                        const unsigned char *p = lds + (arow + 16 * i + l16) * RS + lk * 16;
-                        ah[i] = *(const u32x4 *)p;
-                        al[i] = *(const u32x4 *)(p + KC * 4);
-                    }
-#pragma unroll
-                    for (int j = 0; j < TI; j++) {
-                        const unsigned char *p = lds + (brow + 16 * j + l16) * RS + lk * 16;
-                        bh[j] = *(const u32x4 *)p;
-                        bl[j] = *(const u32x4 *)(p + KC * 4);
-                    }
-#pragma unroll
-                    for (int i = 0; i < TI; i++) {
-                        const u32x4 wh = bf16_rot(ah[i]), wl = bf16_rot(al[i]);
-                        const bf16x8 Ah = __builtin_bit_cast(bf16x8, ah[i]);
-                        const bf16x8 Al = __builtin_bit_cast(bf16x8, al[i]);
-                        const bf16x8 Wh = __builtin_bit_cast(bf16x8, wh);
-                        const bf16x8 Wl = __builtin_bit_cast(bf16x8, wl);
-#pragma unroll
-                        for (int j = 0; j < TI; j++) {
-                            const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh[j]);
-                            const bf16x8 Bl = __builtin_bit_cast(bf16x8, bl[j]);
-                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh, acc_re[i][j], 0, 0, 0);
-                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl, acc_re[i][j], 0, 0, 0);
-                            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, acc_re[i][j], 0, 0, 0);
-                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wh, Bh, acc_im[i][j], 0, 0, 0);
-                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wh, Bl, acc_im[i][j], 0, 0, 0);
-                            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wl, Bh, acc_im[i][j], 0, 0, 0);
-                            // On the output diagonal the dropped lo lo^H term is a sum of
-                            // |lo|^2, a one-signed bias of relative size ~2^-16; add it
-                            // there (elsewhere it averages out and is left out).
-                            if (on_diag && i == j) {
-                                acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bl, acc_re[i][j], 0, 0, 0);
-                                acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wl, Bl, acc_im[i][j], 0, 0, 0);
-                            }
-                        }
-                    }
-                } else {
-                    typedef typename std::conditional<PREC == P64, double2, float2>::type C;
-                    typedef typename std::conditional<PREC == P64, double, float>::type R;
-#pragma unroll
-                    for (int kk = 0; kk < KC; kk += 4) {
-                        C av[TI], bv[TI];
-#pragma unroll
-                        for (int i = 0; i < TI; i++)
-                            av[i] = *(const C *)(lds + (arow + 16 * i + l16) * RS + (kk + lk) * D::EB);
-#pragma unroll
-                        for (int j = 0; j < TI; j++)
-                            bv[j] = *(const C *)(lds + (brow + 16 * j + l16) * RS + (kk + lk) * D::EB);
-#pragma unroll
-                        for (int i = 0; i < TI; i++) {
-                            const R nre = -av[i].x;
-#pragma unroll
-                            for (int j = 0; j < TI; j++) {
-                                if constexpr (PREC == P64) {
-                                    acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, acc_re[i][j], 0, 0, 0);
-                                    acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].y, acc_re[i][j], 0, 0, 0);
-                                    acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, acc_im[i][j], 0, 0, 0);
-                                    acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nre, bv[j].y, acc_im[i][j], 0, 0, 0);
-                                } else {
-                                    acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, acc_re[i][j], 0, 0, 0);
-                                    acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, acc_re[i][j], 0, 0, 0);
-                                    acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].x, acc_im[i][j], 0, 0, 0);
-                                    acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nre, bv[j].y, acc_im[i][j], 0, 0, 0);
-                                }
-                            }
-                        }
-                    }
-                }
-            }
+            if (active) mma_stage<PREC>(lds, arow, brow, l16, lk, on_diag, acc_re, acc_im);
         }
 
         if (active) {
@@ -339,6 +348,124 @@ __global__ void __launch_bounds__(256, 2) k_herk(HerkArgs a) {
         }
         __syncthreads();  // LDS is reused by the next item
     }
+}
+
+// Redundancy-aware product (App. A, Eq. Vpx): V'_x = A_x B_x^H with A_x, B_x
+// gathered rows of Z.  One workgroup per (instance, ST x ST tile of a
+// sub-matrix, k-split); the tile's rows are read through its two row lists
+// straight from Z (a gather fused into the stage loads: no copy of A_x or
+// B_x is formed), and the raw tile goes to its own partial slot.
+template <int PREC>
+__global__ void __launch_bounds__(256, 2) k_submat(SubmatArgs a) {
+    typedef HD<PREC> D;
+    constexpr int ST = D::ST, WT = D::WT, KC = D::KC, RS = D::RS, CPR = D::CPR, NLD = D::NLD, TI = D::TI;
+    typedef typename std::conditional<PREC == P64, f64x4, f32x4>::type Acc;
+    typedef typename std::conditional<PREC == P64, double2, float2>::type PartT;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[D::LDS];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int wr = wave >> 1, wc = wave & 1, l16 = lane & 15, lk = lane >> 4;
+    const int64_t item = blockIdx.x;
+    const int s = (int)(item % a.max_splits);
+    const int tile = (int)((item / a.max_splits) % a.n_tiles);
+    const int inst = (int)(item / ((int64_t)a.max_splits * a.n_tiles));
+    const int64_t K = inst_k(a.count, a.fixed_k, a.n_ax, a.nfb, inst);
+    const int64_t Kr = ((K + KC - 1) / KC) * KC;
+    const int64_t kb = (int64_t)s * a.ksplit;
+    if (kb >= Kr) return;  // an empty k-split: the reduction sums only ceil(K / ksplit) of them
+    const int64_t ke = kb + a.ksplit < Kr ? kb + a.ksplit : Kr;
+    const int32_t *rows = a.rows + (int64_t)tile * 2 * ST;
+    const char *zbase = (const char *)a.Z + (int64_t)inst * a.inst_stride * D::EB;
+    const int64_t ldzb = a.ldz * D::EB;
+
+    Acc acc_re[TI][TI], acc_im[TI][TI];
+    for (int i = 0; i < TI; i++)
+        for (int j = 0; j < TI; j++)
+            for (int e = 0; e < 4; e++) {
+                acc_re[i][j][e] = 0;
+                acc_im[i][j][e] = 0;
+            }
+    int grow[NLD];
+#pragma unroll
+    for (int j = 0; j < NLD; j++) {
+        const int lr = (tid + 256 * j) / CPR;
+        grow[j] = rows[lr];  // A rows for lr < ST, then B rows
+    }
+    u32x4 pre[NLD];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int j = 0; j < NLD; j++) {
+            const int c = (tid + 256 * j) % CPR;
+            pre[j] = u32x4{0u, 0u, 0u, 0u};
+            if (grow[j] >= 0) pre[j] = *(const u32x4 *)(zbase + grow[j] * ldzb + k0 * D::EB + c * 16);
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int j = 0; j < NLD; j++) {
+            const int q = tid + 256 * j;
+            *(u32x4 *)(lds + (q / CPR) * RS + (q % CPR) * 16) = pre[j];
+        }
+    };
+    const int arow = wr * WT, brow = ST + wc * WT;
+    if (kb < ke) load(kb);
+    for (int64_t k0 = kb; k0 < ke; k0 += KC) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (k0 + KC < ke) load(k0 + KC);
+        mma_stage<PREC>(lds, arow, brow, l16, lk, false, acc_re, acc_im);
+    }
+    PartT *P = (PartT *)a.part + (((int64_t)inst * a.max_splits + s) * a.n_tiles + tile) * ST * ST;
+#pragma unroll
+    for (int i = 0; i < TI; i++)
+#pragma unroll
+        for (int j = 0; j < TI; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                PartT v;
+                v.x = acc_re[i][j][e];
+                v.y = acc_im[i][j][e];
+                const int r = arow + 16 * i + (PREC == P64 ? 4 * e + lk : 4 * lk + e);
+                P[(int64_t)r * ST + wc * WT + 16 * j + l16] = v;
+            }
+}
+
+// V of every requested pair: the k-split partials of its tile element summed in
+// FP64 in split order, earlier source chunks carried in vacc.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_submat_reduce(SubmatReduceArgs a) {
+    typedef typename std::conditional<PREC == P64, double2, float2>::type C;
+    const int nf = a.n_feed;
+    const int64_t per_inst = (int64_t)a.n_pair * nf * nf;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= per_inst * a.n_inst) return;
+    const int inst = (int)(gid / per_inst);
+    const int64_t e = gid % per_inst;
+    const int64_t K = inst_k(a.count, a.fixed_k, a.n_ax, a.nfb, inst);
+    const int ns = (int)((K + a.ksplit - 1) / a.ksplit);
+    const int32_t tile = a.loc[2 * e], off = a.loc[2 * e + 1];
+    const int ST2 = a.st * a.st;
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < ns; s++) {
+        const C v = ((const C *)a.part)[(((int64_t)inst * a.max_splits + s) * a.n_tiles + tile) * ST2 + off];
+        re += (double)v.x;
+        im += (double)v.y;
+    }
+    double2 *acc = (double2 *)a.vacc + (int64_t)inst * per_inst + e;
+    if (!a.first) {
+        const double2 o = *acc;
+        re += o.x;
+        im += o.y;
+    }
+    if (!a.last) {
+        *acc = make_double2(re, im);
+        return;
+    }
+    const int t = a.bt.t0 + inst / a.bt.nfb, f = a.bt.f0 + inst % a.bt.nfb;
+    C out;
+    out.x = re;
+    out.y = im;
+    ((C *)a.out)[((int64_t)t * a.n_freq_total + f) * per_inst + e] = out;
 }
 
 // Fixed-order sum of the k-split partials, Hermitian fill and the write of the
@@ -419,6 +546,31 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(ReduceArgs a) {
 }  // namespace
 
 int herk_super_tile(int prec) { return prec == P64 ? HT<P64>::ST : HT<P32>::ST; }
+
+hipError_t launch_submat(int prec, const SubmatArgs &a, hipStream_t s) {
+    const int64_t items = (int64_t)a.n_inst * a.n_tiles * a.max_splits;
+    if (items <= 0) return hipSuccess;
+    if (prec == P64)
+        k_submat<P64><<<(unsigned)items, 256, 0, s>>>(a);
+    else if (prec == P32)
+        k_submat<P32><<<(unsigned)items, 256, 0, s>>>(a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_submat_reduce(int prec, const SubmatReduceArgs &a, hipStream_t s) {
+    const int64_t n = (int64_t)a.n_inst * a.n_pair * a.n_feed * a.n_feed;
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (prec == P64)
+        k_submat_reduce<P64><<<g, 256, 0, s>>>(a);
+    else if (prec == P32)
+        k_submat_reduce<P32><<<g, 256, 0, s>>>(a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 int herk_occupancy(int prec) {
     int nb = 1;

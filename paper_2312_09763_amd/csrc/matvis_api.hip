@@ -80,6 +80,15 @@ struct matvis_ctx {
     void *gridT = nullptr;      // channel-interleaved beam grids (grid beam modes, n_za >= 4)
     double sur_nu0 = 0, sur_nu1 = 1;
     bool sur_set = false;
+
+    // redundancy-aware sub-matrix product (matvis_set_pairs)
+    bool pr_set = false;
+    int32_t pr_n = 0, pr_tiles = 0;
+    int64_t pr_size = 0;
+    int32_t *pr_rows = nullptr;  // [tiles][2][ST] Z rows
+    int32_t *pr_loc = nullptr;   // [n_pair][nf][nf][2]
+    void *pr_part = nullptr;     // [B_cap][max_splits][tiles][ST][ST]
+    double *pr_vacc = nullptr;   // [B_cap][n_pair][nf][nf] complex128
 };
 
 namespace {
@@ -353,7 +362,7 @@ namespace {
 // Enqueue the whole simulate sequence on stream s (no host waits).
 matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_t *beam_idx, const double *freqs,
                                int32_t n_freq, const double *lsts, int32_t n_time, const double *radec, int64_t n_src,
-                               const double *flux, const void *grid, void *vis, hipStream_t s) {
+                               const double *flux, const void *grid, void *vis, hipStream_t s, bool pairs = false) {
     const matvis_config &g = c->cfg;
     const int prec = g.precision;
     const int pol = (g.flags & MATVIS_FLAG_POLARISED_SKY) ? 1 : 0;
@@ -434,7 +443,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 ha.kcols = c->work + 2 * B_cap + 1;
                 ha.balance_grid = c->fused ? c->fused_grid : 0;
                 ha.grid = c->herk_grid;
-                STEP(c, MATVIS_STEP_OTHER, s, launch_worklist(prec, ha, c->fused ? 1 : 0, s));
+                if (!pairs) STEP(c, MATVIS_STEP_OTHER, s, launch_worklist(prec, ha, c->fused ? 1 : 0, s));
 
                 if (c->fused) {
                     FusedArgs fa{};
@@ -483,7 +492,45 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 za.max_m = (round_up(g.n_ax * ns, kColPad) + g.n_ax - 1) / g.n_ax;
                 if (!c->fused) {
                     STEP(c, MATVIS_STEP_ZFORM, s, launch_zform(prec, za, bt, s));
-                    STEP(c, MATVIS_STEP_HERK, s, launch_herk(prec, ha, s));
+                    if (!pairs) STEP(c, MATVIS_STEP_HERK, s, launch_herk(prec, ha, s));
+                }
+                if (pairs) {
+                    // App. A: only the planned sub-matrices, then the requested pairs
+                    SubmatArgs sa{};
+                    sa.Z = c->Z;
+                    sa.ldz = c->ldz;
+                    sa.inst_stride = (int64_t)c->Np * c->ldz;
+                    sa.rows = c->pr_rows;
+                    sa.n_tiles = c->pr_tiles;
+                    sa.count = c->count;
+                    sa.n_ax = g.n_ax;
+                    sa.nfb = nfb;
+                    sa.n_inst = bt.n_inst;
+                    sa.ksplit = c->ksplit;
+                    sa.max_splits = c->max_splits;
+                    sa.part = c->pr_part;
+                    STEP(c, MATVIS_STEP_HERK, s, launch_submat(prec, sa, s));
+                    SubmatReduceArgs sr{};
+                    sr.part = c->pr_part;
+                    sr.n_tiles = c->pr_tiles;
+                    sr.max_splits = c->max_splits;
+                    sr.st = c->st;
+                    sr.loc = c->pr_loc;
+                    sr.n_pair = c->pr_n;
+                    sr.n_feed = g.n_feed;
+                    sr.count = c->count;
+                    sr.n_ax = g.n_ax;
+                    sr.nfb = nfb;
+                    sr.n_inst = bt.n_inst;
+                    sr.ksplit = c->ksplit;
+                    sr.vacc = c->pr_vacc;
+                    sr.first = ch == 0;
+                    sr.last = ch == n_chunks - 1;
+                    sr.out = vis;
+                    sr.n_freq_total = n_freq;
+                    sr.bt = bt;
+                    STEP(c, MATVIS_STEP_REDUCE, s, launch_submat_reduce(prec, sr, s));
+                    continue;
                 }
 
                 ReduceArgs ra{};
@@ -514,13 +561,10 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
     return MATVIS_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-matvis_status matvis_simulate(matvis_ctx *c, const double *antpos, const int32_t *beam_idx, const double *freqs,
-                              int32_t n_freq, const double *lsts, int32_t n_time, const double *src_radec,
-                              int64_t n_src, const double *src_flux, const void *beam_grid, void *vis, void *stream) {
+matvis_status simulate_impl(matvis_ctx *c, const double *antpos, const int32_t *beam_idx, const double *freqs,
+                            int32_t n_freq, const double *lsts, int32_t n_time, const double *src_radec,
+                            int64_t n_src, const double *src_flux, const void *beam_grid, void *vis, void *stream,
+                            bool pairs) {
     if (!c) return MATVIS_EINVAL;
     c->err.clear();
     const matvis_config &g = c->cfg;
@@ -539,22 +583,23 @@ matvis_status matvis_simulate(matvis_ctx *c, const double *antpos, const int32_t
     HIPCHK(c, hipSetDevice(c->device));
     c->last_stream = s;
     if (n_src == 0) {
-        const size_t vb = cbytes(g.precision) * (size_t)n_time * n_freq * g.n_ant * g.n_ant * g.n_feed * g.n_feed;
+        const size_t per = pairs ? (size_t)c->pr_n : (size_t)g.n_ant * g.n_ant;
+        const size_t vb = cbytes(g.precision) * (size_t)n_time * n_freq * per * g.n_feed * g.n_feed;
         HIPCHK(c, hipMemsetAsync(vis, 0, vb, s));
         return MATVIS_OK;
     }
     if ((g.flags & MATVIS_FLAG_NO_GRAPH) || c->profiling)
         return enqueue_simulate(c, antpos, beam_idx, freqs, n_freq, lsts, n_time, src_radec, n_src, src_flux, beam_grid,
-                                vis, s);
+                                vis, s, pairs);
     GraphKey key;
     key.v = {(uint64_t)antpos, (uint64_t)beam_idx, (uint64_t)freqs, (uint64_t)n_freq, (uint64_t)lsts,
              (uint64_t)n_time, (uint64_t)src_radec, (uint64_t)n_src, (uint64_t)src_flux, (uint64_t)beam_grid,
-             (uint64_t)vis};
+             (uint64_t)vis, (uint64_t)pairs};
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
         matvis_status st = enqueue_simulate(c, antpos, beam_idx, freqs, n_freq, lsts, n_time, src_radec, n_src,
-                                            src_flux, beam_grid, vis, c->capture_stream);
+                                            src_flux, beam_grid, vis, c->capture_stream, pairs);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
         if (st != MATVIS_OK) {
@@ -578,6 +623,117 @@ matvis_status matvis_simulate(matvis_ctx *c, const double *antpos, const int32_t
         c->graph_order.push_back(key);
     }
     HIPCHK(c, hipGraphLaunch(it->second, s));
+    return MATVIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+matvis_status matvis_simulate(matvis_ctx *c, const double *antpos, const int32_t *beam_idx, const double *freqs,
+                              int32_t n_freq, const double *lsts, int32_t n_time, const double *src_radec,
+                              int64_t n_src, const double *src_flux, const void *beam_grid, void *vis, void *stream) {
+    return simulate_impl(c, antpos, beam_idx, freqs, n_freq, lsts, n_time, src_radec, n_src, src_flux, beam_grid,
+                         vis, stream, false);
+}
+
+matvis_status matvis_simulate_pairs(matvis_ctx *c, const double *antpos, const int32_t *beam_idx,
+                                    const double *freqs, int32_t n_freq, const double *lsts, int32_t n_time,
+                                    const double *src_radec, int64_t n_src, const double *src_flux,
+                                    const void *beam_grid, void *vis_pairs, void *stream) {
+    if (!c) return MATVIS_EINVAL;
+    if (!c->pr_set) return fail(c, MATVIS_ESTATE, "no pair plan (call matvis_set_pairs)");
+    return simulate_impl(c, antpos, beam_idx, freqs, n_freq, lsts, n_time, src_radec, n_src, src_flux, beam_grid,
+                         vis_pairs, stream, true);
+}
+
+matvis_status matvis_set_pairs(matvis_ctx *c, const int32_t *pair_a, const int32_t *pair_b, int32_t n_pair,
+                               int32_t n_sub, int64_t *size_out) {
+    if (!c) return MATVIS_EINVAL;
+    c->err.clear();
+    const matvis_config &g = c->cfg;
+    if (!pair_a || !pair_b || n_pair <= 0 || n_sub <= 0) return fail(c, MATVIS_EINVAL, "need pairs and n_sub >= 1");
+    if (c->fused || (g.precision != MATVIS_FP64 && g.precision != MATVIS_FP32))
+        return fail(c, MATVIS_EUNSUPPORTED,
+                    "the sub-matrix product reads Z from device memory: FP64, or FP32 with MATVIS_FLAG_UNFUSED");
+    for (int u = 0; u < n_pair; u++)
+        if (pair_a[u] < 0 || pair_a[u] >= g.n_ant || pair_b[u] < 0 || pair_b[u] >= g.n_ant)
+            return fail(c, MATVIS_EINVAL, "pair antenna outside [0, n_ant)");
+    const red::Plan P = red::plan(pair_a, pair_b, n_pair, g.n_ant, n_sub);
+    const int nf = g.n_feed, ST = c->st;
+    // tiles of every sub-matrix over its Z rows (antenna a, feed p -> row a nf + p)
+    std::vector<int32_t> rows, base;
+    std::vector<int> ntc;
+    int64_t size = 0;
+    for (size_t x = 0; x < P.A.size(); x++) {
+        const int ra = (int)P.A[x].size() * nf, rb = (int)P.B[x].size() * nf;
+        const int nta = (ra + ST - 1) / ST, ntb = (rb + ST - 1) / ST;
+        base.push_back((int32_t)(rows.size() / (2 * ST)));
+        ntc.push_back(ntb);
+        size += (int64_t)P.A[x].size() * P.B[x].size();
+        for (int ti = 0; ti < nta; ti++)
+            for (int tj = 0; tj < ntb; tj++) {
+                for (int r = 0; r < ST; r++) {
+                    const int q = ti * ST + r;
+                    rows.push_back(q < ra ? P.A[x][q / nf] * nf + q % nf : -1);
+                }
+                for (int r = 0; r < ST; r++) {
+                    const int q = tj * ST + r;
+                    rows.push_back(q < rb ? P.B[x][q / nf] * nf + q % nf : -1);
+                }
+            }
+    }
+    const int n_tiles = (int)(rows.size() / (2 * ST));
+    std::vector<int> sub_of(g.n_ant, -1), pos_in(g.n_ant, -1);
+    for (size_t x = 0; x < P.A.size(); x++)
+        for (size_t i = 0; i < P.A[x].size(); i++) {
+            sub_of[P.A[x][i]] = (int)x;
+            pos_in[P.A[x][i]] = (int)i;
+        }
+    std::vector<int32_t> loc((size_t)n_pair * nf * nf * 2);
+    for (int u = 0; u < n_pair; u++) {
+        const int x = sub_of[pair_a[u]];
+        const auto &B = P.B[x];
+        const int ib = (int)(std::lower_bound(B.begin(), B.end(), pair_b[u]) - B.begin());
+        for (int p = 0; p < nf; p++)
+            for (int q = 0; q < nf; q++) {
+                const int r = pos_in[pair_a[u]] * nf + p, col = ib * nf + q;
+                const size_t e = (((size_t)u * nf + p) * nf + q) * 2;
+                loc[e] = base[x] + (r / ST) * ntc[x] + col / ST;
+                loc[e + 1] = (r % ST) * ST + col % ST;
+            }
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipDeviceSynchronize());
+    // graphs captured with an earlier plan hold its buffers
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    c->graph_order.clear();
+    for (void *q : {(void *)c->pr_rows, (void *)c->pr_loc, c->pr_part, (void *)c->pr_vacc}) {
+        if (!q) continue;
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), q);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        (void)hipFree(q);
+    }
+    c->pr_rows = c->pr_loc = nullptr;
+    c->pr_part = nullptr;
+    c->pr_vacc = nullptr;
+    c->pr_set = false;
+    const int B_cap = c->ntb * c->nfb;
+    matvis_status st;
+    if ((st = dalloc(c, &c->pr_rows, sizeof(int32_t) * rows.size())) != MATVIS_OK) return st;
+    if ((st = dalloc(c, &c->pr_loc, sizeof(int32_t) * loc.size())) != MATVIS_OK) return st;
+    if ((st = dalloc(c, &c->pr_part, cbytes(g.precision) * (size_t)B_cap * c->max_splits * n_tiles * ST * ST)) !=
+        MATVIS_OK)
+        return st;
+    if ((st = dalloc(c, &c->pr_vacc, sizeof(double) * 2 * (size_t)B_cap * n_pair * nf * nf)) != MATVIS_OK) return st;
+    HIPCHK(c, hipMemcpy(c->pr_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->pr_loc, loc.data(), sizeof(int32_t) * loc.size(), hipMemcpyHostToDevice));
+    c->pr_n = n_pair;
+    c->pr_tiles = n_tiles;
+    c->pr_size = size;
+    c->pr_set = true;
+    if (size_out) *size_out = size;
     return MATVIS_OK;
 }
 

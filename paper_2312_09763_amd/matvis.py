@@ -106,6 +106,15 @@ def load_library():
     L.matvis_set_surrogate.restype = ctypes.c_int
     L.matvis_product_path_of.argtypes = [_P]
     L.matvis_product_path_of.restype = ctypes.c_int32
+    L.matvis_redundant_groups.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P]
+    L.matvis_redundant_groups.restype = ctypes.c_int
+    L.matvis_submatrix_plan.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]
+    L.matvis_submatrix_plan.restype = ctypes.c_int
+    L.matvis_set_pairs.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]
+    L.matvis_set_pairs.restype = ctypes.c_int
+    L.matvis_simulate_pairs.argtypes = [_P, _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P, ctypes.c_int64, _P,
+                                        _P, _P, _P]
+    L.matvis_simulate_pairs.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -280,6 +289,41 @@ class Context:
         self._check(self._L.matvis_step_herk(self._h, _ptr(Z), n_row, n_col, n_col, _ptr(V), _stream_handle(stream)))
         return V
 
+    def set_pairs(self, pairs, n_sub: int = 3) -> int:
+        """matvis_set_pairs: plan the sub-matrix product (App. A) for these (a, b) pairs;
+        returns the total sub-matrix size in antenna pairs."""
+        import numpy as np
+        pa = np.ascontiguousarray([p[0] for p in pairs], dtype=np.int32)
+        pb = np.ascontiguousarray([p[1] for p in pairs], dtype=np.int32)
+        size = ctypes.c_int64()
+        self._check(self._L.matvis_set_pairs(self._h, pa.ctypes.data, pb.ctypes.data, len(pa), int(n_sub),
+                                             ctypes.byref(size)))
+        self._n_pairs = len(pa)
+        return int(size.value)
+
+    def simulate_pairs(self, antpos, freqs, lsts, src_radec, src_flux, beam_grid, vis=None, beam_idx=None,
+                       stream=None):
+        """matvis_simulate_pairs: V of the planned pairs, [t][f][pair][p][q] (allocated if None)."""
+        import torch
+        c = self.cfg
+        n_freq, n_time, n_src = freqs.shape[0], lsts.shape[0], src_radec.shape[1]
+        _need(antpos, torch.float64, (c.n_ant, 3), "antpos")
+        _need(freqs, torch.float64, (n_freq,), "freqs")
+        _need(lsts, torch.float64, (n_time,), "lsts")
+        _need(src_radec, torch.float64, (2, n_src), "src_radec")
+        _need(src_flux, torch.float64, (4, n_freq, n_src) if c.polarised_sky else (n_freq, n_src), "src_flux")
+        _need(beam_grid, self.complex_dtype, (c.n_beam, n_freq, c.n_feed, c.n_ax, c.n_za, c.n_az), "beam_grid")
+        if beam_idx is not None:
+            _need(beam_idx, torch.int32, (c.n_ant,), "beam_idx")
+        shape = (n_time, n_freq, getattr(self, "_n_pairs", 0), c.n_feed, c.n_feed)
+        if vis is None:
+            vis = torch.empty(shape, dtype=self.complex_dtype, device=antpos.device)
+        _need(vis, self.complex_dtype, shape, "vis")
+        self._check(self._L.matvis_simulate_pairs(self._h, _ptr(antpos), _ptr(beam_idx), _ptr(freqs), n_freq,
+                                                  _ptr(lsts), n_time, _ptr(src_radec), n_src, _ptr(src_flux),
+                                                  _ptr(beam_grid), _ptr(vis), _stream_handle(stream)))
+        return vis
+
     def set_surrogate(self, params, nu_min_hz: float, nu_max_hz: float):
         """matvis_set_surrogate: load a learned beam (copied) and its frequency range."""
         import torch
@@ -325,6 +369,38 @@ def autotune(cfg: Config, antpos, freqs, lsts, src_radec, src_flux, beam_grid, b
     tuned = dataclasses.replace(cfg, ksplit=int(best.ksplit), batch_time=int(best.batch_time),
                                 unfused=bool(best.flags & FLAG_UNFUSED))
     return tuned, float(ms.value)
+
+
+def redundant_groups(antpos, beam_idx=None, tol_m: float = 1e-3):
+    """matvis_redundant_groups (host): (group of every pair (i <= j, lexicographic), representative pairs)."""
+    import numpy as np
+    x = np.ascontiguousarray(antpos, dtype=np.float64)
+    n = x.shape[0]
+    npairs = n * (n + 1) // 2
+    bi = None if beam_idx is None else np.ascontiguousarray(beam_idx, dtype=np.int32)
+    group = np.empty(npairs, dtype=np.int32)
+    ra = np.empty(npairs, dtype=np.int32)
+    rb = np.empty(npairs, dtype=np.int32)
+    nu = ctypes.c_int32()
+    _check_lib(load_library().matvis_redundant_groups(x.ctypes.data, None if bi is None else bi.ctypes.data, n,
+                                                      float(tol_m), group.ctypes.data, ra.ctypes.data, rb.ctypes.data,
+                                                      ctypes.byref(nu)), "matvis_redundant_groups")
+    return group, list(zip(ra[:nu.value].tolist(), rb[:nu.value].tolist()))
+
+
+def submatrix_plan(pairs, n_ant: int, n_sub: int):
+    """matvis_submatrix_plan (host): (alpha order, sub-matrix sizes, densities)."""
+    import numpy as np
+    pa = np.ascontiguousarray([p[0] for p in pairs], dtype=np.int32)
+    pb = np.ascontiguousarray([p[1] for p in pairs], dtype=np.int32)
+    alpha = np.empty(n_ant, dtype=np.int32)
+    sizes = np.empty(max(1, n_sub), dtype=np.int32)
+    dens = np.empty(max(1, n_sub), dtype=np.float64)
+    na, ns = ctypes.c_int32(), ctypes.c_int32()
+    _check_lib(load_library().matvis_submatrix_plan(pa.ctypes.data, pb.ctypes.data, len(pa), int(n_ant), int(n_sub),
+                                                    alpha.ctypes.data, sizes.ctypes.data, dens.ctypes.data,
+                                                    ctypes.byref(na), ctypes.byref(ns)), "matvis_submatrix_plan")
+    return alpha[:na.value].tolist(), sizes[:ns.value].tolist(), dens[:ns.value].tolist()
 
 
 def _check_lib(st: int, what: str):
