@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--n-src", type=int, default=None, help="shrink the workload (smoke runs only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--redundancy-steps", type=int, default=2,
+                    help="time the full product against the sub-matrix product (App. A) on a 350-antenna "
+                         "hexagon (0 = skip)")
     ap.add_argument("--side-steps", type=int, default=2,
                     help="steps timed for each side-by-side variant (0 = skip them)")
     args = ap.parse_args()
@@ -201,9 +204,32 @@ def main():
                                            "product_frac_of_peak": vtf / PEAK_TFLOPS[vprec] if vtf else None}
                 log(f"side by side {vprec} + {beam} beam: {vms:.2f} ms/step")
                 del vvis
+        # the polarised sky (I, Q, U, V per source and channel) on the same path
+        st = synth.polarised_stokes(wl.flux, wl.freqs, seed=1)
+        pcfg = mv.config_for(wl, prec, polarised_sky=True)
+        pd = mv.device_inputs(wl, prec, stokes=st)
+        with mv.Context(pcfg) as pctx:
+            pvis = torch.empty_like(vis)
+            pctx.simulate(**pd, vis=pvis)
+            pctx.finish()
+            torch.cuda.synchronize()
+            v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            v0.record(stream)
+            for _ in range(args.side_steps):
+                pctx.simulate(**pd, vis=pvis)
+            v1.record(stream)
+            torch.cuda.synchronize()
+            pctx.finish()
+            pms = v0.elapsed_time(v1) / args.side_steps
+            side[f"{prec}+interpolated+polarised_sky"] = {"ms_per_step": pms, "value": units / (pms / 1e3),
+                                                          "product_path": pctx.product_path}
+            log(f"side by side {prec} + polarised sky: {pms:.2f} ms/step")
+            del pvis
         side[f"{prec}+interpolated"] = {"ms_per_step": ms_step, "value": value, "product_path": ctx.product_path,
                                         "product_ms_per_step": herk_ms / args.profile_steps,
                                         "product_tflops": achieved, "product_frac_of_peak": achieved / PEAK_TFLOPS[prec]}
+
+    red = redundancy_section(args) if args.redundancy_steps > 0 else None
 
     # ---- CPU baseline: the FP64 oracle on one full instance, and the GPU error there
     cpu = None
@@ -255,11 +281,59 @@ def main():
                   "peak_GBps": HBM_GBS},
         "step_ms": steps_ms,
         "side_by_side": side,
+        "redundancy": red,
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def redundancy_section(args):
+    """Full product V = Z Z^H against the sub-matrix product of App. A for the unique
+    baselines of a redundant 350-antenna hexagon (the diffuse-sky array), FP32 and
+    FP64 with Z in device memory; per-step device times from the profiled pass."""
+    import torch
+    from paper_2312_09763_amd import matvis as mv
+    from paper_2312_09763_amd import synth
+    wl = synth.workload(3, n_src=49152, n_time=4, n_freq=8)
+    _, reps = mv.redundant_groups(wl.antpos, None, 1e-6)
+    res = {"workload": f"{wl.n_ant}-antenna hexagon, {wl.n_src} equal-area pixels, {wl.n_time} LSTs x "
+                       f"{wl.n_freq} channels, scalar Gaussian beam",
+           "n_ant": wl.n_ant, "pairs": wl.n_ant * (wl.n_ant + 1) // 2, "unique_pairs": len(reps)}
+    for prec in ("fp32", "fp64"):
+        cfg = mv.config_for(wl, prec, unfused=(prec == "fp32"))
+        d = mv.device_inputs(wl, prec)
+        with mv.Context(cfg) as ctx:
+            size = ctx.set_pairs(reps, 3)
+            r = {"submatrix_size": size, "full_size": wl.n_ant ** 2, "compression": wl.n_ant ** 2 / size}
+            for mode in ("full", "pairs"):
+                run = ctx.simulate if mode == "full" else ctx.simulate_pairs
+                run(**d)
+                ctx.finish()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(args.redundancy_steps):
+                    run(**d)
+                e1.record()
+                torch.cuda.synchronize()
+                ctx.finish()
+                ctx.profile(True)
+                run(**d)
+                prof = ctx.profile_read()
+                ctx.profile(False)
+                ctx.finish()
+                r[f"{mode}_ms_per_step"] = e0.elapsed_time(e1) / args.redundancy_steps
+                r[f"{mode}_product_ms"] = prof["herk"][0]
+                r[f"{mode}_reduce_ms"] = prof["reduce"][0]
+            r["product_speedup"] = r["full_product_ms"] / r["pairs_product_ms"]
+            r["step_speedup"] = r["full_ms_per_step"] / r["pairs_ms_per_step"]
+            log(f"redundancy {prec}: {len(reps)} unique pairs, compression {r['compression']:.1f}, product "
+                f"{r['full_product_ms']:.2f} -> {r['pairs_product_ms']:.2f} ms, step {r['full_ms_per_step']:.2f} -> "
+                f"{r['pairs_ms_per_step']:.2f} ms")
+            res[prec] = r
+    return res
 
 
 if __name__ == "__main__":

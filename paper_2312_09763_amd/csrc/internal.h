@@ -221,7 +221,10 @@ int herk_fused_occupancy(int prec);
 int fused_path(int prec, int n_feed, int n_ax, int n_beam, int n_ant, int n_rows_pad);
 
 // Redundancy-aware sub-matrix product (App. A, Eq. Vpx) on Z in device memory,
-// FP64 and FP32 (kernels_herk.hip).  Tiles are herk_super_tile(prec) square.
+// FP64 and FP32 (kernels_herk.hip).  Tiles are kSubmatTile square: small, because
+// sub-matrices are often thin (tens of rows against hundreds), and a tile's
+// padding is computed for nothing.
+constexpr int kSubmatTile = 32;
 struct SubmatArgs {
     const void *Z;           // [n_inst][Np][ldz] as written by launch_zform
     int64_t ldz;

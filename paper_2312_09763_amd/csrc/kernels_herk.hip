@@ -47,10 +47,11 @@ struct HT<PB3> {
     static constexpr int ST = 128, WT = 64, KC = 16, EB = 4, PLANES = 2;
 };
 
-template <int PREC>
-struct HD {
+// Stage geometry of a square ST_ tile computed by four waves (2 x 2 wave tiles).
+template <int PREC, int ST_>
+struct HG {
     typedef HT<PREC> T;
-    static constexpr int ST = T::ST, WT = T::WT, KC = T::KC, EB = T::EB, PLANES = T::PLANES;
+    static constexpr int ST = ST_, WT = ST_ / 2, KC = T::KC, EB = T::EB, PLANES = T::PLANES;
     static constexpr int ROWB = KC * EB * PLANES;  // bytes of one staged row
     static constexpr int RS = ROWB + 16;           // LDS row stride (16 B pad against bank conflicts)
     static constexpr int CPR = ROWB / 16;          // 16-byte chunks per row
@@ -58,6 +59,8 @@ struct HD {
     static constexpr int LDS = 2 * ST * RS;
     static constexpr int TI = WT / 16;             // 16x16 tiles per wave side
 };
+template <int PREC>
+struct HD : HG<PREC, HT<PREC>::ST> {};
 
 __device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
@@ -146,11 +149,9 @@ __device__ inline u32x4 bf16_rot(u32x4 v) {
 
 // One KC-deep stage of a WT x WT wave tile: rows arow.. of the staged A block
 // against rows brow.. of the staged B block (both in LDS, row stride RS).
-template <int PREC, typename Acc>
+template <int PREC, typename D, typename Acc>
 __device__ __forceinline__ void mma_stage(const unsigned char *lds, int arow, int brow, int l16, int lk, bool on_diag,
-                                          Acc (&acc_re)[HD<PREC>::TI][HD<PREC>::TI],
-                                          Acc (&acc_im)[HD<PREC>::TI][HD<PREC>::TI]) {
-    typedef HD<PREC> D;
+                                          Acc (&acc_re)[D::TI][D::TI], Acc (&acc_im)[D::TI][D::TI]) {
     constexpr int KC = D::KC, RS = D::RS, TI = D::TI;
     if constexpr (PREC == PB3) {
         u32x4 ah[TI], al[TI], bh[TI], bl[TI];
@@ -323,7 +324,7 @@ __global__ void __launch_bounds__(256, 2) k_herk(HerkArgs a) {
             store();
             __syncthreads();
             if (k0 + KC < ke) load(k0 + KC);
-            if (active) mma_stage<PREC>(lds, arow, brow, l16, lk, on_diag, acc_re, acc_im);
+            if (active) mma_stage<PREC, D>(lds, arow, brow, l16, lk, on_diag, acc_re, acc_im);
         }
 
         if (active) {
@@ -355,9 +356,9 @@ __global__ void __launch_bounds__(256, 2) k_herk(HerkArgs a) {
 // sub-matrix, k-split); the tile's rows are read through its two row lists
 // straight from Z (a gather fused into the stage loads: no copy of A_x or
 // B_x is formed), and the raw tile goes to its own partial slot.
-template <int PREC>
+template <int PREC, int STS>
 __global__ void __launch_bounds__(256, 2) k_submat(SubmatArgs a) {
-    typedef HD<PREC> D;
+    typedef HG<PREC, STS> D;
     constexpr int ST = D::ST, WT = D::WT, KC = D::KC, RS = D::RS, CPR = D::CPR, NLD = D::NLD, TI = D::TI;
     typedef typename std::conditional<PREC == P64, f64x4, f32x4>::type Acc;
     typedef typename std::conditional<PREC == P64, double2, float2>::type PartT;
@@ -413,7 +414,7 @@ __global__ void __launch_bounds__(256, 2) k_submat(SubmatArgs a) {
         store();
         __syncthreads();
         if (k0 + KC < ke) load(k0 + KC);
-        mma_stage<PREC>(lds, arow, brow, l16, lk, false, acc_re, acc_im);
+        mma_stage<PREC, D>(lds, arow, brow, l16, lk, false, acc_re, acc_im);
     }
     PartT *P = (PartT *)a.part + (((int64_t)inst * a.max_splits + s) * a.n_tiles + tile) * ST * ST;
 #pragma unroll
@@ -551,9 +552,9 @@ hipError_t launch_submat(int prec, const SubmatArgs &a, hipStream_t s) {
     const int64_t items = (int64_t)a.n_inst * a.n_tiles * a.max_splits;
     if (items <= 0) return hipSuccess;
     if (prec == P64)
-        k_submat<P64><<<(unsigned)items, 256, 0, s>>>(a);
+        k_submat<P64, kSubmatTile><<<(unsigned)items, 256, 0, s>>>(a);
     else if (prec == P32)
-        k_submat<P32><<<(unsigned)items, 256, 0, s>>>(a);
+        k_submat<P32, kSubmatTile><<<(unsigned)items, 256, 0, s>>>(a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

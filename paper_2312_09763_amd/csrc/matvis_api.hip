@@ -514,7 +514,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                     sr.part = c->pr_part;
                     sr.n_tiles = c->pr_tiles;
                     sr.max_splits = c->max_splits;
-                    sr.st = c->st;
+                    sr.st = kSubmatTile;
                     sr.loc = c->pr_loc;
                     sr.n_pair = c->pr_n;
                     sr.n_feed = g.n_feed;
@@ -660,7 +660,7 @@ matvis_status matvis_set_pairs(matvis_ctx *c, const int32_t *pair_a, const int32
         if (pair_a[u] < 0 || pair_a[u] >= g.n_ant || pair_b[u] < 0 || pair_b[u] >= g.n_ant)
             return fail(c, MATVIS_EINVAL, "pair antenna outside [0, n_ant)");
     const red::Plan P = red::plan(pair_a, pair_b, n_pair, g.n_ant, n_sub);
-    const int nf = g.n_feed, ST = c->st;
+    const int nf = g.n_feed, ST = kSubmatTile;
     // tiles of every sub-matrix over its Z rows (antenna a, feed p -> row a nf + p)
     std::vector<int32_t> rows, base;
     std::vector<int> ntc;
