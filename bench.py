@@ -291,8 +291,8 @@ def main():
 
 def redundancy_section(args):
     """Full product V = Z Z^H against the sub-matrix product of App. A for the unique
-    baselines of a redundant 350-antenna hexagon (the diffuse-sky array), FP32 and
-    FP64 with Z in device memory; per-step device times from the profiled pass."""
+    baselines of a redundant 350-antenna hexagon (the diffuse-sky array), BF16X3,
+    FP32 and FP64 with Z in device memory; per-step device times from the profiled pass."""
     import torch
     from paper_2312_09763_amd import matvis as mv
     from paper_2312_09763_amd import synth
@@ -301,8 +301,8 @@ def redundancy_section(args):
     res = {"workload": f"{wl.n_ant}-antenna hexagon, {wl.n_src} equal-area pixels, {wl.n_time} LSTs x "
                        f"{wl.n_freq} channels, scalar Gaussian beam",
            "n_ant": wl.n_ant, "pairs": wl.n_ant * (wl.n_ant + 1) // 2, "unique_pairs": len(reps)}
-    for prec in ("fp32", "fp64"):
-        cfg = mv.config_for(wl, prec, unfused=(prec == "fp32"))
+    for prec in ("bf16x3", "fp32", "fp64"):
+        cfg = mv.config_for(wl, prec, unfused=(prec != "fp64"))
         d = mv.device_inputs(wl, prec)
         with mv.Context(cfg) as ctx:
             size = ctx.set_pairs(reps, 3)

@@ -166,8 +166,8 @@ matvis_status matvis_submatrix_plan(const int32_t *pair_a, const int32_t *pair_b
 /* Plan the sub-matrix product for the pairs (pair_a[u], pair_b[u]) (host
  * arrays, antennas in [0, n_ant); any pairs, usually the representatives of
  * matvis_redundant_groups) with n_sub sub-matrices, and upload the plan to
- * the context's device.  Needs Z in device memory (precision FP64, or FP32
- * with MATVIS_FLAG_UNFUSED): MATVIS_EUNSUPPORTED otherwise.  Allocates the
+ * the context's device.  Needs Z in device memory (precision FP64, or FP32 /
+ * BF16X3 with MATVIS_FLAG_UNFUSED): MATVIS_EUNSUPPORTED otherwise.  Allocates the
  * plan's scratch (so call it outside graph capture); replaces an earlier
  * plan.  *size_out (may be NULL) receives the total sub-matrix size
  * sum_x |A_x| |B_x| in antenna pairs. */

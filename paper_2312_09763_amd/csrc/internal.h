@@ -221,12 +221,13 @@ int herk_fused_occupancy(int prec);
 int fused_path(int prec, int n_feed, int n_ax, int n_beam, int n_ant, int n_rows_pad);
 
 // Redundancy-aware sub-matrix product (App. A, Eq. Vpx) on Z in device memory,
-// FP64 and FP32 (kernels_herk.hip).  Tiles are kSubmatTile square: small, because
+// FP64, FP32 and BF16X3 (kernels_herk.hip).  Tiles are kSubmatTile square: small, because
 // sub-matrices are often thin (tens of rows against hundreds), and a tile's
 // padding is computed for nothing.
 constexpr int kSubmatTile = 32;
 struct SubmatArgs {
-    const void *Z;           // [n_inst][Np][ldz] as written by launch_zform
+    const void *Z;           // [n_inst][Np][ldz] as written by launch_zform (BF16X3: hi plane)
+    const void *Z_lo;        // BF16X3 lo plane
     int64_t ldz;
     int64_t inst_stride;     // elements between instances
     const int32_t *rows;     // [n_tiles][2][ST]: the tile's A rows then B rows of Z, -1 = padding

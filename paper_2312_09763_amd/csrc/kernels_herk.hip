@@ -376,6 +376,7 @@ __global__ void __launch_bounds__(256, 2) k_submat(SubmatArgs a) {
     const int64_t ke = kb + a.ksplit < Kr ? kb + a.ksplit : Kr;
     const int32_t *rows = a.rows + (int64_t)tile * 2 * ST;
     const char *zbase = (const char *)a.Z + (int64_t)inst * a.inst_stride * D::EB;
+    const char *zlo = PREC == PB3 ? (const char *)a.Z_lo + (int64_t)inst * a.inst_stride * D::EB : nullptr;
     const int64_t ldzb = a.ldz * D::EB;
 
     Acc acc_re[TI][TI], acc_im[TI][TI];
@@ -397,7 +398,13 @@ __global__ void __launch_bounds__(256, 2) k_submat(SubmatArgs a) {
         for (int j = 0; j < NLD; j++) {
             const int c = (tid + 256 * j) % CPR;
             pre[j] = u32x4{0u, 0u, 0u, 0u};
-            if (grow[j] >= 0) pre[j] = *(const u32x4 *)(zbase + grow[j] * ldzb + k0 * D::EB + c * 16);
+            if (grow[j] < 0) continue;
+            if constexpr (D::PLANES == 2) {  // BF16X3: hi then lo plane of the staged row
+                const int half = CPR / 2;
+                pre[j] = *(const u32x4 *)((c < half ? zbase : zlo) + grow[j] * ldzb + k0 * D::EB + (c % half) * 16);
+            } else {
+                pre[j] = *(const u32x4 *)(zbase + grow[j] * ldzb + k0 * D::EB + c * 16);
+            }
         }
     };
     auto store = [&]() {
@@ -414,7 +421,9 @@ __global__ void __launch_bounds__(256, 2) k_submat(SubmatArgs a) {
         store();
         __syncthreads();
         if (k0 + KC < ke) load(k0 + KC);
-        mma_stage<PREC, D>(lds, arow, brow, l16, lk, false, acc_re, acc_im);
+        // BF16X3: any tile may hold an autocorrelation (a = b, p = q), where the
+        // dropped lo lo^H term is a one-signed bias, so every tile takes it
+        mma_stage<PREC, D>(lds, arow, brow, l16, lk, PREC == PB3, acc_re, acc_im);
     }
     PartT *P = (PartT *)a.part + (((int64_t)inst * a.max_splits + s) * a.n_tiles + tile) * ST * ST;
 #pragma unroll
@@ -555,6 +564,8 @@ hipError_t launch_submat(int prec, const SubmatArgs &a, hipStream_t s) {
         k_submat<P64, kSubmatTile><<<(unsigned)items, 256, 0, s>>>(a);
     else if (prec == P32)
         k_submat<P32, kSubmatTile><<<(unsigned)items, 256, 0, s>>>(a);
+    else if (prec == PB3)
+        k_submat<PB3, kSubmatTile><<<(unsigned)items, 256, 0, s>>>(a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -566,7 +577,7 @@ hipError_t launch_submat_reduce(int prec, const SubmatReduceArgs &a, hipStream_t
     const unsigned g = (unsigned)((n + 255) / 256);
     if (prec == P64)
         k_submat_reduce<P64><<<g, 256, 0, s>>>(a);
-    else if (prec == P32)
+    else if (prec == P32 || prec == PB3)
         k_submat_reduce<P32><<<g, 256, 0, s>>>(a);
     else
         return hipErrorInvalidValue;

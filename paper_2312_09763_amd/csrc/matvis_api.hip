@@ -498,6 +498,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                     // App. A: only the planned sub-matrices, then the requested pairs
                     SubmatArgs sa{};
                     sa.Z = c->Z;
+                    sa.Z_lo = c->Z_lo;
                     sa.ldz = c->ldz;
                     sa.inst_stride = (int64_t)c->Np * c->ldz;
                     sa.rows = c->pr_rows;
@@ -653,9 +654,9 @@ matvis_status matvis_set_pairs(matvis_ctx *c, const int32_t *pair_a, const int32
     c->err.clear();
     const matvis_config &g = c->cfg;
     if (!pair_a || !pair_b || n_pair <= 0 || n_sub <= 0) return fail(c, MATVIS_EINVAL, "need pairs and n_sub >= 1");
-    if (c->fused || (g.precision != MATVIS_FP64 && g.precision != MATVIS_FP32))
+    if (c->fused)
         return fail(c, MATVIS_EUNSUPPORTED,
-                    "the sub-matrix product reads Z from device memory: FP64, or FP32 with MATVIS_FLAG_UNFUSED");
+                    "the sub-matrix product reads Z from device memory: FP64, or MATVIS_FLAG_UNFUSED");
     for (int u = 0; u < n_pair; u++)
         if (pair_a[u] < 0 || pair_a[u] >= g.n_ant || pair_b[u] < 0 || pair_b[u] >= g.n_ant)
             return fail(c, MATVIS_EINVAL, "pair antenna outside [0, n_ant)");
