@@ -259,9 +259,11 @@ matvis_status matvis_train_surrogate(float *params, const float *x, const float 
                                      int32_t epochs, float lr0, float lr1, uint64_t seed, int32_t fp32_math,
                                      float *loss_history, void *stream);
 
-/* Give a context created with beam_mode MATVIS_BEAM_SURROGATE its network
- * (copied) and the frequency range that normalises w.  The context must have
- * n_beam = 1 and FP32 or BF16X3 precision; beam_grid is then ignored by
+/* Give a context created with beam_mode MATVIS_BEAM_SURROGATE its networks
+ * (copied): params holds n_beam parameter vectors back to back
+ * ([n_beam][MATVIS_MLP_N_PARAMS], one network per unique beam, antenna a using
+ * network beam_idx[a]) and the frequency range that normalises w.  The
+ * context must have FP32 or BF16X3 precision; beam_grid is then ignored by
  * matvis_simulate (NULL is accepted). */
 matvis_status matvis_set_surrogate(matvis_ctx *ctx, const float *params, double nu_min_hz, double nu_max_hz);
 

@@ -364,8 +364,8 @@ struct InferArgs {
     int64_t stokes_stride;
     const double *freqs;
     int64_t ld_src;
-    void *A;               // complex64 [inst][1][n_feed][n_ax][ld_src] = sqrt(I) J
-    int32_t n_feed, n_ax;
+    void *A;               // complex64 [inst][n_beam][n_feed][n_ax][ld_src] = sqrt(I) J (slot beam)
+    int32_t n_feed, n_ax, beam, n_beam;
     Batch bt;
 };
 
@@ -531,7 +531,9 @@ __global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
 #pragma unroll
                     for (int cc = 0; cc < 2; cc++) {
                         if (lk >= a.n_feed || cc >= a.n_ax) continue;
-                        float2 *dst = (float2 *)a.A + ((int64_t)inst * a.n_feed * a.n_ax + lk * a.n_ax + cc) * a.ld_src + m;
+                        float2 *dst = (float2 *)a.A +
+                                      (((int64_t)inst * a.n_beam + a.beam) * a.n_feed * a.n_ax + lk * a.n_ax + cc) *
+                                          a.ld_src + m;
                         *dst = make_float2(sq * J[2 * cc], sq * J[2 * cc + 1]);
                     }
                 } else {
@@ -670,7 +672,7 @@ hipError_t infer_plain(const float *P, const __bf16 *Wb, const float *x, int64_t
 hipError_t infer_sim(const float *P, const __bf16 *Wb, double nu0, double nu1, const double *za_az,
                      const int32_t *count, const int32_t *idx, const double *flux, int64_t n_src, int pol,
                      int64_t stokes_stride, const double *freqs, int64_t ld_src, int64_t max_m, void *A, int n_feed,
-                     int n_ax, const Batch &bt, hipStream_t s) {
+                     int n_ax, int beam, int n_beam, const Batch &bt, hipStream_t s) {
     if (bt.n_inst <= 0 || max_m <= 0) return hipSuccess;
     if (n_feed > 2 || n_ax > 2) return hipErrorInvalidValue;
     InferArgs a{};
@@ -690,6 +692,8 @@ hipError_t infer_sim(const float *P, const __bf16 *Wb, double nu0, double nu1, c
     a.A = A;
     a.n_feed = n_feed;
     a.n_ax = n_ax;
+    a.beam = beam;
+    a.n_beam = n_beam;
     a.bt = bt;
     a.tiles = (max_m + kIPts - 1) / kIPts;
     a.n_tasks = a.tiles * bt.n_inst;

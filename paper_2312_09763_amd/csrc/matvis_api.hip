@@ -75,8 +75,8 @@ struct matvis_ctx {
     std::vector<hipEvent_t> event_pool;
 
     // learned beam (beam_mode MATVIS_BEAM_SURROGATE)
-    float *sur_P = nullptr;     // FP32 parameters
-    __bf16 *sur_Wb = nullptr;   // bf16 W1..W4
+    float *sur_P = nullptr;     // FP32 parameters, one network per unique beam
+    __bf16 *sur_Wb = nullptr;   // bf16 W1..W4 LDS images, one per beam
     void *gridT = nullptr;      // channel-interleaved beam grids (grid beam modes, n_za >= 4)
     double sur_nu0 = 0, sur_nu1 = 1;
     bool sur_set = false;
@@ -169,7 +169,6 @@ matvis_status validate_cfg(const matvis_config *c, std::string &why) {
     if (c->beam_mode == MATVIS_BEAM_SURROGATE) {
         if (c->precision == MATVIS_FP64)
             return why = "the learned beam runs with FP32 or BF16X3 products", MATVIS_EUNSUPPORTED;
-        if (c->n_beam != 1) return why = "the learned beam models one unique beam (n_beam = 1)", MATVIS_EUNSUPPORTED;
     } else {
         if (c->n_za < 3 || c->n_az < 3) return why = "beam grid must be at least 3 x 3", MATVIS_EINVAL;
         if (!(c->dza_rad > 0) || !(c->daz_rad > 0)) return why = "grid spacings must be positive", MATVIS_EINVAL;
@@ -315,8 +314,8 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
         ALLOC(c->gridT, cbytes(prec) * (size_t)grid_interleave_elems(cfg->n_beam, cfg->max_freq,
                                                                      cfg->n_feed * cfg->n_ax, cfg->n_za, cfg->n_az));
     if (cfg->beam_mode == MATVIS_BEAM_SURROGATE) {
-        ALLOC(c->sur_P, sizeof(float) * kNParams);
-        ALLOC(c->sur_Wb, sizeof(__bf16) * mlp::kWbElems);
+        ALLOC(c->sur_P, sizeof(float) * kNParams * cfg->n_beam);
+        ALLOC(c->sur_Wb, sizeof(__bf16) * mlp::kWbElems * cfg->n_beam);
     }
 #undef ALLOC
     // Rows N..Np-1 of Z are never written by the kernels and must read as zero.
@@ -415,10 +414,12 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                     ia.stokes_stride = (int64_t)n_freq * n_src;
                 }
                 if (g.beam_mode == MATVIS_BEAM_SURROGATE)
-                    STEP(c, MATVIS_STEP_BEAM, s,
-                         mlp::infer_sim(c->sur_P, c->sur_Wb, c->sur_nu0, c->sur_nu1, c->za_az, c->count, ia.idx, flux,
-                                        n_src, pol, ia.stokes_stride, freqs, c->chunk, ns, c->A, g.n_feed, g.n_ax,
-                                        bt, s));
+                    for (int b = 0; b < g.n_beam; b++)  // one network per unique beam
+                        STEP(c, MATVIS_STEP_BEAM, s,
+                             mlp::infer_sim(c->sur_P + (size_t)b * kNParams, c->sur_Wb + (size_t)b * mlp::kWbElems,
+                                            c->sur_nu0, c->sur_nu1, c->za_az, c->count, ia.idx, flux, n_src, pol,
+                                            ia.stokes_stride, freqs, c->chunk, ns, c->A, g.n_feed, g.n_ax, b,
+                                            g.n_beam, bt, s));
                 else
                     STEP(c, MATVIS_STEP_BEAM, s,
                          c->gridT ? launch_interp_tf(prec, g.beam_mode, ia, bt, s)
@@ -752,8 +753,9 @@ matvis_status matvis_set_surrogate(matvis_ctx *c, const float *params, double nu
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     c->graph_order.clear();
-    HIPCHK(c, hipMemcpy(c->sur_P, params, sizeof(float) * kNParams, hipMemcpyDeviceToDevice));
-    HIPCHK(c, mlp::pack_weights(c->sur_P, c->sur_Wb, nullptr));
+    HIPCHK(c, hipMemcpy(c->sur_P, params, sizeof(float) * kNParams * c->cfg.n_beam, hipMemcpyDeviceToDevice));
+    for (int b = 0; b < c->cfg.n_beam; b++)
+        HIPCHK(c, mlp::pack_weights(c->sur_P + (size_t)b * kNParams, c->sur_Wb + (size_t)b * mlp::kWbElems, nullptr));
     HIPCHK(c, hipDeviceSynchronize());
     c->sur_nu0 = nu_min_hz;
     c->sur_nu1 = nu_max_hz;

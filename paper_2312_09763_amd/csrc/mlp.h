@@ -67,11 +67,11 @@ hipError_t infer_plain(const float *P, const __bf16 *Wb, const float *x, int64_t
 // Simulator mode: A of every instance of batch bt = sqrt(I) J (sqrt(I) = 1
 // when idx is NULL), or J M for a polarised sky (pol: flux holds the Stokes
 // planes stokes_stride apart, M of pol_sqrt; n_ax = 2), at the batch's
-// visible sources.
+// visible sources, into beam slot `beam` of A [inst][n_beam][n_feed][n_ax][ld].
 hipError_t infer_sim(const float *P, const __bf16 *Wb, double nu0, double nu1, const double *za_az,
                      const int32_t *count, const int32_t *idx, const double *flux, int64_t n_src, int pol,
                      int64_t stokes_stride, const double *freqs, int64_t ld_src, int64_t max_m, void *A, int n_feed,
-                     int n_ax, const Batch &bt, hipStream_t s);
+                     int n_ax, int beam, int n_beam, const Batch &bt, hipStream_t s);
 hipError_t gather_rows(const float *src, int width, const int32_t *perm, int64_t n, float *dst, hipStream_t s);
 }  // namespace mlp
 

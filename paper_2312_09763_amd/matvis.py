@@ -325,9 +325,12 @@ class Context:
         return vis
 
     def set_surrogate(self, params, nu_min_hz: float, nu_max_hz: float):
-        """matvis_set_surrogate: load a learned beam (copied) and its frequency range."""
+        """matvis_set_surrogate: load the learned beams (copied; [MLP_N_PARAMS] for one beam or
+        [n_beam][MLP_N_PARAMS], one network per unique beam) and their frequency range."""
         import torch
-        _need(params, torch.float32, (MLP_N_PARAMS,), "params")
+        nb = self.cfg.n_beam
+        _need(params, torch.float32, (MLP_N_PARAMS,) if nb == 1 and params.dim() == 1 else (nb, MLP_N_PARAMS),
+              "params")
         self._check(self._L.matvis_set_surrogate(self._h, _ptr(params), float(nu_min_hz), float(nu_max_hz)))
 
     def close(self):

@@ -54,7 +54,7 @@ def _init(**kw):
     (dict(n_az=359), mv.EINVAL),          # not periodic
     (dict(latitude_rad=2.0), mv.EINVAL),
     (dict(beam_mode="surrogate", precision="fp64"), mv.EUNSUPPORTED),
-    (dict(beam_mode="surrogate", n_beam=2), mv.EUNSUPPORTED),
+    (dict(polarised_sky=True, n_ax=1), mv.EINVAL),  # the brightness matrix needs two E-field axes
     (dict(n_ant=5000, n_feed=2), mv.EUNSUPPORTED),
 ])
 def test_init_rejects_bad_config(kw, status):

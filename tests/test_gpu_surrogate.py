@@ -261,3 +261,37 @@ def test_simulate_with_learned_beam_matches_reference(p0, precision, cfg):
             worst = max(worst, e)
     say(f"  err_CS {worst:.2e}")
     assert worst <= 1e-4
+
+
+def test_one_learned_network_per_unique_beam():
+    # V_ab depends only on the beams of antennas a and b, so with two networks and
+    # alternating beam indices every same-beam block must equal the run in which
+    # all antennas use that network
+    wl = synth.workload(2, n_ant=90, n_src=700, n_time=1, n_freq=2)
+    P = [torch.from_numpy(synth.surrogate_init(s)).cuda() for s in (1, 2)]
+    nu0, nu1 = float(wl.freqs.min()) - 1e6, float(wl.freqs.max()) + 1e6
+    bidx = np.array([0, 1] * 45, dtype=np.int32)
+    d = mv.device_inputs(wl, "bf16x3")
+    with mv.Context(mv.config_for(wl, "bf16x3", beam_mode="surrogate", n_beam=2)) as ctx:
+        ctx.set_surrogate(torch.stack(P), nu0, nu1)
+        V2 = ctx.simulate(**d, beam_idx=torch.from_numpy(bidx).cuda())
+        ctx.finish()
+        V2 = V2.cpu().numpy().astype(np.complex128)
+        path2 = ctx.product_path
+    single = []
+    for k in range(2):
+        with mv.Context(mv.config_for(wl, "bf16x3", beam_mode="surrogate")) as ctx:
+            ctx.set_surrogate(P[k], nu0, nu1)
+            V = ctx.simulate(**d)
+            ctx.finish()
+            single.append(V.cpu().numpy().astype(np.complex128))
+    for k in range(2):
+        sel = np.where(bidx == k)[0]
+        a = V2[:, :, sel][:, :, :, sel]
+        b = single[k][:, :, sel][:, :, :, sel]
+        e = float(np.abs(a - b).max() / np.abs(b).max())
+        say(f"two learned beams ({path2}), block of beam {k}: {e:.2e} from the one-network run")
+        assert e <= 3e-5
+    # the two networks differ, so the mixed blocks differ from either single run
+    s0, s1 = np.where(bidx == 0)[0], np.where(bidx == 1)[0]
+    assert np.abs(V2[:, :, s0][:, :, :, s1] - single[0][:, :, s0][:, :, :, s1]).max() > 1e-3 * np.abs(single[0]).max()
