@@ -637,6 +637,66 @@ __device__ __forceinline__ void consume_tri_b3(const unsigned char *buf, int o, 
     }
 }
 
+// FP32 forms of the two wave shapes on a stage of 16 complex columns (one
+// complex64 per element, re/im interleaved): per 4-deep k group,
+// re += a.re b.re + a.im b.im and im += a.im b.re - a.re b.im on
+// v_mfma_f32_16x16x4f32, one complex element per lane.
+template <typename L>
+__device__ __forceinline__ void consume_sq_f32(const unsigned char *buf, int rb, int cb, int l16, int lk,
+                                               f32x4 (&re)[18], f32x4 (&im)[18]) {
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+        float2 av[kTI], bv[kTI];
+#pragma unroll
+        for (int i = 0; i < kTI; i++) av[i] = *(const float2 *)(buf + (16 * (rb + i) + l16) * L::RS + (kk + lk) * 8);
+#pragma unroll
+        for (int j = 0; j < kTI; j++) bv[j] = *(const float2 *)(buf + (16 * (cb + j) + l16) * L::RS + (kk + lk) * 8);
+#pragma unroll
+        for (int i = 0; i < kTI; i++) {
+            const float nre = -av[i].x;
+#pragma unroll
+            for (int j = 0; j < kTI; j++) {
+                re[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, re[i * kTI + j], 0, 0, 0);
+                im[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].x, im[i * kTI + j], 0, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < kTI; j++) {
+                re[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, re[i * kTI + j], 0, 0, 0);
+                im[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nre, bv[j].y, im[i * kTI + j], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <typename L, int S>
+__device__ __forceinline__ void consume_tri_f32(const unsigned char *buf, int o, int l16, int lk, f32x4 (&re)[18],
+                                                f32x4 (&im)[18]) {
+    typedef TriSet<S> T;
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+        const unsigned char *p0 = buf + (o + l16) * L::RS + (kk + lk) * 8;
+        float2 av[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) av[k] = *(const float2 *)(p0 + 16 * T::r[k] * L::RS);
+#pragma unroll
+        for (int q = 0; q < T::ncol; q++) {
+            const int c = T::order[q];
+            const int kc = T::slot(c);
+            // a column that is one of the wave's rows is already in registers
+            const float2 b = kc >= 0 ? av[kc] : *(const float2 *)(p0 + 16 * c * L::RS);
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if (T::r[k] >= c) {
+                    f32x4 &r = re[T::base[k] + c], &m = im[T::base[k] + c];
+                    r = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k].x, b.x, r, 0, 0, 0);
+                    m = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k].y, b.x, m, 0, 0, 0);
+                    r = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k].y, b.y, r, 0, 0, 0);
+                    m = __builtin_amdgcn_mfma_f32_16x16x4f32(-av[k].x, b.y, m, 0, 0, 0);
+                }
+        }
+    }
+}
+
 template <int NC>
 struct SrcEntry {
     double x, y, z;   // s_hat of the source
@@ -883,8 +943,9 @@ struct CohSrc {
     float lx, ly;    // C10 / sqrt C00 (all four 0 past the split)
 };
 
-__global__ void __launch_bounds__(512, 1) k_herk_b3_coh(FusedArgs a) {
-    typedef GeomCoh L;
+template <int PREC>
+__global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
+    typedef GeomCoh L;  // 144-byte rows: hi + lo bf16 planes, or one complex64 plane (FP32)
     constexpr int RS = L::RS;
     constexpr int SPS = 16;                 // sources per stage
     constexpr int ROWS = 3 * kST;           // planes P0, P1, L of 128 antennas
@@ -1012,15 +1073,29 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_coh(FusedArgs a) {
                     const float r = (float)__builtin_amdgcn_fract(p);
                     const float fi = __builtin_amdgcn_sinf(-r);
                     const float fr = __builtin_amdgcn_cosf(-r);
-                    split2(w[q].s0 * fr, w[q].s0 * fi, h[0][q], l[0][q]);
-                    split2(w[q].s1 * fr, w[q].s1 * fi, h[1][q], l[1][q]);
-                    split2(w[q].lx * fr - w[q].ly * fi, w[q].lx * fi + w[q].ly * fr, h[2][q], l[2][q]);
+                    if constexpr (PREC == PB3) {
+                        split2(w[q].s0 * fr, w[q].s0 * fi, h[0][q], l[0][q]);
+                        split2(w[q].s1 * fr, w[q].s1 * fi, h[1][q], l[1][q]);
+                        split2(w[q].lx * fr - w[q].ly * fi, w[q].lx * fi + w[q].ly * fr, h[2][q], l[2][q]);
+                    } else {  // FP32: (re, im) words of each plane
+                        h[0][q] = __float_as_uint(w[q].s0 * fr);
+                        l[0][q] = __float_as_uint(w[q].s0 * fi);
+                        h[1][q] = __float_as_uint(w[q].s1 * fr);
+                        l[1][q] = __float_as_uint(w[q].s1 * fi);
+                        h[2][q] = __float_as_uint(w[q].lx * fr - w[q].ly * fi);
+                        l[2][q] = __float_as_uint(w[q].lx * fi + w[q].ly * fr);
+                    }
                 }
 #pragma unroll
                 for (int pl = 0; pl < 3; pl++) {
-                    unsigned char *row = buf + (pl * kST + as) * RS + mp * 8;
-                    *(uint2 *)row = make_uint2(h[pl][0], h[pl][1]);
-                    *(uint2 *)(row + L::PLANEB) = make_uint2(l[pl][0], l[pl][1]);
+                    if constexpr (PREC == PB3) {
+                        unsigned char *row = buf + (pl * kST + as) * RS + mp * 8;
+                        *(uint2 *)row = make_uint2(h[pl][0], h[pl][1]);
+                        *(uint2 *)(row + L::PLANEB) = make_uint2(l[pl][0], l[pl][1]);
+                    } else {  // two complex64 of sources 2 mp, 2 mp + 1
+                        unsigned char *row = buf + (pl * kST + as) * RS + mp * 16;
+                        *(u32x4 *)row = u32x4{h[pl][0], l[pl][0], h[pl][1], l[pl][1]};
+                    }
                 }
             }
         };
@@ -1038,12 +1113,21 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_coh(FusedArgs a) {
                 acc_im[t][e] = 0.f;
             }
         auto consume = [&](const unsigned char *buf) {
-            if (sq)
-                consume_sq_b3<L>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
-            else if (tri_s == 0)
-                consume_tri_b3<L, 0>(buf, tri_o, l16, lk, acc_re, acc_im);
-            else
-                consume_tri_b3<L, 1>(buf, tri_o, l16, lk, acc_re, acc_im);
+            if constexpr (PREC == PB3) {
+                if (sq)
+                    consume_sq_b3<L>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
+                else if (tri_s == 0)
+                    consume_tri_b3<L, 0>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else
+                    consume_tri_b3<L, 1>(buf, tri_o, l16, lk, acc_re, acc_im);
+            } else {
+                if (sq)
+                    consume_sq_f32<L>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
+                else if (tri_s == 0)
+                    consume_tri_f32<L, 0>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else
+                    consume_tri_f32<L, 1>(buf, tri_o, l16, lk, acc_re, acc_im);
+            }
         };
 
         if (fetcher) {
@@ -1142,7 +1226,7 @@ hipError_t launch_pair(const FusedArgs &a, hipStream_t s) {
 }
 
 int fused_path(int prec, int n_feed, int n_ax, int n_beam, int n_ant, int n_rows_pad) {
-    if (prec == PB3 && n_feed == 2 && n_ax == 2 && n_beam == 1 && n_ant > kST / 2 && n_ant <= kST)
+    if ((prec == PB3 || prec == P32) && n_feed == 2 && n_ax == 2 && n_beam == 1 && n_ant > kST / 2 && n_ant <= kST)
         return MATVIS_PATH_SOURCES;  // shared polarised beam: product over sources
     if (prec == PB3 && n_rows_pad == 2 * kST) return MATVIS_PATH_FUSED_ROWS;  // two row blocks: one item per split
     return MATVIS_PATH_FUSED;
@@ -1152,7 +1236,10 @@ hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s) {
     if (a.n_inst <= 0) return hipSuccess;
     const int path = fused_path(prec, a.n_feed, a.n_ax, a.n_beam, a.n_ant, a.n_rows_pad);
     if (path == MATVIS_PATH_SOURCES) {
-        k_herk_b3_coh<<<a.grid, 512, 0, s>>>(a);
+        if (prec == PB3)
+            k_herk_coh<PB3><<<a.grid, 512, 0, s>>>(a);
+        else
+            k_herk_coh<P32><<<a.grid, 512, 0, s>>>(a);
         return hipGetLastError();
     }
     if (path == MATVIS_PATH_FUSED_ROWS) return launch_pair(a, s);

@@ -183,11 +183,12 @@ def test_argument_errors(wl1):
         ctx.finish()
 
 
-@pytest.mark.parametrize("case", ["sources", "rows_scalar", "rows_two_beams", "fused_small", "fp32", "fp64"])
+@pytest.mark.parametrize("case", ["sources", "rows_scalar", "rows_two_beams", "fused_small", "fp32_sources",
+                                  "fp32", "fp64"])
 def test_each_product_path_matches_oracle(orc, case):
     """Every product kernel the library can pick, on the case that selects it, against the oracle."""
     import torch
-    prec = {"fp32": "fp32", "fp64": "fp64"}.get(case, "bf16x3")
+    prec = {"fp32": "fp32", "fp32_sources": "fp32", "fp64": "fp64"}.get(case, "bf16x3")
     bidx = None
     if case == "sources":        # 2 feeds x 2 axes, one beam, 65..128 antennas
         wl, path = synth.workload(2, n_ant=90, n_src=1203, n_time=2, n_freq=2), "sources"
@@ -199,8 +200,10 @@ def test_each_product_path_matches_oracle(orc, case):
         bidx = (np.arange(wl.n_ant) % 2).astype(np.int32)
     elif case == "fused_small":  # polarised, at most 64 antennas: one 128-row block
         wl, path = synth.workload(2, n_ant=40, n_src=1500, n_time=2, n_freq=2), "fused"
+    elif case == "fp32_sources":  # FP32 product over sources (2 x 2, one beam, 65..128 antennas)
+        wl, path = synth.workload(2, n_ant=90, n_src=1203, n_time=2, n_freq=2), "sources"
     elif case == "fp32":
-        wl, path = synth.workload(2, n_ant=90, n_src=1203, n_time=2, n_freq=2), "fused"
+        wl, path = synth.workload(2, n_ant=60, n_src=1203, n_time=2, n_freq=2), "fused"
     else:
         wl, path = synth.workload(2, n_ant=90, n_src=1203, n_time=2, n_freq=2), "z_in_hbm"
     say(f"product path {case}")
