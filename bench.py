@@ -56,7 +56,7 @@ def measured_traffic(path: str):
     summary exists for this path or a source it depends on (the kernel, and the host
     code that sizes its launches) changed since it was taken."""
     import hashlib
-    f = os.path.join(ROOT, "profiles", {"sources": "herk_b3_coh_workload2.json"}.get(path, "none.json"))
+    f = os.path.join(ROOT, "profiles", {"sources": "herk_coh_bf16x3_workload2.json"}.get(path, "none.json"))
     if not os.path.exists(f):
         return None
     rec = json.load(open(f))
