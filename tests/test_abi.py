@@ -88,6 +88,28 @@ def test_learned_beam_entry_points_reject_null_arguments():
                                  None, None) == mv.EINVAL
 
 
+def test_redundancy_entry_points_reject_bad_arguments():
+    # host-side checks, before any device call
+    import ctypes as C
+    L = mv.load_library()
+    pos = (C.c_double * 6)(0, 0, 0, 10, 0, 0)
+    g = (C.c_int32 * 3)()
+    ra, rb = (C.c_int32 * 3)(), (C.c_int32 * 3)()
+    nu = C.c_int32()
+    assert L.matvis_redundant_groups(None, None, 2, 1e-3, g, ra, rb, C.byref(nu)) == mv.EINVAL
+    assert L.matvis_redundant_groups(pos, None, 2, 0.0, g, ra, rb, C.byref(nu)) == mv.EINVAL
+    assert L.matvis_redundant_groups(pos, None, 0, 1e-3, g, ra, rb, C.byref(nu)) == mv.EINVAL
+    assert L.matvis_redundant_groups(pos, None, 2, 1e-3, g, ra, rb, C.byref(nu)) == mv.OK and nu.value == 2
+    pa, pb = (C.c_int32 * 1)(0), (C.c_int32 * 1)(1)
+    al, sz, de, na, ns = (C.c_int32 * 2)(), (C.c_int32 * 1)(), (C.c_double * 1)(), C.c_int32(), C.c_int32()
+    assert L.matvis_submatrix_plan(pa, pb, 1, 2, 0, al, sz, de, C.byref(na), C.byref(ns)) == mv.EINVAL
+    assert L.matvis_submatrix_plan(pa, pb, 1, 1, 1, al, sz, de, C.byref(na), C.byref(ns)) == mv.EINVAL  # b >= n_ant
+    assert L.matvis_submatrix_plan(pa, pb, 1, 2, 1, al, sz, de, C.byref(na), C.byref(ns)) == mv.OK
+    assert (na.value, ns.value, sz[0], de[0]) == (1, 1, 1, 1.0)
+    assert L.matvis_set_pairs(None, pa, pb, 1, 1, None) == mv.EINVAL
+    assert L.matvis_simulate_pairs(None, None, None, None, 1, None, 1, None, 1, None, None, None, None) == mv.EINVAL
+
+
 def test_binding_refuses_without_library(monkeypatch):
     monkeypatch.setattr(mv, "_lib", None)
     monkeypatch.setattr(mv, "LIB_PATH", "/nonexistent/libmatvis.so")
