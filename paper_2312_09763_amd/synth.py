@@ -25,6 +25,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import Optional
 
 import numpy as np
@@ -226,12 +228,21 @@ def lognormal_field(rng: np.random.Generator, ra: np.ndarray, dec: np.ndarray,
     ph = rng.uniform(0.0, 2.0 * math.pi, n_waves)
     amp = math.sqrt(2.0 / n_waves)
     out = np.empty(ra.shape)
-    for s in range(0, ra.size, chunk):
+
+    def one(s):
         e = min(ra.size, s + chunk)
         cd = np.cos(dec[s:e])
         xyz = np.stack([np.cos(ra[s:e]) * cd, np.sin(ra[s:e]) * cd, np.sin(dec[s:e])], axis=1)
-        g = amp * np.cos(xyz @ kvec.T + ph[None, :]).sum(axis=1)
+        # the products one at a time (not a BLAS call), so the values do not depend on threading
+        arg = ph[None, :] + xyz[:, 0:1] * kvec[None, :, 0]
+        arg += xyz[:, 1:2] * kvec[None, :, 1]
+        arg += xyz[:, 2:3] * kvec[None, :, 2]
+        g = amp * np.cos(arg).sum(axis=1)
         out[s:e] = np.exp(g - 0.5)
+
+    # chunks are independent: numpy releases the GIL inside each chunk's work
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(one, range(0, ra.size, chunk)))
     return out
 
 

@@ -6,7 +6,10 @@ post-horizon count swings between about 40 % and 60 % over the day, 16 LSTs x
 direct sum on sampled antenna pairs (with the autocorrelations the
 Cauchy-Schwarz error needs) of sampled instances, and checked for exact
 Hermitian symmetry everywhere.  Workload 3 (350 antennas, equal-area pixels
-with a log-normal sky) runs on a coarser pixelisation of the same kind.
+with a log-normal sky) runs on a coarser pixelisation of the same kind with
+several instances, and at its full pixel count (3 145 728) on one LST at the
+two ends of its band; workload 5 (the same sky, 350 polarised antennas, 700
+rows of Z) at its full pixel count.
 """
 import numpy as np
 import pytest
@@ -67,4 +70,47 @@ def test_workload3_diffuse_sky(precision):
     pairs = sample_pairs(wl.n_ant, 60, 5)
     ecs, ef = sampled_err_cs(Vh, wl, precision, instances, pairs)
     say(f"  sampled err_CS {ecs:.3e} err_F {ef:.3e}")
+    assert ecs <= 1e-5 and ef <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def wl3_full():
+    return synth.workload(3, n_time=1, n_freq=2)
+
+
+def _full_pixel_case(wl, precision, n_pairs, seed):
+    cfg = mv.config_for(wl, precision)
+    d = mv.device_inputs(wl, precision)
+    with mv.Context(cfg) as ctx:
+        V = ctx.simulate(**d)
+        ctx.finish()
+        _, count, _, _ = ctx.step_sky(d["lsts"], d["src_radec"])
+        Vh = V.cpu().numpy()
+        path = ctx.product_path
+    say(f"  path {path}; visible {int(count[0])} of {wl.n_src}")
+    assert np.array_equal(Vh, np.conj(np.transpose(Vh, (0, 1, 3, 2, 5, 4))))
+    instances = [(0, 0), (0, 1)]
+    pairs = sample_pairs(wl.n_ant, n_pairs, seed)
+    ecs, ef = sampled_err_cs(Vh.astype(np.complex128), wl, precision, instances, pairs)
+    say(f"  sampled err_CS {ecs:.3e} err_F {ef:.3e} ({len(pairs)} pairs x {len(instances)} instances)")
+    return ecs, ef
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_workload3_full_pixel_count(wl3_full, precision):
+    # every pixel of nside 512 and 350 antennas; 50 and 250 MHz (the longest phases)
+    wl = wl3_full
+    say(f"workload3 full pixel count {precision}: {wl.n_ant} antennas, {wl.n_src} pixels, "
+        f"channels {wl.freqs / 1e6} MHz")
+    ecs, ef = _full_pixel_case(wl, precision, 60, 5)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert ecs <= tol and ef <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_workload5_full_pixel_count(wl5_full, precision):
+    wl = wl5_full
+    say(f"workload5 full pixel count {precision}: {wl.n_ant} antennas x 2 feeds, {wl.n_src} pixels, "
+        f"channels {wl.freqs / 1e6} MHz")
+    ecs, ef = _full_pixel_case(wl, precision, 40, 7)
     assert ecs <= 1e-5 and ef <= 1e-5

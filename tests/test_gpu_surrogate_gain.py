@@ -149,9 +149,11 @@ def test_storage_and_beam_step_time(trained):
     assert times["surrogate"] > 0 and times["bicubic"] > 0
 
 
-def test_workload5_learned_beam_against_interpolated(trained):
-    # nside 16 (3072 equal-area pixels), 350 polarised antennas, 2 channels inside 100-200 MHz
-    wl = synth.workload(5, n_src=3072, n_time=2, n_freq=2)
+@pytest.mark.parametrize("size", ["nside16", "full"])
+def test_workload5_learned_beam_against_interpolated(trained, size, request):
+    # 350 polarised antennas, 2 channels inside 100-200 MHz; nside 16 (3072 equal-area
+    # pixels) at two LSTs, or every pixel of nside 512 (3 145 728) at one
+    wl = synth.workload(5, n_src=3072, n_time=2, n_freq=2) if size == "nside16" else request.getfixturevalue("wl5_full")
     say(f"workload5: {wl.n_ant} antennas x 2 feeds, {wl.n_src} pixels, channels {wl.freqs / 1e6} MHz")
     cfg = mv.config_for(wl, "bf16x3", beam_mode="surrogate")
     d = mv.device_inputs(wl, "bf16x3")
@@ -161,8 +163,8 @@ def test_workload5_learned_beam_against_interpolated(trained):
         ctx.finish()
         Vh = V.cpu().numpy().astype(np.complex128)
         say(f"  product path {ctx.product_path}")
-    instances = [(0, 0), (1, 1)]
-    pairs = sample_pairs(wl.n_ant, 60, 7)
+    instances = [(0, 0), (1, 1)] if size == "nside16" else [(0, 0), (0, 1)]
+    pairs = sample_pairs(wl.n_ant, 60 if size == "nside16" else 40, 7)
     ecs, ef = sampled_err_cs(Vh, wl, "bf16x3", instances, pairs)
     say(f"  learned beam vs FP64 oracle with the interpolated beam: sampled err_CS {ecs:.2e}, err_F {ef:.2e}")
     assert ecs <= 1e-3
