@@ -25,7 +25,12 @@ Also reported on the same JSON line:
 * side_by_side: the same workload through the FP64 interpolated path, the FP32
   path, and BF16X3 with the learned beam in place of interpolation (its
   weights are a random initialisation: the time does not depend on them; the
-  trained network's accuracy is measured by the tests).
+  trained network's accuracy is measured by the tests);
+* redundancy: the full product against the sub-matrix product of App. A;
+* workloads: the same units on the other synthetic workloads (the 37-antenna
+  scalar case, the batched uneven case, the diffuse-sky array at its full
+  pixel count on a sample of its instances, scalar and polarised, with the
+  interpolated and the learned beam).
 """
 from __future__ import annotations
 
@@ -85,6 +90,8 @@ def main():
     ap.add_argument("--redundancy-steps", type=int, default=2,
                     help="time the full product against the sub-matrix product (App. A) on a 350-antenna "
                          "hexagon (0 = skip)")
+    ap.add_argument("--workload-steps", type=int, default=2,
+                    help="calls timed on each of the other workloads (0 = skip them)")
     ap.add_argument("--side-steps", type=int, default=2,
                     help="steps timed for each side-by-side variant (0 = skip them)")
     args = ap.parse_args()
@@ -162,6 +169,18 @@ def main():
     z_bytes_step = float(np.sum(N * (np.ceil(wl.n_ax * counts / 64.0) * 64) * 8.0) * wl.n_freq)
     steps_ms = {k: round(v[0] / args.profile_steps, 4) for k, v in prof.items()}
     log("per-step device ms:", steps_ms)
+    # Algorithmic HBM bytes of the bandwidth-bound steps, per step.  Sky (rotation and
+    # ordered compaction): per time, X_eq read once (24 B per source) and, per visible
+    # source, index + s_hat + (za, az) written (4 + 24 + 16 B).  Beam: per visible
+    # source and time, (za, az) read (16 B) and one complex64 per channel and beam
+    # component written (the grid taps are L2 gathers, not counted).
+    n_comp = wl.n_feed * wl.n_ax * wl.beam.shape[0]
+    sky_bytes = float(wl.n_time * 24.0 * wl.n_src + np.sum(counts) * 44.0)
+    beam_bytes = float(np.sum(counts) * (16.0 + 8.0 * n_comp * wl.n_freq))
+    hbm_steps = {k: {"bytes_per_step": by, "ms_per_step": steps_ms[k],
+                     "achieved_GBps": by / (steps_ms[k] / 1e3) / 1e9 if steps_ms[k] > 0 else None,
+                     "peak_GBps": HBM_GBS}
+                 for k, by in (("sky", sky_bytes), ("beam", beam_bytes))}
 
     # ---- side by side on the same workload: the FP64 interpolated path, FP32, and
     # BF16X3 with the learned beam (random-init weights: its time does not depend on them)
@@ -230,6 +249,7 @@ def main():
                                         "product_tflops": achieved, "product_frac_of_peak": achieved / PEAK_TFLOPS[prec]}
 
     red = redundancy_section(args) if args.redundancy_steps > 0 else None
+    wls = workloads_section(args) if args.workload_steps > 0 else None
 
     # ---- CPU baseline: the FP64 oracle on one full instance, and the GPU error there
     cpu = None
@@ -280,13 +300,80 @@ def main():
         "zform": {"achieved_GBps": z_bytes_step * args.profile_steps / (zform_ms / 1e3) / 1e9 if zform_ms else None,
                   "peak_GBps": HBM_GBS},
         "step_ms": steps_ms,
+        "hbm_steps": hbm_steps,
         "side_by_side": side,
         "redundancy": red,
+        "workloads": wls,
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def workloads_section(args):
+    """Throughput of the other synthetic workloads on this GPU, in the metric's units:
+    the 37-antenna scalar case (FP64, its stated precision), the batched uneven
+    case at full size (FP32 and BF16X3), and the diffuse-sky array at its full
+    pixel count (3 145 728 pixels, 350 antennas; one LST x 8 of its channels, a
+    sample of the 64 x 128 instances), scalar with the BF16X3 product and
+    polarised with the interpolated and the learned beam (random-init weights:
+    the time does not depend on them)."""
+    import torch
+    from paper_2312_09763_amd import matvis as mv
+    from paper_2312_09763_amd import synth
+    cases = [(1, dict(), "fp64", "interpolated"), (4, dict(), "fp32", "interpolated"),
+             (4, dict(), "bf16x3", "interpolated"), (3, dict(n_time=1, n_freq=8), "bf16x3", "interpolated"),
+             (5, dict(n_time=1, n_freq=8), "bf16x3", "interpolated"), (5, dict(n_time=1, n_freq=8), "bf16x3", "learned")]
+    out = {}
+    made = {}
+    stream = torch.cuda.current_stream()
+    for cfg_id, kw, prec, beam in cases:
+        key = (cfg_id, tuple(sorted(kw.items())))
+        if key not in made:
+            made.clear()  # keep one workload's arrays at a time
+            made[key] = synth.workload(cfg_id, **kw)
+        wl = made[key]
+        extra = {"beam_mode": "surrogate"} if beam == "learned" else {}
+        cfg = mv.config_for(wl, prec, **extra)
+        d = mv.device_inputs(wl, prec)
+        with mv.Context(cfg) as ctx:
+            if beam == "learned":
+                ctx.set_surrogate(torch.from_numpy(synth.surrogate_init(0)).cuda(), 100e6, 200e6)
+            vis = ctx.simulate(**d)
+            ctx.finish()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.workload_steps):
+                ctx.simulate(**d, vis=vis)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ctx.finish()
+            ms = e0.elapsed_time(e1) / args.workload_steps
+            ctx.profile(True)
+            ctx.simulate(**d, vis=vis)
+            prof = ctx.profile_read()
+            ctx.profile(False)
+            ctx.finish()
+            _, count, _, _ = ctx.step_sky(d["lsts"], d["src_radec"])
+            counts = count.cpu().numpy().astype(np.int64)
+            path = ctx.product_path
+        N = wl.n_ant * wl.n_feed
+        K = wl.n_ax * counts
+        flops = float(np.sum((2.0 if path == "sources" else 4.0) * N * (N + 1) * K) * wl.n_freq) * PRODUCTS[prec]
+        herk_ms = prof["herk"][0]
+        tf = flops / (herk_ms / 1e3) / 1e12 if herk_ms > 0 else None
+        name = f"workload{cfg_id}_{prec}_{beam}"
+        out[name] = {"n_ant": wl.n_ant, "n_feed": wl.n_feed, "n_ax": wl.n_ax, "n_src": wl.n_src,
+                     "instances": [wl.n_time, wl.n_freq], "ms_per_call": ms,
+                     "value": wl.work_units() / (ms / 1e3), "product_path": path, "product_ms": herk_ms,
+                     "product_tflops": tf, "product_frac_of_peak": tf / PEAK_TFLOPS[prec] if tf else None,
+                     "step_ms": {k: round(v[0], 4) for k, v in prof.items()}}
+        log(f"{name}: {ms:.2f} ms per call, {wl.work_units() / (ms / 1e3):.3e} units/s, path {path}, "
+            f"product {herk_ms:.2f} ms" + (f" ({tf / PEAK_TFLOPS[prec]:.3f} of peak)" if tf else ""))
+        del vis, d
+    return out
 
 
 def redundancy_section(args):

@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
     constexpr int NC = NF * NX;       // beam components per source
     constexpr int SPS = kKC / NX;     // sources per stage
     constexpr int APB = kST / NF;     // antennas per row block
-    constexpr int NG = 256 / SPS;     // producer thread groups (one source per thread)
+    constexpr int NG = 256 / SPS;     // thread groups per wave kind (one source per thread)
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * L::BUF];
     __shared__ AntEntry tab[2 * APB];
 
@@ -280,9 +280,8 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
     const int total = a.work[a.n_inst] * n_kind;
     const int per_xcd = a.grid / 8;
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    // producer thread roles
-    const int pt = tid - 256;
-    const int msl = pt % SPS, g = pt / SPS;
+    // forming roles: source msl of the stage; group g of the thread's wave kind
+    const int msl = tid % SPS, g = (tid % 256) / SPS;
     constexpr bool diag = DIAG;
 
     for (int item = slot_x; item < total; item += a.grid) {
@@ -340,7 +339,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
             }
         }
 
-        // producer registers: direction and beam of this thread's source in the next stage
+        // direction and beam of this thread's source in the next stage
         double sx = 0.0, sy = 0.0, sz = 0.0;
         float2 w[NC];
         bool live = false;
@@ -364,6 +363,11 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
         // revolutions, on the FP64-reduced phase r in [-1/2, 1/2]:
         // F = exp(-2 pi i r) = cos(-r rev) + i sin(-r rev).  Rows past n_ant and
         // sources past the split are written as zeros (mask factor 0).
+        // The consumers form the last rows of each stage after their products (a
+        // quarter of an off-diagonal item's rows, an eighth of a diagonal one's,
+        // where the products are fewer); the producers form the rest.
+        const int n_crow = diag ? na_tot / 8 : na_tot / 4;
+        const int row0 = consumer ? na_tot - n_crow : 0, row1 = consumer ? na_tot : na_tot - n_crow;
         auto produce = [&](unsigned char *buf) {
             const bool lv = live;
             const double x0 = sx, x1 = sy, x2 = sz;
@@ -372,7 +376,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
             for (int c = 0; c < NC; c++) wl[c] = w[c];
             const bool multi_beam = a.n_beam != 1;
             int cur_b = multi_beam ? -1 : 0;
-            for (int as = g; as < na_tot; as += NG) {
+            for (int as = row0 + g; as < row1; as += NG) {
                 const AntEntry e = tab[as];
                 if (multi_beam && lv && e.b >= 0 && e.b != cur_b) {
                     for (int c = 0; c < NC; c++) wl[c] = Bm[((int64_t)e.b * NC + c) * a.ld_src + m];
@@ -436,19 +440,16 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
             }
         };
 
-        if (!consumer) fetch(0);
+        fetch(0);
         __syncthreads();  // antenna table ready
-        if (!consumer) {
-            produce(lds);
-            fetch(1);
-        }
+        produce(lds);
+        fetch(1);
         __syncthreads();
         for (int stg = 0; stg < n_stage; stg++) {
             unsigned char *cur = lds + (stg & 1) * L::BUF;
             unsigned char *nxt = lds + ((stg + 1) & 1) * L::BUF;
-            if (consumer) {
-                consume(cur);
-            } else if (stg + 1 < n_stage) {
+            if (consumer) consume(cur);
+            if (stg + 1 < n_stage) {
                 produce(nxt);
                 fetch(stg + 2);
             }
