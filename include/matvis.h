@@ -314,8 +314,10 @@ matvis_status matvis_profile_read(matvis_ctx *ctx, double *ms, int64_t *launches
  *   MATVIS_PATH_FUSED      Z formed in LDS per 128-row super-tile pair;
  *   MATVIS_PATH_FUSED_ROWS Z formed once per (instance, k-split) for all of
  *                          129..256 rows (BF16X3);
- *   MATVIS_PATH_SOURCES    2 feeds x 2 axes with one shared beam, 65..128
- *                          antennas (BF16X3): the axis sum is taken per source
+ *   MATVIS_PATH_SOURCES    2 feeds x 2 axes with one shared beam, more than
+ *                          64 antennas (BF16X3 or FP32; blocks of 128
+ *                          antennas, one item per block and two per block
+ *                          pair): the axis sum is taken per source
  *                          first, V[(a,p),(b,q)] = sum_m F_a conj(F_b) C_pq(m),
  *                          so the product runs over sources, not over the
  *                          (source, axis) columns of Z -- half the

@@ -363,10 +363,11 @@ __global__ void __launch_bounds__(512, 1) k_herk_fused(FusedArgs a) {
         // revolutions, on the FP64-reduced phase r in [-1/2, 1/2]:
         // F = exp(-2 pi i r) = cos(-r rev) + i sin(-r rev).  Rows past n_ant and
         // sources past the split are written as zeros (mask factor 0).
-        // The consumers form the last rows of each stage after their products (a
-        // quarter of an off-diagonal item's rows, an eighth of a diagonal one's,
-        // where the products are fewer); the producers form the rest.
-        const int n_crow = diag ? na_tot / 8 : na_tot / 4;
+        // The consumers form the last rows of each stage after their products (an
+        // off-diagonal item's rows: 3/8 with one beam component, whose rows are
+        // cheap to form, else 1/4; half that on a diagonal item, where the products
+        // are fewer); the producers form the rest.
+        const int n_crow = (NC == 1 ? 3 * na_tot / 8 : na_tot / 4) / (diag ? 2 : 1);
         const int row0 = consumer ? na_tot - n_crow : 0, row1 = consumer ? na_tot : na_tot - n_crow;
         auto produce = [&](unsigned char *buf) {
             const bool lv = live;
@@ -524,9 +525,9 @@ typedef RowGeom<FL<PB3>::RS, FL<PB3>::PLANEB, kKC / 16> GeomPair;  // 32 complex
 typedef RowGeom<16 * 4 * 2 + 16, 16 * 4, 1> GeomCoh;               // 16 complex per stage
 
 // Off-diagonal block: rows 16 (rb + i), columns 16 (cb + j), i, j < 4.
-template <typename L>
+template <typename L, int NACC>
 __device__ __forceinline__ void consume_sq_b3(const unsigned char *buf, int rb, int cb, int l16, int lk,
-                                              f32x4 (&re)[18], f32x4 (&im)[18]) {
+                                              f32x4 (&re)[NACC], f32x4 (&im)[NACC]) {
 #pragma unroll
     for (int ks = 0; ks < L::NKS; ks++) {
         u32x4 ah[kTI], al[kTI];
@@ -642,9 +643,9 @@ __device__ __forceinline__ void consume_tri_b3(const unsigned char *buf, int o, 
 // complex64 per element, re/im interleaved): per 4-deep k group,
 // re += a.re b.re + a.im b.im and im += a.im b.re - a.re b.im on
 // v_mfma_f32_16x16x4f32, one complex element per lane.
-template <typename L>
+template <typename L, int NACC>
 __device__ __forceinline__ void consume_sq_f32(const unsigned char *buf, int rb, int cb, int l16, int lk,
-                                               f32x4 (&re)[18], f32x4 (&im)[18]) {
+                                               f32x4 (&re)[NACC], f32x4 (&im)[NACC]) {
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
         float2 av[kTI], bv[kTI];
@@ -916,8 +917,8 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_pair(FusedArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Polarised products with one shared beam (BF16X3, 2 feeds x 2 axes, 65..128
-// antennas).  With Z[(a,p),(m,k)] = B_pk(m) F_a(m) (F the fringe factor of
+// Polarised products with one shared beam (BF16X3 or FP32, 2 feeds x 2 axes,
+// more than 64 antennas).  With Z[(a,p),(m,k)] = B_pk(m) F_a(m) (F the fringe factor of
 // antenna a, B = sqrt(I) A the same for every antenna), the sum over the
 // axis index k can be taken per source first:
 //   V[(a,p),(b,q)] = sum_m F_a(m) conj(F_b(m)) C_pq(m),
@@ -931,12 +932,16 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_pair(FusedArgs a) {
 // over the sources instead of the (source, axis) columns of Z: half the
 // multiply-adds of Z Z^H for the same result.
 //
-// Layout: 384 staged rows per stage (plane * 128 + antenna), 16 sources per
-// stage.  The waves and tiles are those of k_herk_b3_pair: the square waves
-// take V^10 (rows of L against rows of P0), the triangle waves V^00 and V^11.
-// V^10 elements with a < b are stored, conjugated, at the transposed lower
-// position of the (a, p) x (b, q) matrix, which is where the reduction reads
-// them.
+// Layout: up to 512 staged rows per stage (plane * 128 + antenna), 16 sources
+// per stage.  Antennas come in blocks of 128.  A diagonal item (block I)
+// stages P0, P1, L of the block; its waves and tiles are those of
+// k_herk_b3_pair: the square waves take V^10 (rows of L against rows of P0),
+// the triangle waves V^00 and V^11.  An off-diagonal item (blocks I > J, a
+// launch of its own) stages two planes of both blocks and computes two full
+// 128 x 128 products, a 64 x 64 quadrant per wave: kind X, P0_I P0_J^H and
+// P1_I P1_J^H; kind Y, L_I P0_J^H and L_J P0_I^H.  V^10 elements with a < b
+// are stored, conjugated, at the transposed lower position of the
+// (a, p) x (b, q) matrix, which is where the reduction reads them.
 // ---------------------------------------------------------------------------
 struct CohSrc {
     double x, y, z;  // s_hat
@@ -944,19 +949,19 @@ struct CohSrc {
     float lx, ly;    // C10 / sqrt C00 (all four 0 past the split)
 };
 
-template <int PREC>
+template <int PREC, bool OFF>
 __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
     typedef GeomCoh L;  // 144-byte rows: hi + lo bf16 planes, or one complex64 plane (FP32)
     constexpr int RS = L::RS;
     constexpr int SPS = 16;                 // sources per stage
-    constexpr int ROWS = 3 * kST;           // planes P0, P1, L of 128 antennas
+    constexpr int ROWS = 4 * kST;           // up to four planes of 128 antennas
     constexpr int BUF = ROWS * RS;
     // Antennas formed by the square waves (the rest by the triangle waves, which
     // have more products per stage): the split evens out the two waves of a SIMD.
     constexpr int SQ_ANT = 96;
     static_assert(SQ_ANT % 32 == 0 && (kST - SQ_ANT) % 32 == 0, "32 antennas per pass of a wave group");
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
-    __shared__ AntEntry tab[kST];
+    __shared__ AntEntry tab[2 * kST];
     __shared__ CohSrc src[2][SPS];
 
     const int tid = threadIdx.x;
@@ -965,10 +970,18 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
     const bool sq = wave < 4;
     const int l16 = lane & 15, lk = lane >> 4;
     const int Np = a.n_rows_pad;
-    const int total = a.work[a.n_inst];
+    // Antenna blocks of 128: per (instance, k-split), one item per diagonal block
+    // I (V^00_II, V^11_II triangles and V^10_II; OFF = false) and two per block
+    // pair I > J (OFF = true, a launch of its own): kind X, V^00_IJ = P0_I P0_J^H
+    // and V^11_IJ = P1_I P1_J^H; kind Y, V^10_IJ = L_I P0_J^H and V^10_JI =
+    // L_J P0_I^H (the conjugate of the (0, 1) entries).
+    const int nb = Np / (2 * kST);
+    const int n_kind = OFF ? nb * (nb - 1) : nb;
+    const int total = a.work[a.n_inst] * n_kind;
     const int per_xcd = a.grid / 8;
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int mp = tid % (SPS / 2);  // source pair
+    const int a0o = tid / (SPS / 2);  // off-diagonal items: antennas a0o + 64 k of the 256 of blocks I, J
     // this thread's antennas: a0, a0 + 32, ... (SQ_ANT / 32 of them, or (kST - SQ_ANT) / 32)
     const int a0 = sq ? tid / (SPS / 2) : SQ_ANT + (tid - 256) / (SPS / 2);
     // square waves: V^10 rows 16 (sq_rb + i) of L against 16 (sq_cb + j) of P0 (block units)
@@ -982,13 +995,27 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
         int lo = 0, hi = a.n_inst - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (a.work[mid] <= item)
+            if (a.work[mid] * n_kind <= item)
                 lo = mid;
             else
                 hi = mid - 1;
         }
         const int inst = lo;
-        const int s = item - a.work[inst];
+        const int local = item - a.work[inst] * n_kind;
+        const int s = local / n_kind;
+        const int kind = local % n_kind;
+        constexpr bool off = OFF;
+        const bool kind_y = off && (kind & 1);
+        int I = kind, J = kind;
+        if (off) {  // pairs (1, 0), (2, 0), (2, 1), (3, 0), ...
+            int q = kind >> 1;
+            I = 1;
+            while (q >= I) {
+                q -= I;
+                I++;
+            }
+            J = q;
+        }
         const int tslot = inst / a.nfb;
         const int f = a.f0 + inst % a.nfb;
         const int64_t M = a.count[tslot];
@@ -1001,12 +1028,13 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
 
         {
             const double nu_c = a.freqs[f] / kSpeedOfLight;
-            for (int as = tid; as < kST; as += 512) {
+            for (int as = tid; as < (off ? 2 : 1) * kST; as += 512) {
+                const int ant = as < kST ? I * kST + as : J * kST + (as - kST);
                 AntEntry e;
-                if (as < a.n_ant) {
-                    e.ux = nu_c * a.antc[3 * as];
-                    e.uy = nu_c * a.antc[3 * as + 1];
-                    e.uz = nu_c * a.antc[3 * as + 2];
+                if (ant < a.n_ant) {
+                    e.ux = nu_c * a.antc[3 * ant];
+                    e.uy = nu_c * a.antc[3 * ant + 1];
+                    e.uz = nu_c * a.antc[3 * ant + 2];
                     e.b = 0;
                 } else {
                     e.ux = e.uy = e.uz = 0.0;
@@ -1100,21 +1128,82 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
                 }
             }
         };
+        // Off-diagonal items: two planes of each of the 256 antennas of blocks I, J
+        // (X: P0, P1; Y: L, P0), block I in planes 0-1, block J in planes 2-3.
+        auto produce_off = [&](unsigned char *buf, int stage) {
+            CohSrc w[2];
+            w[0] = src[stage & 1][2 * mp];
+            w[1] = src[stage & 1][2 * mp + 1];
+            AntEntry ee[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) ee[k] = tab[a0o + 64 * k];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int as = a0o + 64 * k;
+                const int pl0 = 2 * (as >> 7), row = as & (kST - 1);
+                float vr[2][2], vi[2][2];
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    const double p = ee[k].ux * w[q].x + ee[k].uy * w[q].y + ee[k].uz * w[q].z;
+                    const float r = (float)__builtin_amdgcn_fract(p);
+                    const float fi = __builtin_amdgcn_sinf(-r);
+                    const float fr = __builtin_amdgcn_cosf(-r);
+                    if (kind_y) {
+                        vr[0][q] = w[q].lx * fr - w[q].ly * fi;
+                        vi[0][q] = w[q].lx * fi + w[q].ly * fr;
+                        vr[1][q] = w[q].s0 * fr;
+                        vi[1][q] = w[q].s0 * fi;
+                    } else {
+                        vr[0][q] = w[q].s0 * fr;
+                        vi[0][q] = w[q].s0 * fi;
+                        vr[1][q] = w[q].s1 * fr;
+                        vi[1][q] = w[q].s1 * fi;
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < 2; v++) {
+                    if constexpr (PREC == PB3) {
+                        uint32_t h0, l0, h1, l1;
+                        split2(vr[v][0], vi[v][0], h0, l0);
+                        split2(vr[v][1], vi[v][1], h1, l1);
+                        unsigned char *rp = buf + ((pl0 + v) * kST + row) * RS + mp * 8;
+                        *(uint2 *)rp = make_uint2(h0, h1);
+                        *(uint2 *)(rp + L::PLANEB) = make_uint2(l0, l1);
+                    } else {
+                        unsigned char *rp = buf + ((pl0 + v) * kST + row) * RS + mp * 16;
+                        *(u32x4 *)rp = u32x4{__float_as_uint(vr[v][0]), __float_as_uint(vi[v][0]),
+                                             __float_as_uint(vr[v][1]), __float_as_uint(vi[v][1])};
+                    }
+                }
+            }
+        };
         auto produce = [&](unsigned char *buf, int stage) {
-            if (sq)
+            if constexpr (OFF)
+                produce_off(buf, stage);
+            else if (sq)
                 produce_n(buf, stage, std::integral_constant<int, SQ_ANT / 32>{});
             else
                 produce_n(buf, stage, std::integral_constant<int, (kST - SQ_ANT) / 32>{});
         };
 
-        f32x4 acc_re[18], acc_im[18];
-        for (int t = 0; t < 18; t++)
+        constexpr int NACC = OFF ? 16 : 18;
+        f32x4 acc_re[NACC], acc_im[NACC];
+        for (int t = 0; t < NACC; t++)
             for (int e = 0; e < 4; e++) {
                 acc_re[t][e] = 0.f;
                 acc_im[t][e] = 0.f;
             }
+        // off-diagonal items: wave w takes quadrant w & 3 of product w >> 2
+        const int o_rp = !kind_y ? (wave >> 2) : (wave < 4 ? 0 : 2);       // row plane
+        const int o_cp = !kind_y ? 2 + (wave >> 2) : (wave < 4 ? 3 : 1);  // column plane
+        const int o_rb = o_rp * 8 + 4 * ((wave & 3) >> 1), o_cb = o_cp * 8 + 4 * (wave & 1);
         auto consume = [&](const unsigned char *buf) {
-            if constexpr (PREC == PB3) {
+            if constexpr (OFF) {
+                if constexpr (PREC == PB3)
+                    consume_sq_b3<L>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im);
+                else
+                    consume_sq_f32<L>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im);
+            } else if constexpr (PREC == PB3) {
                 if (sq)
                     consume_sq_b3<L>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
                 else if (tri_s == 0)
@@ -1156,14 +1245,34 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
         int ld = Np;
         asm volatile("" : "+v"(ld));
         float2 *P = (float2 *)a.part + ((int64_t)inst * a.max_splits + s) * (int64_t)Np * Np;
-        if (sq) {
+        if constexpr (OFF) {
+            // rows of the product: antennas of block (Y, waves 4-7: J, else I); columns: the other block
+            const int rblk = kind_y && wave >= 4 ? J : I, cblk = kind_y && wave >= 4 ? I : J;
+            const int r0 = 4 * ((wave & 3) >> 1), c0 = 4 * (wave & 1);
 #pragma unroll
             for (int i = 0; i < kTI; i++)
 #pragma unroll
                 for (int j = 0; j < kTI; j++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        const int ra = 16 * (sq_r0 + i) + 4 * lk + e, cb = 16 * (sq_c0 + j) + l16;
+                        const int A = rblk * kST + 16 * (r0 + i) + 4 * lk + e, Bc = cblk * kST + 16 * (c0 + j) + l16;
+                        const float vr = acc_re[i * kTI + j][e], vi = acc_im[i * kTI + j][e];
+                        if (A >= a.n_ant || Bc >= a.n_ant) continue;
+                        if (!kind_y)  // V^pp, p = wave >> 2: rows 2 A + p > columns 2 Bc + p
+                            P[(int64_t)(2 * A + (wave >> 2)) * ld + 2 * Bc + (wave >> 2)] = make_float2(vr, vi);
+                        else if (wave < 4)  // V^10 with A in I > Bc in J
+                            P[(int64_t)(2 * A + 1) * ld + 2 * Bc] = make_float2(vr, vi);
+                        else  // V^10 with A in J < Bc in I: the conjugate at (2 Bc, 2 A + 1)
+                            P[(int64_t)(2 * Bc) * ld + 2 * A + 1] = make_float2(vr, -vi);
+                    }
+        } else if (sq) {
+#pragma unroll
+            for (int i = 0; i < kTI; i++)
+#pragma unroll
+                for (int j = 0; j < kTI; j++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int ra = I * kST + 16 * (sq_r0 + i) + 4 * lk + e, cb = I * kST + 16 * (sq_c0 + j) + l16;
                         const float vr = acc_re[i * kTI + j][e], vi = acc_im[i * kTI + j][e];
                         if (ra >= a.n_ant || cb >= a.n_ant) continue;
                         if (ra >= cb)
@@ -1183,7 +1292,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
                 const int R = rows[k], C = t - b;
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    const int ra = 16 * R + 4 * lk + e, cb = 16 * C + l16;
+                    const int ra = I * kST + 16 * R + 4 * lk + e, cb = I * kST + 16 * C + l16;
                     if (ra >= a.n_ant || cb >= a.n_ant) continue;
                     P[(int64_t)(2 * ra + tri_t) * ld + 2 * cb + tri_t] = make_float2(acc_re[t][e], acc_im[t][e]);
                 }
@@ -1227,8 +1336,8 @@ hipError_t launch_pair(const FusedArgs &a, hipStream_t s) {
 }
 
 int fused_path(int prec, int n_feed, int n_ax, int n_beam, int n_ant, int n_rows_pad) {
-    if ((prec == PB3 || prec == P32) && n_feed == 2 && n_ax == 2 && n_beam == 1 && n_ant > kST / 2 && n_ant <= kST)
-        return MATVIS_PATH_SOURCES;  // shared polarised beam: product over sources
+    if ((prec == PB3 || prec == P32) && n_feed == 2 && n_ax == 2 && n_beam == 1 && n_ant > kST / 2)
+        return MATVIS_PATH_SOURCES;  // shared polarised beam: product over sources, blocks of 128 antennas
     if (prec == PB3 && n_rows_pad == 2 * kST) return MATVIS_PATH_FUSED_ROWS;  // two row blocks: one item per split
     return MATVIS_PATH_FUSED;
 }
@@ -1238,9 +1347,15 @@ hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s) {
     const int path = fused_path(prec, a.n_feed, a.n_ax, a.n_beam, a.n_ant, a.n_rows_pad);
     if (path == MATVIS_PATH_SOURCES) {
         if (prec == PB3)
-            k_herk_coh<PB3><<<a.grid, 512, 0, s>>>(a);
+            k_herk_coh<PB3, false><<<a.grid, 512, 0, s>>>(a);
         else
-            k_herk_coh<P32><<<a.grid, 512, 0, s>>>(a);
+            k_herk_coh<P32, false><<<a.grid, 512, 0, s>>>(a);
+        if (a.n_rows_pad > 2 * kST) {  // pairs of antenna blocks
+            if (prec == PB3)
+                k_herk_coh<PB3, true><<<a.grid, 512, 0, s>>>(a);
+            else
+                k_herk_coh<P32, true><<<a.grid, 512, 0, s>>>(a);
+        }
         return hipGetLastError();
     }
     if (path == MATVIS_PATH_FUSED_ROWS) return launch_pair(a, s);

@@ -255,6 +255,7 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     c->fused = prec != P64 && !(cfg->flags & MATVIS_FLAG_UNFUSED);
     const bool over_sources =
         c->fused && fused_path(prec, cfg->n_feed, cfg->n_ax, cfg->n_beam, cfg->n_ant, c->Np) == MATVIS_PATH_SOURCES;
+    if (over_sources) c->Np = (int)round_up(c->N, 2 * c->st);  // whole blocks of 128 antennas x 2 feeds
     c->ksplit = cfg->ksplit > 0 ? cfg->ksplit
                                 : (prec == P64 ? 8192 : prec == P32 ? 2048 : over_sources ? 16384 : 4096);
     c->max_splits = (int)((c->ldz + c->ksplit - 1) / c->ksplit);

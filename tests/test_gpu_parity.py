@@ -183,15 +183,19 @@ def test_argument_errors(wl1):
         ctx.finish()
 
 
-@pytest.mark.parametrize("case", ["sources", "rows_scalar", "rows_two_beams", "fused_small", "fp32_sources",
-                                  "fp32", "fp64"])
+@pytest.mark.parametrize("case", ["sources", "sources_2blocks", "sources_3blocks", "rows_scalar", "rows_two_beams",
+                                  "fused_small", "fp32_sources", "fp32_sources_3blocks", "fp32", "fp64"])
 def test_each_product_path_matches_oracle(orc, case):
     """Every product kernel the library can pick, on the case that selects it, against the oracle."""
     import torch
-    prec = {"fp32": "fp32", "fp32_sources": "fp32", "fp64": "fp64"}.get(case, "bf16x3")
+    prec = {"fp32": "fp32", "fp32_sources": "fp32", "fp32_sources_3blocks": "fp32", "fp64": "fp64"}.get(case, "bf16x3")
     bidx = None
-    if case == "sources":        # 2 feeds x 2 axes, one beam, 65..128 antennas
+    if case == "sources":        # 2 feeds x 2 axes, one beam, 65..128 antennas (one block)
         wl, path = synth.workload(2, n_ant=90, n_src=1203, n_time=2, n_freq=2), "sources"
+    elif case == "sources_2blocks":  # two blocks of 128 antennas: diagonal and off-diagonal items
+        wl, path = synth.workload(2, n_ant=200, n_src=901, n_time=2, n_freq=2), "sources"
+    elif case in ("sources_3blocks", "fp32_sources_3blocks"):  # three blocks, the last one ragged
+        wl, path = synth.workload(2, n_ant=301, n_src=700, n_time=1, n_freq=2), "sources"
     elif case == "rows_scalar":  # scalar, 129..256 rows
         wl, path = synth.workload(1, n_ant=200, n_src=999, n_time=2, n_freq=2), "fused_rows"
     elif case == "rows_two_beams":  # polarised with two unique beams
