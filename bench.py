@@ -294,7 +294,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[prec], "traffic": traffic,
                      "kernel": {"z_in_hbm": "k_herk", "fused": "k_herk_fused", "fused_rows": "k_herk_b3_pair",
-                                "sources": "k_herk_coh<2>" if prec == "bf16x3" else "k_herk_coh<1>"}[path],
+                                "fused_blocks": "k_herk_blk3",
+                                "sources": "k_herk_coh<2, false>" if prec == "bf16x3" else "k_herk_coh<1, false>"}[path],
                      "launch_ms": herk_ms_launch, "flops_per_launch": flops_launch,
                      "useful_tflops": achieved / PRODUCTS[prec]},
         "zform": {"achieved_GBps": z_bytes_step * args.profile_steps / (zform_ms / 1e3) / 1e9 if zform_ms else None,

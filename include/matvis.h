@@ -321,13 +321,20 @@ matvis_status matvis_profile_read(matvis_ctx *ctx, double *ms, int64_t *launches
  *                          first, V[(a,p),(b,q)] = sum_m F_a conj(F_b) C_pq(m),
  *                          so the product runs over sources, not over the
  *                          (source, axis) columns of Z -- half the
- *                          multiply-adds for the same V.
+ *                          multiply-adds for the same V;
+ *   MATVIS_PATH_FUSED_BLOCKS one feed, one axis, one shared beam, 257..384
+ *                          antennas (BF16X3 or FP32): three items per
+ *                          (instance, k-split), each a diagonal triangle with
+ *                          the off-diagonal block that shares its rows, so
+ *                          every row block is formed twice instead of three
+ *                          or four times.
  * Returns the path, or a negative status for a NULL context. */
 typedef enum {
     MATVIS_PATH_Z_IN_HBM = 0,
     MATVIS_PATH_FUSED = 1,
     MATVIS_PATH_FUSED_ROWS = 2,
-    MATVIS_PATH_SOURCES = 3
+    MATVIS_PATH_SOURCES = 3,
+    MATVIS_PATH_FUSED_BLOCKS = 4
 } matvis_product_path;
 
 int32_t matvis_product_path_of(const matvis_ctx *ctx);

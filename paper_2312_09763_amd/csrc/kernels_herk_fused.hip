@@ -570,6 +570,7 @@ __device__ __forceinline__ void consume_sq_b3(const unsigned char *buf, int rb, 
 // reused columns so every load has at least one column of products to hide in.
 template <int S>
 struct TriSet {
+    static constexpr int NR = 4;
     static constexpr int r[4] = {S == 0 ? 0 : 2, S == 0 ? 7 : 5, S == 0 ? 1 : 3, S == 0 ? 6 : 4};
     static constexpr int base[4] = {0, r[0] + 1, r[0] + r[1] + 2, r[0] + r[1] + r[2] + 3};
     static constexpr int ncol = S == 0 ? 8 : 6;
@@ -583,17 +584,32 @@ struct TriSet {
     }
 };
 
+// Two-row sets {S, 7 - S} of a 128-row triangle (nine tiles each), columns in
+// natural order; rows S and 7 - S double as columns S and 7 - S.
+template <int S>
+struct TriPair {
+    static constexpr int NR = 2;
+    static constexpr int r[2] = {S, 7 - S};
+    static constexpr int base[2] = {0, S + 1};
+    static constexpr int ncol = 8 - S;
+    static constexpr int order[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+    static constexpr int slot(int c) { return c == r[0] ? 0 : c == r[1] ? 1 : -1; }
+    static constexpr int next_loaded(int p) {
+        return p >= ncol ? -1 : slot(order[p]) < 0 ? p : next_loaded(p + 1);
+    }
+};
+
 // One 128-row diagonal triangle starting at LDS row o: tiles (r, c), c <= r, r in the set.
-template <typename L, int S>
-__device__ __forceinline__ void consume_tri_b3(const unsigned char *buf, int o, int l16, int lk, f32x4 (&re)[18],
-                                               f32x4 (&im)[18]) {
-    typedef TriSet<S> T;
+template <typename L, typename T, int NACC>
+__device__ __forceinline__ void consume_tri_b3(const unsigned char *buf, int o, int l16, int lk, f32x4 (&re)[NACC],
+                                               f32x4 (&im)[NACC]) {
+    constexpr int NR = T::NR;
 #pragma unroll
     for (int ks = 0; ks < L::NKS; ks++) {
         const unsigned char *p0 = buf + (o + l16) * L::RS + ks * 64 + lk * 16;  // row / column 0 of this lane
-        u32x4 ah[4], al[4];
+        u32x4 ah[NR], al[NR];
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
+        for (int k = 0; k < NR; k++) {
             ah[k] = *(const u32x4 *)(p0 + 16 * T::r[k] * L::RS);
             al[k] = *(const u32x4 *)(p0 + 16 * T::r[k] * L::RS + L::PLANEB);
         }
@@ -623,16 +639,16 @@ __device__ __forceinline__ void consume_tri_b3(const unsigned char *buf, int o, 
             __builtin_amdgcn_sched_barrier(0);
             const u32x4 wh = bf16_rot_col(bh), wl = bf16_rot_col(bl);
 #pragma unroll
-            for (int k = 0; k < 4; k++)
+            for (int k = 0; k < NR; k++)
                 if (T::r[k] >= c) mfma_pair(ah[k], bh, wh, re[T::base[k] + c], im[T::base[k] + c]);
 #pragma unroll
-            for (int k = 0; k < 4; k++)
+            for (int k = 0; k < NR; k++)
                 if (T::r[k] >= c) mfma_pair(ah[k], bl, wl, re[T::base[k] + c], im[T::base[k] + c]);
 #pragma unroll
-            for (int k = 0; k < 4; k++)
+            for (int k = 0; k < NR; k++)
                 if (T::r[k] >= c) mfma_pair(al[k], bh, wh, re[T::base[k] + c], im[T::base[k] + c]);
 #pragma unroll
-            for (int k = 0; k < 4; k++)
+            for (int k = 0; k < NR; k++)
                 if (T::r[k] == c) mfma_pair(al[k], bl, wl, re[T::base[k] + c], im[T::base[k] + c]);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -670,16 +686,16 @@ __device__ __forceinline__ void consume_sq_f32(const unsigned char *buf, int rb,
     }
 }
 
-template <typename L, int S>
-__device__ __forceinline__ void consume_tri_f32(const unsigned char *buf, int o, int l16, int lk, f32x4 (&re)[18],
-                                                f32x4 (&im)[18]) {
-    typedef TriSet<S> T;
+template <typename L, typename T, int NACC>
+__device__ __forceinline__ void consume_tri_f32(const unsigned char *buf, int o, int l16, int lk, f32x4 (&re)[NACC],
+                                                f32x4 (&im)[NACC]) {
+    constexpr int NR = T::NR;
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
         const unsigned char *p0 = buf + (o + l16) * L::RS + (kk + lk) * 8;
-        float2 av[4];
+        float2 av[NR];
 #pragma unroll
-        for (int k = 0; k < 4; k++) av[k] = *(const float2 *)(p0 + 16 * T::r[k] * L::RS);
+        for (int k = 0; k < NR; k++) av[k] = *(const float2 *)(p0 + 16 * T::r[k] * L::RS);
 #pragma unroll
         for (int q = 0; q < T::ncol; q++) {
             const int c = T::order[q];
@@ -687,7 +703,7 @@ __device__ __forceinline__ void consume_tri_f32(const unsigned char *buf, int o,
             // a column that is one of the wave's rows is already in registers
             const float2 b = kc >= 0 ? av[kc] : *(const float2 *)(p0 + 16 * c * L::RS);
 #pragma unroll
-            for (int k = 0; k < 4; k++)
+            for (int k = 0; k < NR; k++)
                 if (T::r[k] >= c) {
                     f32x4 &r = re[T::base[k] + c], &m = im[T::base[k] + c];
                     r = __builtin_amdgcn_mfma_f32_16x16x4f32(av[k].x, b.x, r, 0, 0, 0);
@@ -856,9 +872,9 @@ __global__ void __launch_bounds__(512, 1) k_herk_b3_pair(FusedArgs a) {
             if (sq)
                 consume_sq_b3<GeomPair>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
             else if (tri_s == 0)
-                consume_tri_b3<GeomPair, 0>(buf, tri_o, l16, lk, acc_re, acc_im);
+                consume_tri_b3<GeomPair, TriSet<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
             else
-                consume_tri_b3<GeomPair, 1>(buf, tri_o, l16, lk, acc_re, acc_im);
+                consume_tri_b3<GeomPair, TriSet<1>>(buf, tri_o, l16, lk, acc_re, acc_im);
         };
 
         if (fetcher) {
@@ -1207,16 +1223,16 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
                 if (sq)
                     consume_sq_b3<L>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
                 else if (tri_s == 0)
-                    consume_tri_b3<L, 0>(buf, tri_o, l16, lk, acc_re, acc_im);
+                    consume_tri_b3<L, TriSet<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
                 else
-                    consume_tri_b3<L, 1>(buf, tri_o, l16, lk, acc_re, acc_im);
+                    consume_tri_b3<L, TriSet<1>>(buf, tri_o, l16, lk, acc_re, acc_im);
             } else {
                 if (sq)
                     consume_sq_f32<L>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
                 else if (tri_s == 0)
-                    consume_tri_f32<L, 0>(buf, tri_o, l16, lk, acc_re, acc_im);
+                    consume_tri_f32<L, TriSet<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
                 else
-                    consume_tri_f32<L, 1>(buf, tri_o, l16, lk, acc_re, acc_im);
+                    consume_tri_f32<L, TriSet<1>>(buf, tri_o, l16, lk, acc_re, acc_im);
             }
         };
 
@@ -1301,6 +1317,241 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Scalar rows (one feed, one axis, one shared beam) in three blocks of 128
+// (257..384 antennas).  Each item pairs one diagonal triangle with one full
+// off-diagonal block that shares its rows, so every item stages two row blocks
+// and the three items of an (instance, k-split) form 768 rows instead of the
+// 1152 of one item per super-tile:
+//   kind 0: V_10 and the triangle of block 0;  kind 1: V_21 and block 1;
+//   kind 2: V_20 and block 2.
+// LDS plane 0 holds the column block C, plane 1 the row block R (16 sources per
+// stage).  Waves 0-3 take V_RC as four 64 x 64 wave tiles, multiply then form;
+// waves 4-7 take the triangle as two-row sets {s, 7 - s} (nine tiles each),
+// form then multiply.  With one beam, V_ab = sum_m |B_m|^2 F_a(m) conj(F_b(m)),
+// so the rows are |B_m| F_a(m): a real scale instead of a complex product.
+// ---------------------------------------------------------------------------
+struct SclSrc {
+    double x, y, z;  // s_hat
+    float g, pad;    // |B| (0 past the split)
+};
+
+template <int PREC>
+__global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
+    typedef GeomCoh L;
+    constexpr int RS = L::RS;
+    constexpr int SPS = 16;
+    constexpr int BUF = 2 * kST * RS;
+    constexpr int SQ_ROWS = 96;  // rows formed by the square waves, which have more products
+    static_assert(SQ_ROWS % 32 == 0 && (2 * kST - SQ_ROWS) % 32 == 0, "32 rows per pass of a wave group");
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
+    __shared__ AntEntry tab[2 * kST];
+    __shared__ SclSrc src[2][SPS];
+
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid / kWave;
+    const bool sq = wave < 4;
+    const int l16 = lane & 15, lk = lane >> 4;
+    const int Np = a.n_rows_pad;
+    constexpr int n_kind = 3;
+    const int total = a.work[a.n_inst] * n_kind;
+    const int per_xcd = a.grid / 8;
+    const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int mp = tid % (SPS / 2);
+    const int a0 = sq ? tid / (SPS / 2) : SQ_ROWS + (tid - 256) / (SPS / 2);
+    const int sq_r0 = 4 * (wave >> 1), sq_c0 = 4 * (wave & 1);
+    const int tri_s = (wave - 4) & 3;
+
+    for (int item = slot_x; item < total; item += a.grid) {
+        int lo = 0, hi = a.n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.work[mid] * n_kind <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int inst = lo;
+        const int local = item - a.work[inst] * n_kind;
+        const int s = local / n_kind;
+        const int kind = local % n_kind;
+        const int R = kind == 0 ? 1 : 2, C = kind == 1 ? 1 : 0, T = kind;
+        const int tri_o = (T == C ? 0 : 1) * kST;
+        const int tslot = inst / a.nfb;
+        const int f = a.f0 + inst % a.nfb;
+        const int64_t M = a.count[tslot];
+        const int64_t ms_per_split = a.kcols[inst];
+        const int64_t m_begin = (int64_t)s * ms_per_split;
+        const int64_t m_end = m_begin + ms_per_split < M ? m_begin + ms_per_split : M;
+        const int n_stage = (int)((m_end - m_begin + SPS - 1) / SPS);
+        const double *sh = a.s_hat + (int64_t)tslot * 3 * a.ld_src;
+        const float2 *Bm = (const float2 *)a.B + (int64_t)inst * a.ld_src;
+
+        {
+            const double nu_c = a.freqs[f] / kSpeedOfLight;
+            for (int as = tid; as < 2 * kST; as += 512) {
+                const int ant = (as < kST ? C : R) * kST + (as & (kST - 1));
+                AntEntry e;
+                if (ant < a.n_ant) {
+                    e.ux = nu_c * a.antc[3 * ant];
+                    e.uy = nu_c * a.antc[3 * ant + 1];
+                    e.uz = nu_c * a.antc[3 * ant + 2];
+                    e.b = 0;
+                } else {
+                    e.ux = e.uy = e.uz = 0.0;
+                    e.b = -1;
+                }
+                e.pad = 0;
+                tab[as] = e;
+            }
+        }
+
+        // per-source direction and |B|, loaded one stage ahead by the first SPS lanes of wave 0
+        const bool fetcher = tid < SPS;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        float2 fb = make_float2(0.f, 0.f);
+        auto fetch = [&](int stage) {
+            const int64_t m = m_begin + (int64_t)stage * SPS + tid;
+            fx = fy = fz = 0.0;
+            fb = make_float2(0.f, 0.f);
+            if (stage < n_stage && m < m_end) {
+                fx = sh[m];
+                fy = sh[a.ld_src + m];
+                fz = sh[2 * a.ld_src + m];
+                fb = Bm[m];
+            }
+        };
+        auto stash = [&](int stage) {
+            SclSrc &e = src[stage & 1][tid];
+            e.x = fx;
+            e.y = fy;
+            e.z = fz;
+            e.g = sqrtf(fb.x * fb.x + fb.y * fb.y);
+            e.pad = 0.f;
+        };
+        // rows a0 + 32 k (plane row >> 7) of this thread's two sources; rows of
+        // padding antennas (u = 0) only reach outputs that are never stored
+        auto produce_n = [&](unsigned char *buf, int stage, auto na) {
+            constexpr int NA = decltype(na)::value;
+            SclSrc w[2];
+            w[0] = src[stage & 1][2 * mp];
+            w[1] = src[stage & 1][2 * mp + 1];
+#pragma unroll
+            for (int k = 0; k < NA; k++) {
+                const int as = a0 + 32 * k;
+                const AntEntry e = tab[as];
+                float vr[2], vi[2];
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    const double p = e.ux * w[q].x + e.uy * w[q].y + e.uz * w[q].z;
+                    const float r = (float)__builtin_amdgcn_fract(p);
+                    vi[q] = w[q].g * __builtin_amdgcn_sinf(-r);
+                    vr[q] = w[q].g * __builtin_amdgcn_cosf(-r);
+                }
+                if constexpr (PREC == PB3) {
+                    uint32_t h0, l0, h1, l1;
+                    split2(vr[0], vi[0], h0, l0);
+                    split2(vr[1], vi[1], h1, l1);
+                    unsigned char *rp = buf + as * RS + mp * 8;
+                    *(uint2 *)rp = make_uint2(h0, h1);
+                    *(uint2 *)(rp + L::PLANEB) = make_uint2(l0, l1);
+                } else {
+                    *(u32x4 *)(buf + as * RS + mp * 16) =
+                        u32x4{__float_as_uint(vr[0]), __float_as_uint(vi[0]), __float_as_uint(vr[1]), __float_as_uint(vi[1])};
+                }
+            }
+        };
+        auto produce = [&](unsigned char *buf, int stage) {
+            if (sq)
+                produce_n(buf, stage, std::integral_constant<int, SQ_ROWS / 32>{});
+            else
+                produce_n(buf, stage, std::integral_constant<int, (2 * kST - SQ_ROWS) / 32>{});
+        };
+
+        f32x4 acc_re[16], acc_im[16];
+        for (int t = 0; t < 16; t++)
+            for (int e = 0; e < 4; e++) {
+                acc_re[t][e] = 0.f;
+                acc_im[t][e] = 0.f;
+            }
+        auto consume = [&](const unsigned char *buf) {
+            if constexpr (PREC == PB3) {
+                if (sq)
+                    consume_sq_b3<L>(buf, 8 + sq_r0, sq_c0, l16, lk, acc_re, acc_im);
+                else if (tri_s == 0)
+                    consume_tri_b3<L, TriPair<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else if (tri_s == 1)
+                    consume_tri_b3<L, TriPair<1>>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else if (tri_s == 2)
+                    consume_tri_b3<L, TriPair<2>>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else
+                    consume_tri_b3<L, TriPair<3>>(buf, tri_o, l16, lk, acc_re, acc_im);
+            } else {
+                if (sq)
+                    consume_sq_f32<L>(buf, 8 + sq_r0, sq_c0, l16, lk, acc_re, acc_im);
+                else if (tri_s == 0)
+                    consume_tri_f32<L, TriPair<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else if (tri_s == 1)
+                    consume_tri_f32<L, TriPair<1>>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else if (tri_s == 2)
+                    consume_tri_f32<L, TriPair<2>>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else
+                    consume_tri_f32<L, TriPair<3>>(buf, tri_o, l16, lk, acc_re, acc_im);
+            }
+        };
+
+        if (fetcher) {
+            fetch(0);
+            stash(0);
+            fetch(1);
+            stash(1);
+        }
+        __syncthreads();  // antenna table and the first two stages' sources ready
+        produce(lds, 0);
+        __syncthreads();
+        for (int stg = 0; stg < n_stage; stg++) {
+            unsigned char *cur = lds + (stg & 1) * BUF;
+            unsigned char *nxt = lds + ((stg + 1) & 1) * BUF;
+            const bool more = stg + 1 < n_stage;
+            if (fetcher && stg + 2 < n_stage) fetch(stg + 2);
+            if (sq) consume(cur);
+            if (more) produce(nxt, stg + 1);
+            if (!sq) consume(cur);
+            // src[stg & 1] was last read by the producers of stage stg (one stage ago)
+            if (fetcher && stg + 2 < n_stage) stash(stg + 2);
+            __syncthreads();
+        }
+
+        int ld = Np;
+        asm volatile("" : "+v"(ld));
+        float2 *P = (float2 *)a.part + ((int64_t)inst * a.max_splits + s) * (int64_t)Np * Np;
+        if (sq) {
+#pragma unroll
+            for (int i = 0; i < kTI; i++)
+#pragma unroll
+                for (int j = 0; j < kTI; j++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int A = R * kST + 16 * (sq_r0 + i) + 4 * lk + e, Bc = C * kST + 16 * (sq_c0 + j) + l16;
+                        if (A < a.n_ant && Bc < a.n_ant)
+                            P[(int64_t)A * ld + Bc] = make_float2(acc_re[i * kTI + j][e], acc_im[i * kTI + j][e]);
+                    }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 9; t++) {
+                const int Rr = t <= tri_s ? tri_s : 7 - tri_s, Cc = t <= tri_s ? t : t - tri_s - 1;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int A = T * kST + 16 * Rr + 4 * lk + e, Bc = T * kST + 16 * Cc + l16;
+                    if (A < a.n_ant && Bc < a.n_ant)
+                        P[(int64_t)A * ld + Bc] = make_float2(acc_re[t][e], acc_im[t][e]);
+                }
+            }
+        }
+    }
+}
+
 template <int PREC, bool DIAG>
 hipError_t launch_kind(const FusedArgs &a, hipStream_t s) {
     if (a.n_feed == 2 && a.n_ax == 2)
@@ -1338,6 +1589,8 @@ hipError_t launch_pair(const FusedArgs &a, hipStream_t s) {
 int fused_path(int prec, int n_feed, int n_ax, int n_beam, int n_ant, int n_rows_pad) {
     if ((prec == PB3 || prec == P32) && n_feed == 2 && n_ax == 2 && n_beam == 1 && n_ant > kST / 2)
         return MATVIS_PATH_SOURCES;  // shared polarised beam: product over sources, blocks of 128 antennas
+    if ((prec == PB3 || prec == P32) && n_feed == 1 && n_ax == 1 && n_beam == 1 && n_rows_pad == 3 * kST)
+        return MATVIS_PATH_FUSED_BLOCKS;  // scalar rows in three blocks: items pairing a triangle and a block
     if (prec == PB3 && n_rows_pad == 2 * kST) return MATVIS_PATH_FUSED_ROWS;  // two row blocks: one item per split
     return MATVIS_PATH_FUSED;
 }
@@ -1359,6 +1612,13 @@ hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s) {
         return hipGetLastError();
     }
     if (path == MATVIS_PATH_FUSED_ROWS) return launch_pair(a, s);
+    if (path == MATVIS_PATH_FUSED_BLOCKS) {
+        if (prec == PB3)
+            k_herk_blk3<PB3><<<a.grid, 512, 0, s>>>(a);
+        else
+            k_herk_blk3<P32><<<a.grid, 512, 0, s>>>(a);
+        return hipGetLastError();
+    }
     if (prec == P32) return launch_prec<P32>(a, s);
     if (prec == PB3) return launch_prec<PB3>(a, s);
     return hipErrorInvalidValue;

@@ -31,7 +31,7 @@ STEPS = ("sky", "beam", "zform", "herk", "reduce", "other")
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 BEAM_MODES = {"bilinear": BILINEAR, "bicubic": BICUBIC, "surrogate": SURROGATE}
 MLP_N_PARAMS = 83848  # learned-beam parameter count (include/matvis.h)
-PRODUCT_PATHS = ("z_in_hbm", "fused", "fused_rows", "sources")  # matvis_product_path
+PRODUCT_PATHS = ("z_in_hbm", "fused", "fused_rows", "sources", "fused_blocks")  # matvis_product_path
 
 
 class MatvisError(RuntimeError):

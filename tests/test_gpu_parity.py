@@ -184,11 +184,13 @@ def test_argument_errors(wl1):
 
 
 @pytest.mark.parametrize("case", ["sources", "sources_2blocks", "sources_3blocks", "rows_scalar", "rows_two_beams",
-                                  "fused_small", "fp32_sources", "fp32_sources_3blocks", "fp32", "fp64"])
+                                  "blocks_scalar", "fp32_blocks_scalar", "fused_small", "fp32_sources",
+                                  "fp32_sources_3blocks", "fp32", "fp64"])
 def test_each_product_path_matches_oracle(orc, case):
     """Every product kernel the library can pick, on the case that selects it, against the oracle."""
     import torch
-    prec = {"fp32": "fp32", "fp32_sources": "fp32", "fp32_sources_3blocks": "fp32", "fp64": "fp64"}.get(case, "bf16x3")
+    prec = {"fp32": "fp32", "fp32_sources": "fp32", "fp32_sources_3blocks": "fp32", "fp32_blocks_scalar": "fp32",
+            "fp64": "fp64"}.get(case, "bf16x3")
     bidx = None
     if case == "sources":        # 2 feeds x 2 axes, one beam, 65..128 antennas (one block)
         wl, path = synth.workload(2, n_ant=90, n_src=1203, n_time=2, n_freq=2), "sources"
@@ -198,6 +200,8 @@ def test_each_product_path_matches_oracle(orc, case):
         wl, path = synth.workload(2, n_ant=301, n_src=700, n_time=1, n_freq=2), "sources"
     elif case == "rows_scalar":  # scalar, 129..256 rows
         wl, path = synth.workload(1, n_ant=200, n_src=999, n_time=2, n_freq=2), "fused_rows"
+    elif case in ("blocks_scalar", "fp32_blocks_scalar"):  # scalar, 257..384 rows, the last block ragged
+        wl, path = synth.workload(1, n_ant=300, n_src=1100, n_time=2, n_freq=2), "fused_blocks"
     elif case == "rows_two_beams":  # polarised with two unique beams
         wl, path = synth.workload(2, n_ant=100, n_src=777, n_time=2, n_freq=2), "fused_rows"
         wl.beam = np.concatenate([wl.beam, 0.7 * wl.beam ** 2], axis=0)
