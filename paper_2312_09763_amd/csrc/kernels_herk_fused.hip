@@ -12,7 +12,8 @@
 //   F = cospi(2r) - i sinpi(2r)           (FP32 sincospi),
 //   Z[(a, p)][(m, k)] = B_{beam(a), p, k}(m) F,  B = sqrt(I) A (from the beam step),
 // and write it to the other LDS buffer (complex64 on FP32; bf16 hi / lo planes
-// on BF16X3).  One barrier per stage swaps the buffers, so the VALU work of
+// on BF16X3); the consumers form the last rows of each stage after their
+// products.  One barrier per stage swaps the buffers, so the VALU work of
 // the producers overlaps the matrix-core work of the consumers on every SIMD
 // (one wave of each kind per SIMD).
 //
