@@ -183,9 +183,10 @@ def test_argument_errors(wl1):
         ctx.finish()
 
 
-@pytest.mark.parametrize("case", ["sources", "sources_2blocks", "sources_3blocks", "rows_scalar", "rows_two_beams",
-                                  "blocks_scalar", "fp32_blocks_scalar", "fused_small", "fp32_sources",
-                                  "fp32_sources_3blocks", "fp32", "fp64"])
+@pytest.mark.parametrize("case", ["sources", "sources_2blocks", "sources_3blocks", "sources_129", "sources_256",
+                                  "rows_scalar", "rows_two_beams", "blocks_scalar", "blocks_257", "blocks_384",
+                                  "fp32_blocks_scalar", "fused_small", "fp32_sources", "fp32_sources_3blocks", "fp32",
+                                  "fp64"])
 def test_each_product_path_matches_oracle(orc, case):
     """Every product kernel the library can pick, on the case that selects it, against the oracle."""
     import torch
@@ -196,6 +197,10 @@ def test_each_product_path_matches_oracle(orc, case):
         wl, path = synth.workload(2, n_ant=90, n_src=1203, n_time=2, n_freq=2), "sources"
     elif case == "sources_2blocks":  # two blocks of 128 antennas: diagonal and off-diagonal items
         wl, path = synth.workload(2, n_ant=200, n_src=901, n_time=2, n_freq=2), "sources"
+    elif case in ("sources_129", "sources_256"):  # one antenna in the second block; two full blocks
+        wl, path = synth.workload(2, n_ant=int(case[-3:]), n_src=400, n_time=1, n_freq=2), "sources"
+    elif case in ("blocks_257", "blocks_384"):  # one row in the third block; three full blocks
+        wl, path = synth.workload(1, n_ant=int(case[-3:]), n_src=500, n_time=1, n_freq=2), "fused_blocks"
     elif case in ("sources_3blocks", "fp32_sources_3blocks"):  # three blocks, the last one ragged
         wl, path = synth.workload(2, n_ant=301, n_src=700, n_time=1, n_freq=2), "sources"
     elif case == "rows_scalar":  # scalar, 129..256 rows
