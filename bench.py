@@ -83,6 +83,7 @@ def main():
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--unfused", action="store_true", help="write Z to HBM in its own step (FP32 / BF16X3)")
+    ap.add_argument("--batch-time", type=int, default=0, help="times per device batch (0 = the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-src", type=int, default=None, help="shrink the workload (smoke runs only)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -118,7 +119,7 @@ def main():
     prec = args.precision
     wl = synth.workload(2, n_src=args.n_src)
     log(f"workload2: n_ant={wl.n_ant} n_src={wl.n_src} n_time={wl.n_time} n_freq={wl.n_freq} precision={prec}")
-    cfg = mv.config_for(wl, prec, unfused=args.unfused)
+    cfg = mv.config_for(wl, prec, unfused=args.unfused, batch_time=args.batch_time)
     ctx = mv.Context(cfg)
     d = mv.device_inputs(wl, prec)
     vis = torch.empty((wl.n_time, wl.n_freq, wl.n_ant, wl.n_ant, wl.n_feed, wl.n_feed), dtype=ctx.complex_dtype,

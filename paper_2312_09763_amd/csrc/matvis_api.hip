@@ -267,9 +267,7 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
                    (size_t)c->max_splits * c->Np * c->Np * cbytes(prec);
     size_t budget = (size_t)12 << 30;
     int ntb_auto = (int)std::max<size_t>(1, budget / std::max<size_t>(1, zinst * c->nfb));
-    // up to 32 times: one launch of each step per 512 instances of the benchmark
-    // workload (32 against 16 saved ~1 % of its step in launch and tail time)
-    c->ntb = cfg->batch_time > 0 ? cfg->batch_time : std::min(ntb_auto, 32);
+    c->ntb = cfg->batch_time > 0 ? cfg->batch_time : std::min(ntb_auto, 16);
     c->ntb = std::max(1, std::min(c->ntb, cfg->max_time));
     const int B = c->ntb * c->nfb;
     c->nblk_cap = std::max<int64_t>((c->chunk + 255) / 256, 1);
