@@ -58,17 +58,19 @@ def test_polarised_sky_matches_oracle(wl_pol, precision):
     assert float(metrics.err_cs(ref_i, ref).max()) > 1e-2
 
 
-def test_polarised_sky_product_over_sources():
-    # 2 feeds x 2 axes, one beam, 65..128 antennas: the product over sources
-    wl = synth.workload(2, n_ant=90, n_src=1203, n_time=2, n_freq=2)
+@pytest.mark.parametrize("n_ant,prec", [(90, "bf16x3"), (230, "bf16x3"), (230, "fp32")])
+def test_polarised_sky_product_over_sources(n_ant, prec):
+    # 2 feeds x 2 axes, one beam: the product over sources, one block of 128
+    # antennas or two (diagonal and off-diagonal items)
+    wl = synth.workload(2, n_ant=n_ant, n_src=1203 if n_ant < 128 else 800, n_time=2, n_freq=2)
     st = synth.polarised_stokes(wl.flux, wl.freqs, seed=14)
-    V, path = _run(wl, st, "bf16x3")
+    V, path = _run(wl, st, prec)
     assert path == "sources"
-    ref = oracle.simulate(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, st, grid_as_used(wl, "bf16x3"), wl.latitude,
+    ref = oracle.simulate(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, st, grid_as_used(wl, prec), wl.latitude,
                           wl.dza, wl.daz, wl.interp)
     ecs = float(metrics.err_cs(V.astype(np.complex128), ref).max())
-    say(f"polarised sky, product over sources: err_CS {ecs:.2e}")
-    assert ecs <= TOL["bf16x3"]
+    say(f"polarised sky, product over sources, {n_ant} antennas {prec}: err_CS {ecs:.2e}")
+    assert ecs <= TOL[prec]
 
 
 def test_polarised_sky_per_antenna_beams_rows_path():
