@@ -79,22 +79,36 @@ __global__ void __launch_bounds__(kSkyBlock) k_xeq_cells(const double *__restric
     for (int c = threadIdx.x; c < kCells; c += kSkyBlock) hist[(int64_t)blockIdx.x * kCells + c] = h[c];
 }
 
-// hist[b][c] -> first position of block b's cell-c sources in the cell-major order.
-// Each thread walks its cell's column of blocks kU entries at a time, so the
-// loads of a group are in flight together (the walk is latency-bound).
-__global__ void __launch_bounds__(1024) k_cell_offsets(int32_t *__restrict__ hist, int nblk) {
-    constexpr int kU = 16;
+// hist[b][c] -> first position of block b's cell-c sources in the cell-major
+// order, in three passes over chunks of `chunk` blocks (a multiple of 8 giving
+// at most 256 chunks) so that every pass reads whole rows of hist (coalesced)
+// and all CUs take part:
+//   k_cell_chunk_sums:    part[ch][c] = cell-c count over the blocks of chunk ch;
+//   k_cell_chunk_offsets: cell totals scanned (exclusive), then each cell's
+//                         chunks scanned on top: part[ch][c] = first position of
+//                         chunk ch's cell-c sources (one workgroup);
+//   k_cell_apply:         each chunk walks its blocks, hist[b][c] = position.
+__host__ __device__ inline int cell_chunk(int nblk) { return ((nblk + 255) / 256 + 7) / 8 * 8; }
+
+__global__ void __launch_bounds__(256) k_cell_chunk_sums(const int32_t *__restrict__ hist, int nblk, int chunk,
+                                                         int32_t *__restrict__ part) {
+    const int ch = blockIdx.x;
+    const int b0 = ch * chunk, b1 = nblk < b0 + chunk ? nblk : b0 + chunk;
+    for (int c = threadIdx.x; c < kCells; c += 256) {
+        int run = 0;
+#pragma unroll 8
+        for (int b = b0; b < b1; b++) run += hist[(int64_t)b * kCells + c];
+        part[(int64_t)ch * kCells + c] = run;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_cell_chunk_offsets(int32_t *__restrict__ part, int nchunk) {
     __shared__ int tot[kCells];
     __shared__ int wsum[1024 / kWave];
     for (int c = threadIdx.x; c < kCells; c += 1024) {
         int run = 0;
-        for (int b0 = 0; b0 < nblk; b0 += kU) {
-            int v[kU];
-#pragma unroll
-            for (int u = 0; u < kU; u++) v[u] = b0 + u < nblk ? hist[(int64_t)(b0 + u) * kCells + c] : 0;
-#pragma unroll
-            for (int u = 0; u < kU; u++) run += v[u];
-        }
+#pragma unroll 16
+        for (int ch = 0; ch < nchunk; ch++) run += part[(int64_t)ch * kCells + c];
         tot[c] = run;
     }
     __syncthreads();
@@ -123,16 +137,25 @@ __global__ void __launch_bounds__(1024) k_cell_offsets(int32_t *__restrict__ his
     }
     for (int c = threadIdx.x; c < kCells; c += 1024) {
         int run = tot[c];
-        for (int b0 = 0; b0 < nblk; b0 += kU) {
-            int v[kU];
-#pragma unroll
-            for (int u = 0; u < kU; u++) v[u] = b0 + u < nblk ? hist[(int64_t)(b0 + u) * kCells + c] : 0;
-#pragma unroll
-            for (int u = 0; u < kU; u++)
-                if (b0 + u < nblk) {
-                    hist[(int64_t)(b0 + u) * kCells + c] = run;
-                    run += v[u];
-                }
+        for (int ch = 0; ch < nchunk; ch++) {
+            const int v = part[(int64_t)ch * kCells + c];
+            part[(int64_t)ch * kCells + c] = run;
+            run += v;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cell_apply(int32_t *__restrict__ hist, int nblk, int chunk,
+                                                    const int32_t *__restrict__ part) {
+    const int ch = blockIdx.x;
+    const int b0 = ch * chunk, b1 = nblk < b0 + chunk ? nblk : b0 + chunk;
+    for (int c = threadIdx.x; c < kCells; c += 256) {
+        int run = part[(int64_t)ch * kCells + c];
+#pragma unroll 8
+        for (int b = b0; b < b1; b++) {
+            const int v = hist[(int64_t)b * kCells + c];
+            hist[(int64_t)b * kCells + c] = run;
+            run += v;
         }
     }
 }
@@ -358,14 +381,23 @@ hipError_t launch_xeq_sorted(const double *radec, int64_t n_src, int64_t ld, Sor
     k_xeq_cells<<<nblk, kSkyBlock, 0, s>>>(radec, n_src, sb.xeq_in, ld, sb.cell, sb.hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_cell_offsets<<<1, 1024, 0, s>>>(sb.hist, nblk);
+    // chunk partials after the per-block counts (sort_hist_entries leaves room)
+    const int chunk = cell_chunk(nblk);
+    const int nchunk = (nblk + chunk - 1) / chunk;
+    int32_t *part = sb.hist + (int64_t)nblk * kCells;
+    k_cell_chunk_sums<<<nchunk, 256, 0, s>>>(sb.hist, nblk, chunk, part);
+    k_cell_chunk_offsets<<<1, 1024, 0, s>>>(part, nchunk);
+    k_cell_apply<<<nchunk, 256, 0, s>>>(sb.hist, nblk, chunk, part);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_cell_scatter<<<nblk, kSkyBlock, 0, s>>>(sb.xeq_in, n_src, ld, sb.cell, sb.hist, xeq, sb.perm);
     return hipGetLastError();
 }
 
-int64_t sort_hist_entries(int64_t max_src) { return ((max_src + kSkyBlock - 1) / kSkyBlock) * kCells; }
+int64_t sort_hist_entries(int64_t max_src) {
+    const int64_t nblk = (max_src + kSkyBlock - 1) / kSkyBlock;
+    return (nblk + (nblk + 7) / 8) * kCells;  // per-block counts, then per-chunk partials (chunks of >= 8 blocks)
+}
 
 hipError_t launch_rotmats(const double *lsts, int32_t n_time, double latitude, double *rot, hipStream_t s) {
     if (n_time <= 0) return hipSuccess;
