@@ -120,11 +120,15 @@ def test_no_visible_sources_and_no_sources():
         assert torch.count_nonzero(vis).item() == 0
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
-def test_deterministic_hermitian_and_graph_equals_direct(wl2_small, precision):
+@pytest.mark.parametrize("precision,case", [("fp64", "wl2"), ("bf16x3", "wl2"), ("bf16x3", "sources_3blocks"),
+                                            ("fp32", "sources_3blocks"), ("bf16x3", "blocks_scalar")])
+def test_deterministic_hermitian_and_graph_equals_direct(wl2_small, precision, case):
     import torch
-    cfg = mv.config_for(wl2_small, precision)
-    d = mv.device_inputs(wl2_small, precision)
+    wl = {"wl2": lambda: wl2_small,
+          "sources_3blocks": lambda: synth.workload(2, n_ant=301, n_src=611, n_time=2, n_freq=2),
+          "blocks_scalar": lambda: synth.workload(1, n_ant=300, n_src=1100, n_time=2, n_freq=2)}[case]()
+    cfg = mv.config_for(wl, precision)
+    d = mv.device_inputs(wl, precision)
     with mv.Context(cfg) as ctx:
         a = ctx.simulate(**d).clone()
         b = ctx.simulate(**d).clone()  # graph replay
