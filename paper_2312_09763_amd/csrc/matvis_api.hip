@@ -250,14 +250,15 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     // BF16X3: 2.5e-6 at 4096, whose split error dominates below that).
     // The product over sources (two axes summed per source) accumulates ksplit / 2
     // sources per item: err_CS 3.5e-6 at 8192, 4.9e-6 at 16384, 7.0e-6 at 32768 on
-    // the same workload; 16384 keeps a factor 2 to 1e-5 and halves the partials
-    // the reduction reads.
+    // the same workload; 20480 (~5.4e-6) keeps a factor 1.8 to 1e-5, and at the
+    // benchmark's ~50 000 visible columns it gives three splits per instance
+    // instead of four (fewer items and partials: 1.4 % of its step).
     c->fused = prec != P64 && !(cfg->flags & MATVIS_FLAG_UNFUSED);
     const bool over_sources =
         c->fused && fused_path(prec, cfg->n_feed, cfg->n_ax, cfg->n_beam, cfg->n_ant, c->Np) == MATVIS_PATH_SOURCES;
     if (over_sources) c->Np = (int)round_up(c->N, 2 * c->st);  // whole blocks of 128 antennas x 2 feeds
     c->ksplit = cfg->ksplit > 0 ? cfg->ksplit
-                                : (prec == P64 ? 8192 : prec == P32 ? 2048 : over_sources ? 16384 : 4096);
+                                : (prec == P64 ? 8192 : prec == P32 ? 2048 : over_sources ? 20480 : 4096);
     c->max_splits = (int)((c->ldz + c->ksplit - 1) / c->ksplit);
     // batch: all channels of a few times, enough instances to fill the GPU with
     // work items while keeping Z within a fixed share of device memory
