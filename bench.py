@@ -108,7 +108,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the simulator shards (t, nu) instances "
-              f"across GPUs with no communication, but multi-GPU runs are not part of this build.", file=sys.stderr)
+              f"across GPUs with no communication; this benchmark measures one GPU.", file=sys.stderr)
         sys.exit(2)
 
     import torch
