@@ -257,13 +257,20 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     const bool over_sources =
         c->fused && fused_path(prec, cfg->n_feed, cfg->n_ax, cfg->n_beam, cfg->n_ant, c->Np) == MATVIS_PATH_SOURCES;
     if (over_sources) c->Np = (int)round_up(c->N, 2 * c->st);  // whole blocks of 128 antennas x 2 feeds
+    // FP32 product over sources: 8192 (err_CS 2.9e-6 on the benchmark instance,
+    // against 0.8e-6 at 2048 and 1.5e-6 at 4096; the step 28.7 -> 27.3 ms).
     // scalar rows in three blocks (BF16X3): 8192 columns per split (err_CS 3.5e-6
     // against 2.8e-6 at 4096 on the 350-antenna diffuse sky, with half the partials:
     // its reduction went from 0.82 to 0.46 ms per two instances)
     const bool three_blocks =
         c->fused && fused_path(prec, cfg->n_feed, cfg->n_ax, cfg->n_beam, cfg->n_ant, c->Np) == MATVIS_PATH_FUSED_BLOCKS;
     c->ksplit = cfg->ksplit > 0 ? cfg->ksplit
-                                : (prec == P64 ? 8192 : prec == P32 ? 2048 : over_sources ? 20480 : three_blocks ? 8192 : 4096);
+                                : (prec == P64            ? 8192
+                                   : prec == P32 && over_sources ? 8192
+                                   : prec == P32            ? 2048
+                                   : over_sources           ? 20480
+                                   : three_blocks           ? 8192
+                                                            : 4096);
     c->max_splits = (int)((c->ldz + c->ksplit - 1) / c->ksplit);
     // batch: all channels of a few times, enough instances to fill the GPU with
     // work items while keeping Z within a fixed share of device memory
