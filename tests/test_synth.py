@@ -100,3 +100,13 @@ def test_workloads_shapes():
     wl = synth.workload(3, n_ant=20, n_src=12 * 16 * 16, n_time=2, n_freq=3)
     mean_t = wl.flux[0].sum() / (4 * math.pi / 3072) / 3072 / (wl.freqs[0] / 150e6) ** -0.5
     assert wl.n_src == 3072 and abs(mean_t - 1) < 0.3  # log-normal brightness has mean 1
+
+
+def test_lognormal_field_independent_of_chunking():
+    # the chunks run on a thread pool: the field must not depend on how the
+    # pixels are cut, and it is log-normal with unit mean in expectation
+    ra, dec = synth.ring_pixel_centres(16)
+    f1 = synth.lognormal_field(np.random.Generator(np.random.PCG64(3)), ra, dec, chunk=1 << 16)
+    f2 = synth.lognormal_field(np.random.Generator(np.random.PCG64(3)), ra, dec, chunk=97)
+    np.testing.assert_array_equal(f1, f2)
+    assert np.all(f1 > 0) and 0.5 < f1.mean() < 1.5
