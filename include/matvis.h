@@ -273,9 +273,11 @@ matvis_status matvis_set_surrogate(matvis_ctx *ctx, const float *params, double 
  * caller's own inputs for each candidate that fits in device memory and
  * returns in *best a copy of *base with the fastest ksplit, batch_time and
  * MATVIS_FLAG_UNFUSED choice, and the time of one call in *best_ms (host
- * pointers).  Candidate k-splits are limited per precision so that FP32
- * accumulation stays well inside the precision's tolerance (FP32 <= 2048,
- * BF16X3 <= 8192 columns).  If cache_path is not NULL, results are read from
+ * pointers).  The candidates include 0 for ksplit and batch_time (the
+ * library's own choice for the precision and product path), so the result is
+ * never slower than the defaults; the other candidate k-splits are at most
+ * the fused paths' defaults (FP32 <= 2048, BF16X3 <= 8192 columns), so FP32
+ * accumulation stays as accurate as with the defaults or more.  If cache_path is not NULL, results are read from
  * and written to that JSON file, keyed by GPU architecture, rows, axes,
  * sources, times, channels, precision and beam mode; a cached entry is
  * returned without timing.  vis is overwritten.  Synchronous.

@@ -2,8 +2,9 @@
 //
 // The search space is small and discrete, so it is searched exhaustively on
 // the caller's own inputs: for each candidate (k-split, times per batch,
-// fused or unfused Z) a context is created, one call captures and warms the
-// graph, and two replays are timed with HIP events.  Candidates that do not
+// fused or unfused Z; 0 for the library's own choice) a context is created,
+// one call captures and warms the graph, and two replays are timed with HIP
+// events.  Candidates that do not
 // fit in device memory are skipped.  Winners are cached in a JSON file, one
 // entry per line:
 //   "gfx950|N256|ax2|src50000|t32|f16|p2|b1": {"ksplit": 4096, "batch_time": 8, "flags": 0, "ms": 23.1},
@@ -39,11 +40,12 @@ std::map<std::string, Entry> read_cache(const char *path) {
         const std::string key = line.substr(q0 + 1, q1 - q0 - 1);
         Entry e;
         const char *p;
-        if ((p = strstr(line.c_str(), "\"ksplit\":"))) e.ksplit = atoll(p + 9);
-        if ((p = strstr(line.c_str(), "\"batch_time\":"))) e.batch_time = atoi(p + 13);
+        bool has_k = false, has_t = false;  // 0 is a valid value: the library's own choice
+        if ((p = strstr(line.c_str(), "\"ksplit\":"))) e.ksplit = atoll(p + 9), has_k = true;
+        if ((p = strstr(line.c_str(), "\"batch_time\":"))) e.batch_time = atoi(p + 13), has_t = true;
         if ((p = strstr(line.c_str(), "\"flags\":"))) e.flags = atoi(p + 8);
         if ((p = strstr(line.c_str(), "\"ms\":"))) e.ms = atof(p + 5);
-        if (e.ksplit > 0 && e.batch_time > 0) out[key] = e;
+        if (has_k && has_t && e.ksplit >= 0 && e.batch_time >= 0 && e.ms > 0) out[key] = e;
     }
     return out;
 }
@@ -95,17 +97,19 @@ extern "C" matvis_status matvis_autotune(const matvis_config *base, const double
         return MATVIS_OK;
     }
 
+    // 0 is the library's own choice (per precision and product path), so the
+    // winner is never slower than the defaults; the other k-splits are at most
+    // the defaults of the fused paths, so never less accurate than them
     std::vector<long long> ksplits;
     if (base->precision == MATVIS_FP64)
-        ksplits = {4096, 8192, 16384};
+        ksplits = {0, 4096, 16384};
     else if (base->precision == MATVIS_FP32)
-        ksplits = {1024, 2048};
+        ksplits = {0, 1024, 2048};
     else
-        ksplits = {2048, 4096, 8192};
-    std::vector<int> tbs;
+        ksplits = {0, 2048, 4096, 8192};
+    std::vector<int> tbs = {0};
     for (int tb : {2, 4, 8})
         if (tb <= base->max_time) tbs.push_back(tb);
-    if (tbs.empty()) tbs.push_back(base->max_time);
     std::vector<int> fuse = {0};
     if (base->precision != MATVIS_FP64) fuse.push_back(MATVIS_FLAG_UNFUSED);
 
