@@ -25,14 +25,25 @@ _SO = os.path.join(_OUT_DIR, "liboracle.so")
 _lib = None
 
 
+_SO_LD = os.path.join(_OUT_DIR, "liboracle_ld.so")
+_lib_ld = None
+
+
+def _gcc(out: str, extra) -> None:
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off"] +
+                          list(extra) + ["-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile the C reference with gcc (plain -O2, IEEE semantics, OpenMP)."""
+    """Compile the C reference with gcc (plain -O2, IEEE semantics, OpenMP): the
+    double build, and the same source with long double arithmetic (used only to
+    bound the double build's own rounding on small cases)."""
     os.makedirs(_OUT_DIR, exist_ok=True)
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _SO)
+    for so, extra in ((_SO, []), (_SO_LD, ['-DORC_REAL=long double'])):
+        if force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(_SRC):
+            _gcc(so, extra)
     return _SO
 
 
@@ -46,10 +57,30 @@ def lib():
     return _lib
 
 
+def lib_ld():
+    """The long double build (same source, ORC_REAL = long double)."""
+    global _lib_ld
+    if _lib_ld is None:
+        if not os.path.exists(_SO_LD) or os.path.getmtime(_SO_LD) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib_ld = ctypes.CDLL(_SO_LD)
+        _lib_ld.orc_simulate.argtypes = [ctypes.POINTER(GeomLD)] + [_P] * 3 + [ctypes.c_int32, _P, ctypes.c_int64] + \
+            [_P] * 4 + [ctypes.c_int32] + [_P] * 3
+        _lib_ld.orc_simulate.restype = ctypes.c_int
+    return _lib_ld
+
+
 class Geom(ctypes.Structure):
     _fields_ = [("n_ant", ctypes.c_int32), ("n_feed", ctypes.c_int32), ("n_ax", ctypes.c_int32),
                 ("n_beam", ctypes.c_int32), ("n_za", ctypes.c_int32), ("n_az", ctypes.c_int32),
                 ("dza", ctypes.c_double), ("daz", ctypes.c_double), ("latitude", ctypes.c_double),
+                ("interp", ctypes.c_int32)]
+
+
+class GeomLD(ctypes.Structure):
+    _fields_ = [("n_ant", ctypes.c_int32), ("n_feed", ctypes.c_int32), ("n_ax", ctypes.c_int32),
+                ("n_beam", ctypes.c_int32), ("n_za", ctypes.c_int32), ("n_az", ctypes.c_int32),
+                ("dza", ctypes.c_longdouble), ("daz", ctypes.c_longdouble), ("latitude", ctypes.c_longdouble),
                 ("interp", ctypes.c_int32)]
 
 
@@ -300,4 +331,32 @@ def gram(Z) -> np.ndarray:
     Z = _c128(Z)
     V = np.empty((Z.shape[0], Z.shape[0]), dtype=np.complex128)
     lib().orc_gram(Z.shape[0], Z.shape[1], _ptr(Z), _ptr(V))
+    return V
+
+
+def simulate_longdouble(antpos, freqs, lsts, ra, dec, flux, beam_grid, latitude: float, dza: float, daz: float,
+                        interp_mode: str, instances: Optional[Sequence] = None) -> np.ndarray:
+    """The direct sum of ``simulate`` (Stokes I, one beam or beam_idx = None) in long
+    double arithmetic: the same C source built with ORC_REAL = long double.  The
+    inputs are the double values, widened exactly; the result is V[inst][a][b][p][q]
+    as numpy clongdouble.  Used only to bound the double build's own error."""
+    ld, cld = np.longdouble, np.clongdouble
+    if np.finfo(ld).nmant <= np.finfo(np.float64).nmant:
+        raise RuntimeError("long double is not wider than double on this platform")
+    conv = lambda x: np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(ld))
+    antpos, freqs, lsts, ra, dec, flux = map(conv, (antpos, freqs, lsts, ra, dec, flux))
+    beam_grid = np.ascontiguousarray(np.asarray(beam_grid, dtype=np.complex128).astype(cld))
+    nb, nfreq, nf, nx, nza, naz = beam_grid.shape
+    na = antpos.shape[0]
+    if instances is None:
+        instances = [(t, f) for t in range(lsts.size) for f in range(freqs.size)]
+    it = _i32([i[0] for i in instances])
+    iff = _i32([i[1] for i in instances])
+    G = GeomLD(na, nf, nx, nb, nza, naz, dza, daz, latitude, 0 if interp_mode == "bilinear" else 1)
+    V = np.zeros((len(instances), na, na, nf, nf), dtype=cld)
+    rc = lib_ld().orc_simulate(ctypes.byref(G), _ptr(antpos), None, _ptr(freqs), freqs.size, _ptr(lsts), ra.size,
+                               _ptr(ra), _ptr(dec), _ptr(flux), _ptr(beam_grid), len(instances), _ptr(it),
+                               _ptr(iff), _ptr(V))
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
     return V

@@ -38,18 +38,27 @@
  *     az, with Keys' ghost rows g[-1] = 3 g[0] - 3 g[1] + g[2] and
  *     g[n] = 3 g[n-1] - 3 g[n-2] + g[n-3] at the two za ends.
  */
-#include <complex.h>
-#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <tgmath.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
 
-#define SPEED_OF_LIGHT 299792458.0
+/* The arithmetic type.  The reference is built in double precision; a second
+ * build with -DORC_REAL="long double" (x86 80-bit extended) runs the same
+ * source in wider arithmetic, only to bound the double build's own rounding
+ * on small cases.  Every array argument then has that type too. */
+#ifndef ORC_REAL
+#define ORC_REAL double
+#endif
+typedef ORC_REAL real;
+typedef ORC_REAL _Complex cplx;
 
-typedef double _Complex cplx;
+#define SPEED_OF_LIGHT 299792458.0
+/* pi to beyond long-double precision; in the double build this rounds to M_PI */
+#define PI ((real)3.14159265358979323846264338327950288L)
 
 int orc_version(void) { return 1; }
 
@@ -70,7 +79,7 @@ int orc_get_threads(void) {
 }
 
 /* Eq. (xeq): X_eq = (cos a cos d, sin a cos d, sin d).  out is [n][3]. */
-void orc_xeq(int64_t n, const double *ra, const double *dec, double *out) {
+void orc_xeq(int64_t n, const real *ra, const real *dec, real *out) {
     for (int64_t i = 0; i < n; i++) {
         out[3 * i + 0] = cos(ra[i]) * cos(dec[i]);
         out[3 * i + 1] = sin(ra[i]) * cos(dec[i]);
@@ -79,9 +88,9 @@ void orc_xeq(int64_t n, const double *ra, const double *dec, double *out) {
 }
 
 /* Eq. (rotation) with H = -lst and l = latitude; R is row-major [3][3]. */
-void orc_rotation(double lst, double latitude, double *R) {
-    double H = -lst;
-    double l = latitude;
+void orc_rotation(real lst, real latitude, real *R) {
+    real H = -lst;
+    real l = latitude;
     R[0] = sin(H);
     R[1] = cos(H);
     R[2] = 0.0;
@@ -94,10 +103,10 @@ void orc_rotation(double lst, double latitude, double *R) {
 }
 
 /* X_hrz = R X_eq for every source (Sec. 3.3).  xeq, xhrz are [n][3]. */
-void orc_topocentric(const double *R, int64_t n, const double *xeq, double *xhrz) {
+void orc_topocentric(const real *R, int64_t n, const real *xeq, real *xhrz) {
     for (int64_t i = 0; i < n; i++) {
         for (int r = 0; r < 3; r++) {
-            double s = 0.0;
+            real s = 0.0;
             for (int c = 0; c < 3; c++) s += R[3 * r + c] * xeq[3 * i + c];
             xhrz[3 * i + r] = s;
         }
@@ -105,7 +114,7 @@ void orc_topocentric(const double *R, int64_t n, const double *xeq, double *xhrz
 }
 
 /* Horizon cut of Alg. 2 step (i): ascending indices of sources with U > 0. */
-int64_t orc_visible(int64_t n, const double *xhrz, int32_t *idx) {
+int64_t orc_visible(int64_t n, const real *xhrz, int32_t *idx) {
     int64_t m = 0;
     for (int64_t i = 0; i < n; i++)
         if (xhrz[3 * i + 2] > 0.0) idx[m++] = (int32_t)i;
@@ -113,13 +122,13 @@ int64_t orc_visible(int64_t n, const double *xhrz, int32_t *idx) {
 }
 
 /* Zenith angle and azimuth (North through East) of topocentric unit vectors. */
-void orc_azza(int64_t n, const double *xhrz, double *az, double *za) {
+void orc_azza(int64_t n, const real *xhrz, real *az, real *za) {
     for (int64_t i = 0; i < n; i++) {
-        double e = xhrz[3 * i + 0], nn = xhrz[3 * i + 1], u = xhrz[3 * i + 2];
+        real e = xhrz[3 * i + 0], nn = xhrz[3 * i + 1], u = xhrz[3 * i + 2];
         za[i] = atan2(hypot(e, nn), u);
-        double a = atan2(e, nn);
-        if (a < 0.0) a += 2.0 * M_PI;
-        if (a >= 2.0 * M_PI) a -= 2.0 * M_PI;
+        real a = atan2(e, nn);
+        if (a < 0.0) a += 2.0 * PI;
+        if (a >= 2.0 * PI) a -= 2.0 * PI;
         az[i] = a;
     }
 }
@@ -137,15 +146,15 @@ static int wrap(int k, int n) {
 static cplx node(const cplx *g, int n_az, int j, int k) { return g[(int64_t)j * n_az + wrap(k, n_az)]; }
 
 /* Bilinear interpolation of one complex grid plane g[n_za][n_az]. */
-cplx orc_bilinear_one(const cplx *g, int n_za, int n_az, double dza, double daz, double za, double az) {
-    double u = za / dza;
-    double v = az / daz;
+cplx orc_bilinear_one(const cplx *g, int n_za, int n_az, real dza, real daz, real za, real az) {
+    real u = za / dza;
+    real v = az / daz;
     int j0 = (int)floor(u);
     if (j0 < 0) j0 = 0;
     if (j0 > n_za - 2) j0 = n_za - 2;
-    double t = u - j0;
-    double kf = floor(v);
-    double s = v - kf;
+    real t = u - j0;
+    real kf = floor(v);
+    real s = v - kf;
     int k0 = (int)kf;
     cplx a00 = node(g, n_az, j0, k0), a01 = node(g, n_az, j0, k0 + 1);
     cplx a10 = node(g, n_az, j0 + 1, k0), a11 = node(g, n_az, j0 + 1, k0 + 1);
@@ -153,8 +162,8 @@ cplx orc_bilinear_one(const cplx *g, int n_za, int n_az, double dza, double daz,
 }
 
 /* Keys (1981) cubic-convolution kernel with a = -1/2. */
-static double keys_w(double x) {
-    const double a = -0.5;
+static real keys_w(real x) {
+    const real a = -0.5;
     x = fabs(x);
     if (x <= 1.0) return (a + 2.0) * x * x * x - (a + 3.0) * x * x + 1.0;
     if (x < 2.0) return a * x * x * x - 5.0 * a * x * x + 8.0 * a * x - 4.0 * a;
@@ -170,21 +179,21 @@ static cplx row_value(const cplx *g, int n_za, int n_az, int j, int k) {
 }
 
 /* Bicubic (Keys) interpolation of one complex grid plane g[n_za][n_az]. */
-cplx orc_bicubic_one(const cplx *g, int n_za, int n_az, double dza, double daz, double za, double az) {
-    double u = za / dza;
-    double v = az / daz;
+cplx orc_bicubic_one(const cplx *g, int n_za, int n_az, real dza, real daz, real za, real az) {
+    real u = za / dza;
+    real v = az / daz;
     int j0 = (int)floor(u);
     if (j0 < 0) j0 = 0;
     if (j0 > n_za - 2) j0 = n_za - 2;
-    double t = u - j0;
-    double kf = floor(v);
-    double s = v - kf;
+    real t = u - j0;
+    real kf = floor(v);
+    real s = v - kf;
     int k0 = (int)kf;
     cplx acc = 0.0;
     for (int dj = -1; dj <= 2; dj++) {
-        double wj = keys_w(t - dj);
+        real wj = keys_w(t - dj);
         for (int dk = -1; dk <= 2; dk++) {
-            double wk = keys_w(s - dk);
+            real wk = keys_w(s - dk);
             acc += wj * wk * row_value(g, n_za, n_az, j0 + dj, k0 + dk);
         }
     }
@@ -192,8 +201,8 @@ cplx orc_bicubic_one(const cplx *g, int n_za, int n_az, double dza, double daz, 
 }
 
 /* Interpolate many points (Python-facing helper): mode 0 bilinear, 1 bicubic. */
-void orc_interp(int mode, const cplx *g, int n_za, int n_az, double dza, double daz, int64_t n,
-                const double *za, const double *az, cplx *out) {
+void orc_interp(int mode, const cplx *g, int n_za, int n_az, real dza, real daz, int64_t n,
+                const real *za, const real *az, cplx *out) {
     for (int64_t i = 0; i < n; i++)
         out[i] = mode == 0 ? orc_bilinear_one(g, n_za, n_az, dza, daz, za[i], az[i])
                            : orc_bicubic_one(g, n_za, n_az, dza, daz, za[i], az[i]);
@@ -206,30 +215,30 @@ void orc_interp(int mode, const cplx *g, int n_za, int n_az, double dza, double 
 typedef struct {
     int32_t n_ant, n_feed, n_ax, n_beam;
     int32_t n_za, n_az;
-    double dza, daz;
-    double latitude;
+    real dza, daz;
+    real latitude;
     int32_t interp; /* 0 bilinear, 1 bicubic */
 } orc_geom;
 
 /* Visible set and beam values for one (t, nu).
  * beam_f: grid slice of channel f: [n_beam][n_feed][n_ax][n_za][n_az].
  * Outputs: idx[m], xhrz_vis[m][3], A[n_beam][n_feed][n_ax][m] (row stride n_src). */
-static int64_t instance_sky(const orc_geom *G, double lst, int64_t n_src, const double *xeq, const cplx *beam_f,
-                            int32_t *idx, double *xhrz_all, double *xhrz_vis, cplx *A) {
-    double R[9];
+static int64_t instance_sky(const orc_geom *G, real lst, int64_t n_src, const real *xeq, const cplx *beam_f,
+                            int32_t *idx, real *xhrz_all, real *xhrz_vis, cplx *A) {
+    real R[9];
     orc_rotation(lst, G->latitude, R);
     orc_topocentric(R, n_src, xeq, xhrz_all);
     int64_t m = orc_visible(n_src, xhrz_all, idx);
     int64_t plane = (int64_t)G->n_za * G->n_az;
     for (int64_t i = 0; i < m; i++) {
-        const double *s = xhrz_all + 3 * (int64_t)idx[i];
+        const real *s = xhrz_all + 3 * (int64_t)idx[i];
         xhrz_vis[3 * i + 0] = s[0];
         xhrz_vis[3 * i + 1] = s[1];
         xhrz_vis[3 * i + 2] = s[2];
     }
     if (A) {
         for (int64_t i = 0; i < m; i++) {
-            double az, za;
+            real az, za;
             orc_azza(1, xhrz_vis + 3 * i, &az, &za);
             for (int b = 0; b < G->n_beam; b++)
                 for (int p = 0; p < G->n_feed; p++)
@@ -249,24 +258,24 @@ static int64_t instance_sky(const orc_geom *G, double lst, int64_t n_src, const 
  *                    * exp(-2 pi i nu (x_a - x_b) . s_n / c)
  * summed in ascending n, every (a, b) evaluated independently.
  * A is [n_beam][n_feed][n_ax][lda] over the m visible sources; flux_vis[m]. */
-static void direct_sum(const orc_geom *G, const double *antpos, const int32_t *beam_idx, double freq, int64_t m,
-                       const double *xhrz_vis, const double *flux_vis, const cplx *A, int64_t lda, cplx *V) {
+static void direct_sum(const orc_geom *G, const real *antpos, const int32_t *beam_idx, real freq, int64_t m,
+                       const real *xhrz_vis, const real *flux_vis, const cplx *A, int64_t lda, cplx *V) {
     const int na = G->n_ant, nf = G->n_feed, nx = G->n_ax;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int a = 0; a < na; a++) {
         for (int b = 0; b < na; b++) {
-            double bx = antpos[3 * a + 0] - antpos[3 * b + 0];
-            double by = antpos[3 * a + 1] - antpos[3 * b + 1];
-            double bz = antpos[3 * a + 2] - antpos[3 * b + 2];
+            real bx = antpos[3 * a + 0] - antpos[3 * b + 0];
+            real by = antpos[3 * a + 1] - antpos[3 * b + 1];
+            real bz = antpos[3 * a + 2] - antpos[3 * b + 2];
             int ia = beam_idx ? beam_idx[a] : 0;
             int ib = beam_idx ? beam_idx[b] : 0;
             for (int p = 0; p < nf; p++)
                 for (int q = 0; q < nf; q++) {
                     cplx acc = 0.0;
                     for (int64_t n = 0; n < m; n++) {
-                        const double *s = xhrz_vis + 3 * n;
-                        double tau = (bx * s[0] + by * s[1] + bz * s[2]) / SPEED_OF_LIGHT;
-                        double ph = -2.0 * M_PI * freq * tau;
+                        const real *s = xhrz_vis + 3 * n;
+                        real tau = (bx * s[0] + by * s[1] + bz * s[2]) / SPEED_OF_LIGHT;
+                        real ph = -2.0 * PI * freq * tau;
                         cplx fringe = cos(ph) + I * sin(ph);
                         cplx beams = 0.0;
                         for (int k = 0; k < nx; k++) {
@@ -288,14 +297,14 @@ static void direct_sum(const orc_geom *G, const double *antpos, const int32_t *b
  *   beam_grid [n_beam][n_freq][n_feed][n_ax][n_za][n_az] complex128,
  *   inst_t/inst_f [n_inst], V out [n_inst][n_ant][n_ant][n_feed][n_feed] complex128.
  * Returns 0, or -1 on allocation failure. */
-int orc_simulate(const orc_geom *G, const double *antpos, const int32_t *beam_idx, const double *freqs,
-                 int32_t n_freq, const double *lsts, int64_t n_src, const double *ra, const double *dec,
-                 const double *flux, const cplx *beam_grid, int32_t n_inst, const int32_t *inst_t,
+int orc_simulate(const orc_geom *G, const real *antpos, const int32_t *beam_idx, const real *freqs,
+                 int32_t n_freq, const real *lsts, int64_t n_src, const real *ra, const real *dec,
+                 const real *flux, const cplx *beam_grid, int32_t n_inst, const int32_t *inst_t,
                  const int32_t *inst_f, cplx *V) {
-    double *xeq = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
-    double *xall = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
-    double *xvis = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
-    double *fvis = malloc(sizeof(double) * (n_src ? n_src : 1));
+    real *xeq = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
+    real *xall = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
+    real *xvis = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
+    real *fvis = malloc(sizeof(real) * (n_src ? n_src : 1));
     int32_t *idx = malloc(sizeof(int32_t) * (n_src ? n_src : 1));
     int64_t plane = (int64_t)G->n_za * G->n_az;
     int64_t per_freq = (int64_t)G->n_feed * G->n_ax * plane;
@@ -322,15 +331,15 @@ int orc_simulate(const orc_geom *G, const double *antpos, const int32_t *beam_id
 /* The direct sum of Eq. (matvisrime) for a chosen list of antenna pairs only
  * (pair_a[j], pair_b[j]), j < n_pair: V[inst][j][p][q].  Same arithmetic as
  * orc_simulate, for checking single entries of large problems. */
-int orc_simulate_pairs(const orc_geom *G, const double *antpos, const int32_t *beam_idx, const double *freqs,
-                       int32_t n_freq, const double *lsts, int64_t n_src, const double *ra, const double *dec,
-                       const double *flux, const cplx *beam_grid, int32_t n_inst, const int32_t *inst_t,
+int orc_simulate_pairs(const orc_geom *G, const real *antpos, const int32_t *beam_idx, const real *freqs,
+                       int32_t n_freq, const real *lsts, int64_t n_src, const real *ra, const real *dec,
+                       const real *flux, const cplx *beam_grid, int32_t n_inst, const int32_t *inst_t,
                        const int32_t *inst_f, int32_t n_pair, const int32_t *pair_a, const int32_t *pair_b,
                        cplx *V) {
-    double *xeq = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
-    double *xall = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
-    double *xvis = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
-    double *fvis = malloc(sizeof(double) * (n_src ? n_src : 1));
+    real *xeq = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
+    real *xall = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
+    real *xvis = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
+    real *fvis = malloc(sizeof(real) * (n_src ? n_src : 1));
     int32_t *idx = malloc(sizeof(int32_t) * (n_src ? n_src : 1));
     int64_t plane = (int64_t)G->n_za * G->n_az;
     int64_t per_freq = (int64_t)G->n_feed * G->n_ax * plane;
@@ -348,22 +357,22 @@ int orc_simulate_pairs(const orc_geom *G, const double *antpos, const int32_t *b
             memcpy(slice + b * per_freq, beam_grid + ((int64_t)b * n_freq + f) * per_freq, sizeof(cplx) * per_freq);
         int64_t m = instance_sky(G, lsts[t], n_src, xeq, slice, idx, xall, xvis, A);
         for (int64_t n = 0; n < m; n++) fvis[n] = flux[(int64_t)f * n_src + idx[n]];
-        double freq = freqs[f];
+        real freq = freqs[f];
 #pragma omp parallel for schedule(dynamic, 1)
         for (int32_t j = 0; j < n_pair; j++) {
             int a = pair_a[j], b = pair_b[j];
-            double bx = antpos[3 * a + 0] - antpos[3 * b + 0];
-            double by = antpos[3 * a + 1] - antpos[3 * b + 1];
-            double bz = antpos[3 * a + 2] - antpos[3 * b + 2];
+            real bx = antpos[3 * a + 0] - antpos[3 * b + 0];
+            real by = antpos[3 * a + 1] - antpos[3 * b + 1];
+            real bz = antpos[3 * a + 2] - antpos[3 * b + 2];
             int ia = beam_idx ? beam_idx[a] : 0;
             int ib = beam_idx ? beam_idx[b] : 0;
             for (int p = 0; p < nf; p++)
                 for (int q = 0; q < nf; q++) {
                     cplx acc = 0.0;
                     for (int64_t n = 0; n < m; n++) {
-                        const double *s = xvis + 3 * n;
-                        double tau = (bx * s[0] + by * s[1] + bz * s[2]) / SPEED_OF_LIGHT;
-                        double ph = -2.0 * M_PI * freq * tau;
+                        const real *s = xvis + 3 * n;
+                        real tau = (bx * s[0] + by * s[1] + bz * s[2]) / SPEED_OF_LIGHT;
+                        real ph = -2.0 * PI * freq * tau;
                         cplx fringe = cos(ph) + I * sin(ph);
                         cplx beams = 0.0;
                         for (int k = 0; k < nx; k++)
@@ -382,13 +391,13 @@ int orc_simulate_pairs(const orc_geom *G, const double *antpos, const int32_t *b
 /* Same direct sum, with the beam supplied by the caller for every source
  * (A_all [n_beam][n_feed][n_ax][n_src] at this instance), e.g. an analytic
  * beam evaluated exactly.  One instance; returns the visible count. */
-int64_t orc_simulate_given_beam(const orc_geom *G, const double *antpos, const int32_t *beam_idx, double freq,
-                                double lst, int64_t n_src, const double *ra, const double *dec, const double *flux_f,
+int64_t orc_simulate_given_beam(const orc_geom *G, const real *antpos, const int32_t *beam_idx, real freq,
+                                real lst, int64_t n_src, const real *ra, const real *dec, const real *flux_f,
                                 const cplx *A_all, cplx *V) {
-    double *xeq = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
-    double *xall = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
-    double *xvis = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
-    double *fvis = malloc(sizeof(double) * (n_src ? n_src : 1));
+    real *xeq = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
+    real *xall = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
+    real *xvis = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
+    real *fvis = malloc(sizeof(real) * (n_src ? n_src : 1));
     int32_t *idx = malloc(sizeof(int32_t) * (n_src ? n_src : 1));
     cplx *A = malloc(sizeof(cplx) * (size_t)G->n_beam * G->n_feed * G->n_ax * (n_src ? n_src : 1));
     if (!xeq || !xall || !xvis || !fvis || !idx || !A) {
@@ -415,17 +424,17 @@ int64_t orc_simulate_given_beam(const orc_geom *G, const double *antpos, const i
  * needs n_ax = 2.  n_pair < 0 evaluates every (a, b) into V[inst][a][b][p][q];
  * otherwise the listed pairs into V[inst][j][p][q].  Returns 0, -1 on
  * allocation failure, -2 when n_ax != 2. */
-int orc_simulate_pol(const orc_geom *G, const double *antpos, const int32_t *beam_idx, const double *freqs,
-                     int32_t n_freq, const double *lsts, int64_t n_src, const double *ra, const double *dec,
-                     const double *stokes, const cplx *beam_grid, int32_t n_inst, const int32_t *inst_t,
+int orc_simulate_pol(const orc_geom *G, const real *antpos, const int32_t *beam_idx, const real *freqs,
+                     int32_t n_freq, const real *lsts, int64_t n_src, const real *ra, const real *dec,
+                     const real *stokes, const cplx *beam_grid, int32_t n_inst, const int32_t *inst_t,
                      const int32_t *inst_f, int32_t n_pair, const int32_t *pair_a, const int32_t *pair_b,
                      cplx *V) {
     if (G->n_ax != 2) return -2;
     const int64_t ns1 = n_src ? n_src : 1;
-    double *xeq = malloc(sizeof(double) * 3 * ns1);
-    double *xall = malloc(sizeof(double) * 3 * ns1);
-    double *xvis = malloc(sizeof(double) * 3 * ns1);
-    double *svis = malloc(sizeof(double) * 4 * ns1);
+    real *xeq = malloc(sizeof(real) * 3 * ns1);
+    real *xall = malloc(sizeof(real) * 3 * ns1);
+    real *xvis = malloc(sizeof(real) * 3 * ns1);
+    real *svis = malloc(sizeof(real) * 4 * ns1);
     int32_t *idx = malloc(sizeof(int32_t) * ns1);
     int64_t plane = (int64_t)G->n_za * G->n_az;
     int64_t per_freq = (int64_t)G->n_feed * G->n_ax * plane;
@@ -445,25 +454,25 @@ int orc_simulate_pol(const orc_geom *G, const double *antpos, const int32_t *bea
         int64_t m = instance_sky(G, lsts[t], n_src, xeq, slice, idx, xall, xvis, A);
         for (int st = 0; st < 4; st++)
             for (int64_t n = 0; n < m; n++) svis[st * ns1 + n] = stokes[((int64_t)st * n_freq + f) * n_src + idx[n]];
-        double freq = freqs[f];
+        real freq = freqs[f];
 #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t j = 0; j < npair; j++) {
             int a = n_pair < 0 ? (int)(j / na) : pair_a[j];
             int b = n_pair < 0 ? (int)(j % na) : pair_b[j];
-            double bx = antpos[3 * a + 0] - antpos[3 * b + 0];
-            double by = antpos[3 * a + 1] - antpos[3 * b + 1];
-            double bz = antpos[3 * a + 2] - antpos[3 * b + 2];
+            real bx = antpos[3 * a + 0] - antpos[3 * b + 0];
+            real by = antpos[3 * a + 1] - antpos[3 * b + 1];
+            real bz = antpos[3 * a + 2] - antpos[3 * b + 2];
             int ia = beam_idx ? beam_idx[a] : 0;
             int ib = beam_idx ? beam_idx[b] : 0;
             for (int p = 0; p < nf; p++)
                 for (int q = 0; q < nf; q++) {
                     cplx acc = 0.0;
                     for (int64_t n = 0; n < m; n++) {
-                        const double *s = xvis + 3 * n;
-                        double tau = (bx * s[0] + by * s[1] + bz * s[2]) / SPEED_OF_LIGHT;
-                        double ph = -2.0 * M_PI * freq * tau;
+                        const real *s = xvis + 3 * n;
+                        real tau = (bx * s[0] + by * s[1] + bz * s[2]) / SPEED_OF_LIGHT;
+                        real ph = -2.0 * PI * freq * tau;
                         cplx fringe = cos(ph) + I * sin(ph);
-                        double si = svis[n], sq = svis[ns1 + n], su = svis[2 * ns1 + n], sv = svis[3 * ns1 + n];
+                        real si = svis[n], sq = svis[ns1 + n], su = svis[2 * ns1 + n], sv = svis[3 * ns1 + n];
                         cplx C[2][2];
                         C[0][0] = si + sq;
                         C[0][1] = su + I * sv;
@@ -490,16 +499,16 @@ int orc_simulate_pol(const orc_geom *G, const double *antpos, const int32_t *bea
  *   Z[(a, p)][(n, k)] = sqrt(I_n) A_{beam(a), p, k}(n) exp(-2 pi i nu x_a . s_n / c)
  * over the m visible sources (given their X_hrz, flux and beam values A
  * [n_beam][n_feed][n_ax][lda]).  Z is [n_ant * n_feed][m * n_ax] row-major. */
-void orc_zmatrix(const orc_geom *G, const double *antpos, const int32_t *beam_idx, double freq, int64_t m,
-                 const double *xhrz_vis, const double *flux_vis, const cplx *A, int64_t lda, cplx *Z) {
+void orc_zmatrix(const orc_geom *G, const real *antpos, const int32_t *beam_idx, real freq, int64_t m,
+                 const real *xhrz_vis, const real *flux_vis, const cplx *A, int64_t lda, cplx *Z) {
     const int na = G->n_ant, nf = G->n_feed, nx = G->n_ax;
     int64_t ncol = m * nx;
     for (int a = 0; a < na; a++) {
         int ia = beam_idx ? beam_idx[a] : 0;
         for (int64_t n = 0; n < m; n++) {
-            const double *s = xhrz_vis + 3 * n;
-            double tau = (antpos[3 * a] * s[0] + antpos[3 * a + 1] * s[1] + antpos[3 * a + 2] * s[2]) / SPEED_OF_LIGHT;
-            double ph = -2.0 * M_PI * freq * tau;
+            const real *s = xhrz_vis + 3 * n;
+            real tau = (antpos[3 * a] * s[0] + antpos[3 * a + 1] * s[1] + antpos[3 * a + 2] * s[2]) / SPEED_OF_LIGHT;
+            real ph = -2.0 * PI * freq * tau;
             cplx F = cos(ph) + I * sin(ph);
             for (int p = 0; p < nf; p++)
                 for (int k = 0; k < nx; k++)
@@ -523,10 +532,10 @@ void orc_gram(int64_t nrow, int64_t ncol, const cplx *Z, cplx *V) {
 
 /* Sky of one instance for step tests: visible indices, their X_hrz and the
  * beam at them.  Returns the visible count m. */
-int64_t orc_instance_sky(const orc_geom *G, double lst, int64_t n_src, const double *ra, const double *dec,
-                         const cplx *beam_f, int32_t *idx, double *xhrz_vis, cplx *A) {
-    double *xeq = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
-    double *xall = malloc(sizeof(double) * 3 * (n_src ? n_src : 1));
+int64_t orc_instance_sky(const orc_geom *G, real lst, int64_t n_src, const real *ra, const real *dec,
+                         const cplx *beam_f, int32_t *idx, real *xhrz_vis, cplx *A) {
+    real *xeq = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
+    real *xall = malloc(sizeof(real) * 3 * (n_src ? n_src : 1));
     if (!xeq || !xall) {
         free(xeq); free(xall);
         return -1;

@@ -64,19 +64,12 @@ def sample_pairs(n_ant, n, seed):
 
 
 def sampled_err_cs(V, wl, prec, instances, pairs, grid=None):
-    """max over sampled entries of |V - V_ref| / sqrt(|V_ref aa| |V_ref bb|), and the Frobenius error."""
+    """err_CS and err_F over sampled entries (each the max over the instances): V is the
+    full device result [t][f][a][b][p][q]; the oracle gives the listed pairs only."""
     import oracle
     ref = oracle.simulate_pairs(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, wl.flux, grid_as_used(wl, prec) if grid is None else grid,
                                 wl.latitude, wl.dza, wl.daz, wl.interp, instances=instances, pairs=pairs)
-    idx = {p: i for i, p in enumerate(pairs)}
-    worst, num, den = 0.0, 0.0, 0.0
-    for ii, (t, f) in enumerate(instances):
-        for (a, b), k in idx.items():
-            g = V[t, f, a, b]
-            r = ref[ii, k]
-            ra, rb = ref[ii, idx[(a, a)]], ref[ii, idx[(b, b)]]
-            scale = np.sqrt(np.abs(np.diag(ra))[:, None] * np.abs(np.diag(rb))[None, :])
-            worst = max(worst, float(np.max(np.abs(g - r) / np.maximum(scale, 1e-300))))
-            num += float(np.sum(np.abs(g - r) ** 2))
-            den += float(np.sum(np.abs(r) ** 2))
-    return worst, np.sqrt(num / den)
+    pa = np.array([a for a, _ in pairs])
+    pb = np.array([b for _, b in pairs])
+    Vp = np.stack([V[t, f][pa, pb] for (t, f) in instances])  # [inst][pair][p][q]
+    return float(metrics.err_cs_pairs(Vp, ref, pairs).max()), float(metrics.err_f_pairs(Vp, ref).max())
