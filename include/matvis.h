@@ -230,6 +230,21 @@ matvis_status matvis_mlp_forward(const float *params, const float *x, int64_t n,
 matvis_status matvis_mlp_loss_grad(const float *params, const float *x, const float *y, int64_t n, int32_t fp32_math,
                                    float *grad, float *loss, void *stream);
 
+/* matvis_mlp_loss_grad without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight training loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as
+ * matvis_mlp_loss_grad, but the activation workspace is a fixed array of the
+ * library's (32 MB of device memory, held on every GPU the library runs on
+ * until the process ends), so n is limited to 4096 rows: larger n returns
+ * MATVIS_EINVAL with a message on stderr.  No hipMalloc, hipFree or memset
+ * node is issued.  Asynchronous on `stream` (it does not synchronise).
+ * Every call on one GPU shares that GPU's workspace: calls that overlap in
+ * time on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller.  The first call on each device looks up the
+ * workspace's device address, so make it outside graph capture. */
+matvis_status matvis_mlp_loss_grad_noalloc(const float *params, const float *x, const float *y, int64_t n,
+                                           int32_t fp32_math, float *grad, float *loss, void *stream);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on
  * params with first / second moment vectors m1, m2 of the same length. */
 matvis_status matvis_mlp_adam(float *params, const float *grad, float *m1, float *m2, int64_t step, float lr,

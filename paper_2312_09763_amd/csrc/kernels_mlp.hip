@@ -227,6 +227,12 @@ __global__ void k_gather_rows(const float *__restrict__ src, int width, const in
     dst[i] = src[(int64_t)perm[r] * width + c];
 }
 
+// out[i] = v (a kernel rather than a memset node, so the sequence may be captured into a graph)
+__global__ void k_fill(float *__restrict__ out, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = v;
+}
+
 __global__ void k_to_bf16(const float *__restrict__ in, __bf16 *__restrict__ out, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (__bf16)in[i];
@@ -629,6 +635,12 @@ hipError_t adam(float *p, const float *g, float *m1, float *m2, int64_t n, int64
 hipError_t gather_rows(const float *src, int width, const int32_t *perm, int64_t n, float *dst, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     k_gather_rows<<<(unsigned)((n * width + 255) / 256), 256, 0, s>>>(src, width, perm, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t fill(float *out, int64_t n, float v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(out, n, v);
     return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ hipError_t loss_grad(const float *out, const float *y, int64_t n, float *dout, f
 // db[c] = sum_m dZ[m][c] (fixed summation order) through the workspace ws
 hipError_t colsum(const float *dZ, int64_t M, int N, float *db, float *ws, int64_t ws_elems, hipStream_t s);
 hipError_t adam(float *p, const float *g, float *m1, float *m2, int64_t n, int64_t step, float lr, hipStream_t s);
+hipError_t fill(float *out, int64_t n, float v, hipStream_t s);
 hipError_t to_bf16(const float *in, __bf16 *out, int64_t n, hipStream_t s);
 // bf16 W1..W4 (kWbElems values, 160 KB) in the inference kernel's LDS image:
 // 1 KB MFMA A-operand blocks per (layer, 16-row tile, 32-deep k block), the

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <numeric>
 #include <random>
 #include <vector>
@@ -27,16 +28,48 @@ namespace {
         }                                              \
     } while (0)
 
-// Activation workspace for n rows.
+// Activation workspace for n rows: buffer sizes in floats, in the order the
+// workspace holds them.  alloc() gives each its own device allocation; bind()
+// carves them, 256-byte aligned, out of one caller-provided block of
+// Work::floats_for(rows) floats.
 struct Work {
     int64_t n = 0;
     float *phi = nullptr, *Z[4] = {}, *H[4] = {}, *out = nullptr, *dout = nullptr, *dH = nullptr, *dZ = nullptr,
           *part = nullptr, *ws = nullptr;
     int64_t ws_elems = 0;  // split-k partial products and column-sum partials
     std::vector<void *> allocs;
+    static int64_t ws_for(int64_t rows) { return std::max<int64_t>(384 * 4096, (rows + 255) / 256 * kHid); }
+    // the (pointer, size) list in workspace order
+    template <typename F>
+    static hipError_t each(int64_t rows, float **phi, float **Z, float **H, float **out, float **dout, float **dH,
+                           float **dZ, float **part, float **ws, F &&one) {
+        hipError_t e = one(phi, rows * kFeat);
+        for (int l = 0; l < 4 && e == hipSuccess; l++) e = one(&Z[l], rows * kHid);
+        for (int l = 0; l < 4 && e == hipSuccess; l++) e = one(&H[l], rows * kHid);
+        if (e == hipSuccess) e = one(out, rows * kOut);
+        if (e == hipSuccess) e = one(dout, rows * kOut);
+        if (e == hipSuccess) e = one(dH, rows * kHid);
+        if (e == hipSuccess) e = one(dZ, rows * kHid);
+        if (e == hipSuccess) e = one(part, (rows * kOut + 255) / 256 + 1);
+        if (e == hipSuccess) e = one(ws, ws_for(rows));
+        return e;
+    }
+    static constexpr int64_t kAlign = 64;  // floats (256 bytes)
+    static int64_t round_a(int64_t c) { return (std::max<int64_t>(c, 1) + kAlign - 1) / kAlign * kAlign; }
+    static int64_t floats_for(int64_t rows) {
+        int64_t total = 0;
+        float *dummy[16] = {};
+        each(rows, &dummy[0], &dummy[1], &dummy[5], &dummy[9], &dummy[10], &dummy[11], &dummy[12], &dummy[13],
+             &dummy[14], [&](float **, int64_t count) {
+                 total += round_a(count);
+                 return hipSuccess;
+             });
+        return total;
+    }
     hipError_t alloc(int64_t rows) {
         n = rows;
-        auto one = [&](float **p, int64_t count) -> hipError_t {
+        ws_elems = ws_for(rows);
+        return each(rows, &phi, Z, H, &out, &dout, &dH, &dZ, &part, &ws, [&](float **p, int64_t count) {
             void *q = nullptr;
             hipError_t e = hipMalloc(&q, sizeof(float) * std::max<int64_t>(count, 1));
             if (e == hipSuccess) {
@@ -44,18 +77,18 @@ struct Work {
                 *p = (float *)q;
             }
             return e;
-        };
-        hipError_t e = one(&phi, rows * kFeat);
-        for (int l = 0; l < 4 && e == hipSuccess; l++) e = one(&Z[l], rows * kHid);
-        for (int l = 0; l < 4 && e == hipSuccess; l++) e = one(&H[l], rows * kHid);
-        if (e == hipSuccess) e = one(&out, rows * kOut);
-        if (e == hipSuccess) e = one(&dout, rows * kOut);
-        if (e == hipSuccess) e = one(&dH, rows * kHid);
-        if (e == hipSuccess) e = one(&dZ, rows * kHid);
-        if (e == hipSuccess) e = one(&part, (rows * kOut + 255) / 256 + 1);
-        ws_elems = std::max<int64_t>(384 * 4096, (rows + 255) / 256 * kHid);
-        if (e == hipSuccess) e = one(&ws, ws_elems);
-        return e;
+        });
+    }
+    // no allocation: the buffers are consecutive pieces of base[0 .. floats_for(rows))
+    void bind(float *base, int64_t rows) {
+        n = rows;
+        ws_elems = ws_for(rows);
+        int64_t off = 0;
+        each(rows, &phi, Z, H, &out, &dout, &dH, &dZ, &part, &ws, [&](float **p, int64_t count) {
+            *p = base + off;
+            off += round_a(count);
+            return hipSuccess;
+        });
     }
     ~Work() {
         for (void *p : allocs) (void)hipFree(p);
@@ -81,7 +114,7 @@ hipError_t loss_grad_impl(const float *P, const float *x, const float *y, bool b
     RET(mlp::gemm(false, w.H[3], kHid, 1, P + kOffW5, kHid, 1, ni, kOut, kHid, P + kOffB5, w.out, nullptr, 0,
                   w.ws, w.ws_elems, s));
     RET(mlp::loss_grad(w.out, y, n, w.dout, w.part, loss, s));
-    RET(hipMemsetAsync(grad, 0, sizeof(float) * kOffW1, s));  // the Fourier matrix is not trained
+    RET(mlp::fill(grad, kOffW1, 0.f, s));  // the Fourier matrix is not trained
     // output layer
     RET(mlp::gemm(false, w.dout, 1, kOut, w.H[3], 1, kHid, kOut, kHid, ni, nullptr, grad + kOffW5, nullptr, 0,
                   w.ws, w.ws_elems, s));
@@ -108,6 +141,36 @@ hipError_t loss_grad_impl(const float *P, const float *x, const float *y, bool b
 
 }  // namespace
 
+// ---- The allocation-free loss / gradient (matvis_mlp_loss_grad_noalloc) ----
+// Its workspace is one file-scope device array of kNoAllocRows rows' worth of
+// activations (31.7 MB), which every GPU the library runs on holds until the
+// process ends.  Host code never uses the array's name as an address: its
+// device address is looked up once per device (hipGetSymbolAddress, with that
+// device current) and kept in noalloc_ptr.
+static constexpr int64_t kNoAllocRows = 4096;
+static constexpr int64_t kNoAllocFloats = 7930048;  // Work::floats_for(kNoAllocRows), checked below
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex noalloc_mu;
+static float *noalloc_ptr[kMaxDevices] = {};
+
+static hipError_t noalloc_scratch(float **p) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void *q = nullptr;
+        e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        noalloc_ptr[dev] = (float *)q;
+    }
+    *p = noalloc_ptr[dev];
+    return hipSuccess;
+}
+
 extern "C" {
 
 matvis_status matvis_mlp_forward(const float *params, const float *x, int64_t n, float *out, void *stream) {
@@ -133,6 +196,29 @@ matvis_status matvis_mlp_loss_grad(const float *params, const float *x, const fl
     CK(w.alloc(n));
     CK(loss_grad_impl(params, x, y, !fp32_math, grad, loss, w, s));
     CK(hipStreamSynchronize(s));
+    return MATVIS_OK;
+}
+
+matvis_status matvis_mlp_loss_grad_noalloc(const float *params, const float *x, const float *y, int64_t n,
+                                           int32_t fp32_math, float *grad, float *loss, void *stream) {
+    if (!params || !x || !y || !grad || !loss || n <= 0) return MATVIS_EINVAL;
+    if (n > kNoAllocRows) {
+        fprintf(stderr,
+                "matvis_mlp_loss_grad_noalloc: n = %lld rows exceeds the static workspace of %lld rows "
+                "(use matvis_mlp_loss_grad)\n",
+                (long long)n, (long long)kNoAllocRows);
+        return MATVIS_EINVAL;
+    }
+    if (Work::floats_for(kNoAllocRows) != kNoAllocFloats) {  // layout and array size out of step
+        fprintf(stderr, "matvis_mlp_loss_grad_noalloc: workspace layout needs %lld floats, array holds %lld\n",
+                (long long)Work::floats_for(kNoAllocRows), (long long)kNoAllocFloats);
+        return MATVIS_EUNSUPPORTED;
+    }
+    float *base = nullptr;
+    CK(noalloc_scratch(&base));
+    Work w;
+    w.bind(base, n);
+    CK(loss_grad_impl(params, x, y, !fp32_math, grad, loss, w, (hipStream_t)stream));
     return MATVIS_OK;
 }
 

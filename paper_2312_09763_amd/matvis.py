@@ -93,6 +93,8 @@ def load_library():
     L.matvis_mlp_forward.restype = ctypes.c_int
     L.matvis_mlp_loss_grad.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P]
     L.matvis_mlp_loss_grad.restype = ctypes.c_int
+    L.matvis_mlp_loss_grad_noalloc.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P]
+    L.matvis_mlp_loss_grad_noalloc.restype = ctypes.c_int
     L.matvis_mlp_adam.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float, _P]
     L.matvis_mlp_adam.restype = ctypes.c_int
     L.matvis_beam_samples.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -436,6 +438,22 @@ def mlp_loss_grad(params, x, y, fp32_math: bool = False, stream=None):
                                                    _ptr(grad), _ptr(loss), _stream_handle(stream)),
                "matvis_mlp_loss_grad")
     return grad, loss
+
+
+def mlp_loss_grad_noalloc(params, x, y, grad, loss, fp32_math: bool = False, stream=None):
+    """matvis_mlp_loss_grad_noalloc: the same loss and gradient written into the caller's
+    grad [MLP_N_PARAMS] and loss [1], with no device allocation (n <= 4096 rows;
+    asynchronous on the stream)."""
+    import torch
+    n = x.shape[0]
+    _need(params, torch.float32, (MLP_N_PARAMS,), "params")
+    _need(x, torch.float32, (n, 3), "x")
+    _need(y, torch.float32, (n, 8), "y")
+    _need(grad, torch.float32, (MLP_N_PARAMS,), "grad")
+    _need(loss, torch.float32, (1,), "loss")
+    _check_lib(load_library().matvis_mlp_loss_grad_noalloc(_ptr(params), _ptr(x), _ptr(y), n, 1 if fp32_math else 0,
+                                                           _ptr(grad), _ptr(loss), _stream_handle(stream)),
+               "matvis_mlp_loss_grad_noalloc")
 
 
 def mlp_adam(params, grad, m1, m2, step: int, lr: float, stream=None):
