@@ -91,6 +91,19 @@ typedef struct {
                              is stored (a multiple of 64); 0 = automatic.  FP32
                              accumulators see ksplit / 2 sequential updates, so this
                              bounds their rounding; the partials are summed in FP64. */
+    int32_t tile;         /* product kernel variant, 0 = the library's choice.  Bits 0-3:
+                             Z rows per 16-source stage formed by the multiply-first
+                             waves, in units of 32 antennas (2, 3 or 4; 3 by default),
+                             on the paths that split forming between two wave kinds
+                             (MATVIS_PATH_SOURCES diagonal blocks: 2 or 3;
+                             MATVIS_PATH_FUSED_BLOCKS: 2, 3 or 4).  Bit 4: the kernel
+                             of the off-diagonal antenna-block pairs on
+                             MATVIS_PATH_SOURCES with BF16X3: 0 puts each source's
+                             coherency weight on the rows only (the plain fringe rows
+                             of the other block as columns), 1 splits it as square
+                             roots over both sides (FP32 always uses the latter).
+                             Bits 0-3 only reschedule work; bit 4 changes the
+                             rounding (not the tolerance). */
 } matvis_config;
 
 #define MATVIS_FLAG_NO_GRAPH 1 /* launch kernels directly instead of replaying a captured hipGraph */
@@ -283,25 +296,34 @@ matvis_status matvis_train_surrogate(float *params, const float *x, const float 
 matvis_status matvis_set_surrogate(matvis_ctx *ctx, const float *params, double nu_min_hz, double nu_max_hz);
 
 /* ---------------------------------------------------------------------------
- * Autotuner for the batched product (work-item k-split, times per batch, Z
- * formed inside the product or not).  It times matvis_simulate on the
- * caller's own inputs for each candidate that fits in device memory and
- * returns in *best a copy of *base with the fastest ksplit, batch_time and
- * MATVIS_FLAG_UNFUSED choice, and the time of one call in *best_ms (host
- * pointers).  The candidates include 0 for ksplit and batch_time (the
- * library's own choice for the precision and product path), so the result is
- * never slower than the defaults; the other candidate k-splits are at most
- * the fused paths' defaults (FP32 <= 2048, BF16X3 <= 8192 columns), so FP32
- * accumulation stays as accurate as with the defaults or more.  If cache_path is not NULL, results are read from
- * and written to that JSON file, keyed by GPU architecture, rows, axes,
- * sources, times, channels, precision and beam mode; a cached entry is
- * returned without timing.  vis is overwritten.  Synchronous.
+ * Autotuner for the batched product (the grouped persistent launch of many
+ * (t, nu) instances).  It times matvis_simulate on the caller's own inputs and
+ * returns in *best a copy of *base with the fastest product kernel variant
+ * (tile), ksplit, src_chunk, batch_time and MATVIS_FLAG_UNFUSED choice, and
+ * the time of one call in *best_ms (host pointers).  The search is coordinate
+ * descent from the library's defaults over, in order: the block-pair kernel
+ * (tile bit 4), the forming split (tile bits 0-3), ksplit (the path's default, half and a
+ * quarter of it: never more than the default, so FP32 accumulation is as
+ * accurate as with the default or more), src_chunk (default, 2^18, 2^20
+ * sources), batch_time (default, 1, 2, 4, 8) and fused / unfused Z.  0, the
+ * library's own choice, is a candidate on every axis, so the result is never
+ * slower than the defaults as timed.  Candidates that do not fit in device
+ * memory are skipped.  With beam_mode MATVIS_BEAM_SURROGATE, surrogate_params
+ * ([n_beam][MATVIS_MLP_N_PARAMS], device) and nu_min_hz / nu_max_hz are given
+ * to every candidate context as matvis_set_surrogate would (MATVIS_EINVAL if
+ * surrogate_params is NULL); otherwise they are ignored.  If cache_path is
+ * not NULL, results are read from and written to that JSON file, keyed by
+ * GPU architecture, product path, rows, axes, unique beams, the polarised-sky
+ * flag, the source count as a power-of-two bucket, times, channels,
+ * precision and beam mode; a cached entry is returned without timing.  vis is
+ * overwritten.  Synchronous.
  * ------------------------------------------------------------------------- */
 matvis_status matvis_autotune(const matvis_config *base, const double *antpos, const int32_t *beam_idx,
                               const double *freqs, int32_t n_freq, const double *lsts, int32_t n_time,
                               const double *src_radec, int64_t n_src, const double *src_flux,
                               const void *beam_grid, void *vis, void *stream, const char *cache_path,
-                              matvis_config *best, double *best_ms);
+                              matvis_config *best, double *best_ms, const float *surrogate_params,
+                              double nu_min_hz, double nu_max_hz);
 
 /* ---------------------------------------------------------------------------
  * Per-step timing (the paper times each step of Alg. 2 separately, Sec. 6.1).
@@ -319,7 +341,10 @@ typedef enum {
     MATVIS_STEP_HERK = 3,   /* the Z Z^H product kernel alone */
     MATVIS_STEP_REDUCE = 4, /* k-split reduction + Hermitian fill */
     MATVIS_STEP_OTHER = 5,  /* input preparation and the work-list prefix */
-    MATVIS_N_STEPS = 6
+    MATVIS_STEP_HERK_PAIRS = 6, /* the product's second launch, where it has one: the
+                                   off-diagonal antenna-block pairs (paths SOURCES and
+                                   FUSED); the product's time is HERK + HERK_PAIRS */
+    MATVIS_N_STEPS = 7
 } matvis_step;
 
 matvis_status matvis_profile_enable(matvis_ctx *ctx, int32_t enable);

@@ -214,9 +214,18 @@ struct FusedArgs {
     void *part;
     int32_t *work;           // built by launch_worklist
     int32_t grid;
+    int32_t tile;            // kernel variant (matvis_config.tile): bits 0-3 the forming split
 };
-hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s);
+// which: FUSED_ALL every launch of the path; FUSED_FIRST its first launch only (the
+// diagonal blocks, or the only launch); FUSED_PAIRS its second launch only (the
+// off-diagonal block pairs of paths SOURCES and FUSED; nothing on the others).
+enum { FUSED_ALL = 0, FUSED_FIRST = 1, FUSED_PAIRS = 2 };
+hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s, int which = FUSED_ALL);
+// whether the path of these arguments has a second (block-pair) launch
+bool fused_has_pairs(int prec, const FusedArgs &a);
 int herk_fused_occupancy(int prec);
+// the library's k-split for a precision and product path (matvis_config.ksplit = 0)
+int64_t default_ksplit(int prec, bool over_sources, bool three_blocks);
 // product kernel launch_herk_fused picks (a matvis_product_path value, never Z_IN_HBM)
 int fused_path(int prec, int n_feed, int n_ax, int n_beam, int n_ant, int n_rows_pad);
 

@@ -966,16 +966,16 @@ struct CohSrc {
     float lx, ly;    // C10 / sqrt C00 (all four 0 past the split)
 };
 
-template <int PREC, bool OFF>
+template <int PREC, bool OFF, int SQ_ANT = 96>
 __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
     typedef GeomCoh L;  // 144-byte rows: hi + lo bf16 planes, or one complex64 plane (FP32)
     constexpr int RS = L::RS;
     constexpr int SPS = 16;                 // sources per stage
     constexpr int ROWS = 4 * kST;           // up to four planes of 128 antennas
     constexpr int BUF = ROWS * RS;
-    // Antennas formed by the square waves (the rest by the triangle waves, which
-    // have more products per stage): the split evens out the two waves of a SIMD.
-    constexpr int SQ_ANT = 96;
+    // SQ_ANT: antennas formed by the square waves (the rest by the triangle waves,
+    // which have more products per stage); the split evens out the two waves of a
+    // SIMD, 96 by default, 64 as a tuning variant.
     static_assert(SQ_ANT % 32 == 0 && (kST - SQ_ANT) % 32 == 0, "32 antennas per pass of a wave group");
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
     __shared__ AntEntry tab[2 * kST];
@@ -1319,6 +1319,301 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Off-diagonal block pairs of the product over sources (BF16X3) with the
+// per-source weight on one side.  For antenna blocks I > J each of the four
+// block products is
+//   sum_m w(m) F_a(m) conj(F_b(m)) = ((w F_I) F_J^H)[a, b],  a in I, b in J,
+// with w = C_00, C_11 (kind X: V^00_IJ, V^11_IJ), or w = C_10 and conj C_10
+// (kind Y: V^10_IJ, and V^01_IJ = the Hermitian partner of V^10_JI).  So the
+// columns of both products of an item are the unweighted fringe rows F_J, formed
+// and split once, and only the rows carry the weights.  A stage holds four
+// planes of 128 rows x 16 sources: w0 F_I, w1 F_I, F_J, and F_J rotated,
+// (re, im) -> (-im, re), for the imaginary parts, written at forming time so the
+// multiply loop runs MFMAs on LDS operands with no vector work on them.
+// Against k_herk_coh<PREC, true> (both operands weighted by square roots of the
+// coherency) that is a quarter fewer rows to scale and split per stage and no
+// operand rotation in the multiply loop; on a SIMD the matrix and vector work
+// of its two waves largely take turns rather than overlap, so the vector
+// instructions saved are time saved.
+//
+// Waves s and s + 4 share SIMD s: wave s takes product 0 and row half s >> 1 of
+// the 128 x 128 block, wave s + 4 product 1 and the other row half, both column
+// half s & 1 (16 tiles of 16 x 16 each).  When block I is the last, short block,
+// tile rows past its antennas are neither formed nor multiplied, and every
+// SIMD keeps one wave of each row half, so the saving is shared evenly.
+// ---------------------------------------------------------------------------
+struct PairSrc {
+    double x, y, z;   // s_hat
+    float c00, c11;   // coherency through the beam, C_pq = sum_k B_pk conj(B_qk)
+    float c10x, c10y; // (all four 0 past the split)
+};
+
+// Rows 16 (rb + i), i < NR, of one plane against columns 16 (cb + j) and their
+// rotations 16 (wb + j), j < 4: re += a b, im += a rot(b) for the hi / lo terms.
+template <typename L, int NR>
+__device__ __forceinline__ void consume_pairs_b3(const unsigned char *buf, int rb, int cb, int wb, int l16, int lk,
+                                                 f32x4 (&re)[16], f32x4 (&im)[16]) {
+    u32x4 ah[NR], al[NR];
+#pragma unroll
+    for (int i = 0; i < NR; i++) {
+        const unsigned char *p = buf + (16 * (rb + i) + l16) * L::RS + lk * 16;
+        ah[i] = *(const u32x4 *)p;
+        al[i] = *(const u32x4 *)(p + L::PLANEB);
+    }
+    const unsigned char *pc = buf + (16 * cb + l16) * L::RS + lk * 16;
+    const unsigned char *pw = buf + (16 * wb + l16) * L::RS + lk * 16;
+    u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
+    u32x4 mh = *(const u32x4 *)pw, ml = *(const u32x4 *)(pw + L::PLANEB);
+#pragma unroll
+    for (int j = 0; j < kTI; j++) {
+        const u32x4 bh = nh, bl = nl, wh = mh, wl = ml;
+        if (j + 1 < kTI) {
+            const unsigned char *q = pc + 16 * (j + 1) * L::RS, *r = pw + 16 * (j + 1) * L::RS;
+            nh = *(const u32x4 *)q;
+            nl = *(const u32x4 *)(q + L::PLANEB);
+            mh = *(const u32x4 *)r;
+            ml = *(const u32x4 *)(r + L::PLANEB);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this column's products
+#pragma unroll
+        for (int i = 0; i < NR; i++) mfma_pair(ah[i], bh, wh, re[i * kTI + j], im[i * kTI + j]);
+#pragma unroll
+        for (int i = 0; i < NR; i++) mfma_pair(ah[i], bl, wl, re[i * kTI + j], im[i * kTI + j]);
+#pragma unroll
+        for (int i = 0; i < NR; i++) mfma_pair(al[i], bh, wh, re[i * kTI + j], im[i * kTI + j]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+__global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
+    typedef GeomCoh L;
+    constexpr int RS = L::RS;
+    constexpr int SPS = 16;         // sources per stage
+    constexpr int BUF = 4 * kST * RS;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
+    __shared__ AntEntry tab[2 * kST];
+    __shared__ PairSrc src[2][SPS];
+
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid / kWave;
+    const int l16 = lane & 15, lk = lane >> 4;
+    const int Np = a.n_rows_pad;
+    const int nb = Np / (2 * kST);
+    const int n_kind = nb * (nb - 1);  // two kinds per block pair
+    const int total = a.work[a.n_inst] * n_kind;
+    const int per_xcd = a.grid / 8;
+    const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int mp = tid % (SPS / 2);   // source pair 2 mp, 2 mp + 1
+    const int a0 = tid / (SPS / 2);   // antennas a0 + 64 k of the 256 of blocks I (k < 2) and J
+    const int simd = wave & 3, pr = wave >> 2;
+    const int rh = (simd >> 1) ^ pr, ch = simd & 1;
+    const int o_rb = pr * 8 + 4 * rh, o_cb = 2 * 8 + 4 * ch, o_wb = 3 * 8 + 4 * ch;
+    const bool mult_first = wave < 4;
+
+    for (int item = slot_x; item < total; item += a.grid) {
+        int lo = 0, hi = a.n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.work[mid] * n_kind <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int inst = lo;
+        const int local = item - a.work[inst] * n_kind;
+        const int s = local / n_kind;
+        const int kind = local % n_kind;
+        const bool kind_y = kind & 1;
+        int q = kind >> 1, I = 1;  // pairs (1, 0), (2, 0), (2, 1), (3, 0), ...
+        while (q >= I) {
+            q -= I;
+            I++;
+        }
+        const int J = q;
+        const int n_i = a.n_ant - I * kST < kST ? a.n_ant - I * kST : kST;  // antennas of block I
+        int nrt = (n_i + 15) / 16 - 4 * rh;                              // this wave's row tiles
+        nrt = nrt < 0 ? 0 : nrt > kTI ? kTI : nrt;
+        const int tslot = inst / a.nfb;
+        const int f = a.f0 + inst % a.nfb;
+        const int64_t M = a.count[tslot];
+        const int64_t ms_per_split = a.kcols[inst] / 2;
+        const int64_t m_begin = (int64_t)s * ms_per_split;
+        const int64_t m_end = m_begin + ms_per_split < M ? m_begin + ms_per_split : M;
+        const int n_stage = (int)((m_end - m_begin + SPS - 1) / SPS);
+        const double *sh = a.s_hat + (int64_t)tslot * 3 * a.ld_src;
+        const float2 *Bm = (const float2 *)a.B + (int64_t)inst * 4 * a.ld_src;
+
+        {
+            const double nu_c = a.freqs[f] / kSpeedOfLight;
+            for (int as = tid; as < 2 * kST; as += 512) {
+                const int ant = as < kST ? I * kST + as : J * kST + (as - kST);
+                AntEntry e;
+                if (ant < a.n_ant) {
+                    e.ux = nu_c * a.antc[3 * ant];
+                    e.uy = nu_c * a.antc[3 * ant + 1];
+                    e.uz = nu_c * a.antc[3 * ant + 2];
+                    e.b = 0;
+                } else {
+                    e.ux = e.uy = e.uz = 0.0;
+                    e.b = -1;
+                }
+                e.pad = 0;
+                tab[as] = e;
+            }
+        }
+
+        // per-source direction and coherency, loaded and formed one stage ahead by
+        // the first SPS lanes of wave 0
+        const bool fetcher = tid < SPS;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        float2 fb[4];
+        auto fetch = [&](int stage) {
+            const int64_t m = m_begin + (int64_t)stage * SPS + tid;
+            const bool ok = stage < n_stage && m < m_end;
+            fx = fy = fz = 0.0;
+            for (int c = 0; c < 4; c++) fb[c] = make_float2(0.f, 0.f);
+            if (ok) {
+                fx = sh[m];
+                fy = sh[a.ld_src + m];
+                fz = sh[2 * a.ld_src + m];
+                for (int c = 0; c < 4; c++) fb[c] = Bm[(int64_t)c * a.ld_src + m];
+            }
+        };
+        auto stash = [&](int stage) {
+            PairSrc &e = src[stage & 1][tid];
+            e.x = fx;
+            e.y = fy;
+            e.z = fz;
+            // B components c = 2 p + k; C_10 = B_10 conj(B_00) + B_11 conj(B_01)
+            e.c00 = fb[0].x * fb[0].x + fb[0].y * fb[0].y + fb[1].x * fb[1].x + fb[1].y * fb[1].y;
+            e.c11 = fb[2].x * fb[2].x + fb[2].y * fb[2].y + fb[3].x * fb[3].x + fb[3].y * fb[3].y;
+            e.c10x = fb[2].x * fb[0].x + fb[2].y * fb[0].y + fb[3].x * fb[1].x + fb[3].y * fb[1].y;
+            e.c10y = fb[2].y * fb[0].x - fb[2].x * fb[0].y + fb[3].y * fb[1].x - fb[3].x * fb[1].y;
+        };
+        // Weighted rows of block I (planes 0, 1) or plain and rotated rows of block
+        // J (planes 2, 3) for this thread's two sources.  Rows of block I past its
+        // antennas are skipped (never multiplied); a source past the split has zero
+        // weights, and its J rows only meet zero-weighted I rows.
+        auto produce = [&](unsigned char *buf, int stage, auto ky) {
+            constexpr bool KY = decltype(ky)::value;
+            PairSrc w[2];
+            w[0] = src[stage & 1][2 * mp];
+            w[1] = src[stage & 1][2 * mp + 1];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int as = a0 + 64 * k;
+                const bool in_i = k < 2;
+                if (in_i && as >= n_i) continue;
+                const AntEntry e = tab[as];
+                float fr[2], fi[2];
+#pragma unroll
+                for (int qq = 0; qq < 2; qq++) {
+                    const double p = e.ux * w[qq].x + e.uy * w[qq].y + e.uz * w[qq].z;
+                    const float r = (float)__builtin_amdgcn_fract(p);
+                    fi[qq] = __builtin_amdgcn_sinf(-r);
+                    fr[qq] = __builtin_amdgcn_cosf(-r);
+                }
+                if (in_i) {
+                    uint32_t h0[2], l0[2], h1[2], l1[2];
+#pragma unroll
+                    for (int qq = 0; qq < 2; qq++) {
+                        if constexpr (KY) {  // w0 = C_10, w1 = conj C_10
+                            const float cx = w[qq].c10x, cy = w[qq].c10y;
+                            split2(cx * fr[qq] - cy * fi[qq], cx * fi[qq] + cy * fr[qq], h0[qq], l0[qq]);
+                            split2(cx * fr[qq] + cy * fi[qq], cx * fi[qq] - cy * fr[qq], h1[qq], l1[qq]);
+                        } else {  // w0 = C_00, w1 = C_11
+                            split2(w[qq].c00 * fr[qq], w[qq].c00 * fi[qq], h0[qq], l0[qq]);
+                            split2(w[qq].c11 * fr[qq], w[qq].c11 * fi[qq], h1[qq], l1[qq]);
+                        }
+                    }
+                    unsigned char *r0 = buf + as * RS + mp * 8, *r1 = buf + (kST + as) * RS + mp * 8;
+                    *(uint2 *)r0 = make_uint2(h0[0], h0[1]);
+                    *(uint2 *)(r0 + L::PLANEB) = make_uint2(l0[0], l0[1]);
+                    *(uint2 *)r1 = make_uint2(h1[0], h1[1]);
+                    *(uint2 *)(r1 + L::PLANEB) = make_uint2(l1[0], l1[1]);
+                } else {
+                    uint32_t h[2], l[2];
+#pragma unroll
+                    for (int qq = 0; qq < 2; qq++) split2(fr[qq], fi[qq], h[qq], l[qq]);
+                    const int rj = as - kST;  // row of block J
+                    unsigned char *r2 = buf + (2 * kST + rj) * RS + mp * 8, *r3 = buf + (3 * kST + rj) * RS + mp * 8;
+                    *(uint2 *)r2 = make_uint2(h[0], h[1]);
+                    *(uint2 *)(r2 + L::PLANEB) = make_uint2(l[0], l[1]);
+                    // (re, im) -> (-im, re) on each bf16 pair: swap the halves, negate the low one
+                    *(uint2 *)r3 = make_uint2(__builtin_amdgcn_alignbit(h[0], h[0], 16) ^ 0x00008000u,
+                                              __builtin_amdgcn_alignbit(h[1], h[1], 16) ^ 0x00008000u);
+                    *(uint2 *)(r3 + L::PLANEB) = make_uint2(__builtin_amdgcn_alignbit(l[0], l[0], 16) ^ 0x00008000u,
+                                                            __builtin_amdgcn_alignbit(l[1], l[1], 16) ^ 0x00008000u);
+                }
+            }
+        };
+
+        f32x4 acc_re[16], acc_im[16];
+        for (int t = 0; t < 16; t++)
+            for (int e = 0; e < 4; e++) {
+                acc_re[t][e] = 0.f;
+                acc_im[t][e] = 0.f;
+            }
+        auto consume = [&](const unsigned char *buf) {
+            switch (nrt) {
+                case 4: consume_pairs_b3<L, 4>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
+                case 3: consume_pairs_b3<L, 3>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
+                case 2: consume_pairs_b3<L, 2>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
+                case 1: consume_pairs_b3<L, 1>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
+                default: break;
+            }
+        };
+        auto run = [&](auto ky) {
+            if (fetcher) {
+                fetch(0);
+                stash(0);
+                fetch(1);
+                stash(1);
+            }
+            __syncthreads();  // antenna table and the first two stages' sources ready
+            produce(lds, 0, ky);
+            __syncthreads();
+            for (int stg = 0; stg < n_stage; stg++) {
+                unsigned char *cur = lds + (stg & 1) * BUF;
+                unsigned char *nxt = lds + ((stg + 1) & 1) * BUF;
+                const bool more = stg + 1 < n_stage;
+                if (fetcher && stg + 2 < n_stage) fetch(stg + 2);
+                if (mult_first) consume(cur);
+                if (more) produce(nxt, stg + 1, ky);
+                if (!mult_first) consume(cur);
+                // src[stg & 1] was last read by the producers of stage stg (one stage ago)
+                if (fetcher && stg + 2 < n_stage) stash(stg + 2);
+                __syncthreads();
+            }
+        };
+        if (kind_y)
+            run(std::true_type{});
+        else
+            run(std::false_type{});
+
+        int ld = Np;
+        asm volatile("" : "+v"(ld));
+        float2 *P = (float2 *)a.part + ((int64_t)inst * a.max_splits + s) * (int64_t)Np * Np;
+        // product pr at antennas A of block I (rows) and B of block J (columns), A > B:
+        //   X: V^pp at (2 A + pr, 2 B + pr);
+        //   Y: pr = 0, V^10 at (2 A + 1, 2 B); pr = 1, V^01 at (2 A, 2 B + 1)
+        const int row_off = kind_y ? 1 - pr : pr, col_off = kind_y ? pr : pr;
+#pragma unroll
+        for (int i = 0; i < kTI; i++)
+#pragma unroll
+            for (int j = 0; j < kTI; j++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int A = I * kST + 16 * (4 * rh + i) + 4 * lk + e, Bc = J * kST + 16 * (4 * ch + j) + l16;
+                    if (i >= nrt || A >= a.n_ant || Bc >= a.n_ant) continue;
+                    P[(int64_t)(2 * A + row_off) * ld + 2 * Bc + col_off] =
+                        make_float2(acc_re[i * kTI + j][e], acc_im[i * kTI + j][e]);
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Scalar rows (one feed, one axis, one shared beam) in three blocks of 128
 // (257..384 antennas).  Each item pairs one diagonal triangle with one full
 // off-diagonal block that shares its rows, so every item stages two row blocks
@@ -1337,13 +1632,15 @@ struct SclSrc {
     float g, pad;    // |B| (0 past the split)
 };
 
-template <int PREC>
+template <int PREC, int SQ_ROWS = 96>
 __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
     typedef GeomCoh L;
     constexpr int RS = L::RS;
     constexpr int SPS = 16;
     constexpr int BUF = 2 * kST * RS;
-    constexpr int SQ_ROWS = 96;  // rows formed by the square waves, which have more products
+    // SQ_ROWS: rows formed by the square waves of the 256 of a stage (the triangle
+    // waves, with fewer products, form the rest); 96 by default, 64 and 128 as
+    // tuning variants
     static_assert(SQ_ROWS % 32 == 0 && (2 * kST - SQ_ROWS) % 32 == 0, "32 rows per pass of a wave group");
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
     __shared__ AntEntry tab[2 * kST];
@@ -1567,9 +1864,11 @@ hipError_t launch_kind(const FusedArgs &a, hipStream_t s) {
 }
 
 template <int PREC>
-hipError_t launch_prec(const FusedArgs &a, hipStream_t s) {
-    hipError_t e = launch_kind<PREC, true>(a, s);
-    if (e != hipSuccess || a.n_rows_pad <= kST) return e;  // a single row block has no off-diagonal tiles
+hipError_t launch_prec(const FusedArgs &a, hipStream_t s, int which) {
+    hipError_t e = hipSuccess;
+    if (which != FUSED_PAIRS) e = launch_kind<PREC, true>(a, s);
+    if (e != hipSuccess || a.n_rows_pad <= kST || which == FUSED_FIRST)
+        return e;  // a single row block has no off-diagonal tiles
     return launch_kind<PREC, false>(a, s);
 }
 
@@ -1596,32 +1895,66 @@ int fused_path(int prec, int n_feed, int n_ax, int n_beam, int n_ant, int n_rows
     return MATVIS_PATH_FUSED;
 }
 
-hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s) {
+bool fused_has_pairs(int prec, const FusedArgs &a) {
+    const int path = fused_path(prec, a.n_feed, a.n_ax, a.n_beam, a.n_ant, a.n_rows_pad);
+    if (path == MATVIS_PATH_SOURCES) return a.n_rows_pad > 2 * kST;
+    if (path == MATVIS_PATH_FUSED) return a.n_rows_pad > kST;
+    return false;
+}
+
+hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s, int which) {
     if (a.n_inst <= 0) return hipSuccess;
     const int path = fused_path(prec, a.n_feed, a.n_ax, a.n_beam, a.n_ant, a.n_rows_pad);
+    const bool first = which != FUSED_PAIRS, pairs = which != FUSED_FIRST;
+    const int split = a.tile & 15;  // rows per stage formed by the square waves, in units of 32 (0: default)
     if (path == MATVIS_PATH_SOURCES) {
-        if (prec == PB3)
-            k_herk_coh<PB3, false><<<a.grid, 512, 0, s>>>(a);
-        else
-            k_herk_coh<P32, false><<<a.grid, 512, 0, s>>>(a);
-        if (a.n_rows_pad > 2 * kST) {  // pairs of antenna blocks
-            if (prec == PB3)
+        if (first) {
+            if (prec == PB3) {
+                if (split == 2)
+                    k_herk_coh<PB3, false, 64><<<a.grid, 512, 0, s>>>(a);
+                else
+                    k_herk_coh<PB3, false, 96><<<a.grid, 512, 0, s>>>(a);
+            } else {
+                if (split == 2)
+                    k_herk_coh<P32, false, 64><<<a.grid, 512, 0, s>>>(a);
+                else
+                    k_herk_coh<P32, false, 96><<<a.grid, 512, 0, s>>>(a);
+            }
+        }
+        if (pairs && a.n_rows_pad > 2 * kST) {  // pairs of antenna blocks
+            // bits 4-5 of the variant: 0 the one-sided-weight pair kernel (BF16X3), 1 the
+            // two-sided one; FP32 always takes the latter
+            if (prec == PB3 && ((a.tile >> 4) & 3) == 0)
+                k_herk_pairs<<<a.grid, 512, 0, s>>>(a);
+            else if (prec == PB3)
                 k_herk_coh<PB3, true><<<a.grid, 512, 0, s>>>(a);
             else
                 k_herk_coh<P32, true><<<a.grid, 512, 0, s>>>(a);
         }
         return hipGetLastError();
     }
-    if (path == MATVIS_PATH_FUSED_ROWS) return launch_pair(a, s);
+    if (path == MATVIS_PATH_FUSED_ROWS) return first ? launch_pair(a, s) : hipSuccess;
     if (path == MATVIS_PATH_FUSED_BLOCKS) {
-        if (prec == PB3)
-            k_herk_blk3<PB3><<<a.grid, 512, 0, s>>>(a);
-        else
-            k_herk_blk3<P32><<<a.grid, 512, 0, s>>>(a);
+        if (!first) return hipSuccess;
+        if (prec == PB3) {
+            if (split == 2)
+                k_herk_blk3<PB3, 64><<<a.grid, 512, 0, s>>>(a);
+            else if (split == 4)
+                k_herk_blk3<PB3, 128><<<a.grid, 512, 0, s>>>(a);
+            else
+                k_herk_blk3<PB3, 96><<<a.grid, 512, 0, s>>>(a);
+        } else {
+            if (split == 2)
+                k_herk_blk3<P32, 64><<<a.grid, 512, 0, s>>>(a);
+            else if (split == 4)
+                k_herk_blk3<P32, 128><<<a.grid, 512, 0, s>>>(a);
+            else
+                k_herk_blk3<P32, 96><<<a.grid, 512, 0, s>>>(a);
+        }
         return hipGetLastError();
     }
-    if (prec == P32) return launch_prec<P32>(a, s);
-    if (prec == PB3) return launch_prec<PB3>(a, s);
+    if (prec == P32) return launch_prec<P32>(a, s, which);
+    if (prec == PB3) return launch_prec<PB3>(a, s, which);
     return hipErrorInvalidValue;
 }
 

@@ -153,6 +153,21 @@ int64_t round_up(int64_t x, int64_t m) { return ((x + m - 1) / m) * m; }
 
 size_t cbytes(int prec) { return prec == P64 ? 16 : 8; }  // bytes per complex of beams / Z / output
 
+}  // namespace
+
+// The library's k-split (Z columns per product work item) for a precision and
+// product path when the configuration leaves it at 0.
+int64_t mv::default_ksplit(int prec, bool over_sources, bool three_blocks) {
+    return prec == P64                   ? 8192
+           : prec == P32 && over_sources ? 8192
+           : prec == P32                 ? 2048
+           : over_sources                ? 20480
+           : three_blocks                ? 8192
+                                         : 4096;
+}
+
+namespace {
+
 matvis_status validate_cfg(const matvis_config *c, std::string &why) {
     if (!c) return why = "config is NULL", MATVIS_EINVAL;
     if (c->n_ant <= 0) return why = "n_ant must be positive", MATVIS_EINVAL;
@@ -181,6 +196,9 @@ matvis_status validate_cfg(const matvis_config *c, std::string &why) {
         return why = "latitude out of range", MATVIS_EINVAL;
     if (c->src_chunk < 0 || c->batch_time < 0 || c->batch_freq < 0) return why = "negative batch sizes", MATVIS_EINVAL;
     if ((int64_t)c->n_ant * c->n_feed > 8192) return why = "n_ant * n_feed above 8192", MATVIS_EUNSUPPORTED;
+    if (c->tile < 0 || (c->tile & ~0x1f) != 0 || ((c->tile & 15) != 0 && ((c->tile & 15) < 2 || (c->tile & 15) > 4)))
+        return why = "tile: bits 0-3 (forming split) must be 0, 2, 3 or 4, bit 4 (block-pair kernel) 0 or 1, "
+                     "no other bits", MATVIS_EINVAL;
     if (c->ksplit < 0 || c->ksplit % 64 != 0 || c->ksplit > ((int64_t)1 << 30))
         return why = "ksplit must be 0 or a positive multiple of 64", MATVIS_EINVAL;
     return MATVIS_OK;
@@ -239,8 +257,16 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     c->N = cfg->n_ant * cfg->n_feed;
     c->st = herk_super_tile(prec);
     c->Np = (int)round_up(c->N, c->st);
+    // Sources per chunk.  Where Z goes through device memory its size sets the
+    // chunk (2^18 sources); where the product forms Z itself only the per-source
+    // buffers and the k-split partials grow with the chunk, so whole skies of up
+    // to 2^22 sources go in one chunk: every chunk costs a launch of each step,
+    // the load imbalance at the end of each product launch and a pass of the
+    // reduction (on the 3.1M-pixel polarised sky one chunk instead of twelve was
+    // 79.5 -> 71.7 ms per call of 8 instances).
+    c->fused = prec != P64 && !(cfg->flags & MATVIS_FLAG_UNFUSED);
     c->chunk = cfg->src_chunk > 0 ? std::min<int64_t>(cfg->src_chunk, cfg->max_src)
-                                  : std::min<int64_t>(cfg->max_src, (int64_t)1 << 18);
+                                  : std::min<int64_t>(cfg->max_src, (int64_t)1 << (c->fused ? 22 : 18));
     c->ldz = round_up((int64_t)cfg->n_ax * c->chunk, kColPad);
     // Columns per work item.  FP32 accumulators see ksplit / 2 sequential MFMA
     // updates per item; 2048 keeps that rounding near 2e-6 of the Cauchy-Schwarz
@@ -253,7 +279,6 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     // the same workload; 20480 (~5.4e-6) keeps a factor 1.8 to 1e-5, and at the
     // benchmark's ~50 000 visible columns it gives three splits per instance
     // instead of four (fewer items and partials: 1.4 % of its step).
-    c->fused = prec != P64 && !(cfg->flags & MATVIS_FLAG_UNFUSED);
     const bool over_sources =
         c->fused && fused_path(prec, cfg->n_feed, cfg->n_ax, cfg->n_beam, cfg->n_ant, c->Np) == MATVIS_PATH_SOURCES;
     if (over_sources) c->Np = (int)round_up(c->N, 2 * c->st);  // whole blocks of 128 antennas x 2 feeds
@@ -264,13 +289,7 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     // its reduction went from 0.82 to 0.46 ms per two instances)
     const bool three_blocks =
         c->fused && fused_path(prec, cfg->n_feed, cfg->n_ax, cfg->n_beam, cfg->n_ant, c->Np) == MATVIS_PATH_FUSED_BLOCKS;
-    c->ksplit = cfg->ksplit > 0 ? cfg->ksplit
-                                : (prec == P64            ? 8192
-                                   : prec == P32 && over_sources ? 8192
-                                   : prec == P32            ? 2048
-                                   : over_sources           ? 20480
-                                   : three_blocks           ? 8192
-                                                            : 4096);
+    c->ksplit = cfg->ksplit > 0 ? cfg->ksplit : default_ksplit(prec, over_sources, three_blocks);
     c->max_splits = (int)((c->ldz + c->ksplit - 1) / c->ksplit);
     // batch: all channels of a few times, enough instances to fill the GPU with
     // work items while keeping Z within a fixed share of device memory
@@ -482,7 +501,13 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                     fa.part = c->part;
                     fa.work = c->work;
                     fa.grid = c->fused_grid;
-                    STEP(c, MATVIS_STEP_HERK, s, launch_herk_fused(prec, fa, s));
+                    fa.tile = g.tile;
+                    if (c->profiling && fused_has_pairs(prec, fa)) {  // time the two launches apart
+                        STEP(c, MATVIS_STEP_HERK, s, launch_herk_fused(prec, fa, s, FUSED_FIRST));
+                        STEP(c, MATVIS_STEP_HERK_PAIRS, s, launch_herk_fused(prec, fa, s, FUSED_PAIRS));
+                    } else {
+                        STEP(c, MATVIS_STEP_HERK, s, launch_herk_fused(prec, fa, s));
+                    }
                 }
 
                 ZformArgs za{};

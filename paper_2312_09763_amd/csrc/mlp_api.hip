@@ -59,8 +59,8 @@ struct Work {
     static int64_t floats_for(int64_t rows) {
         int64_t total = 0;
         float *dummy[16] = {};
-        each(rows, &dummy[0], &dummy[1], &dummy[5], &dummy[9], &dummy[10], &dummy[11], &dummy[12], &dummy[13],
-             &dummy[14], [&](float **, int64_t count) {
+        (void)each(rows, &dummy[0], &dummy[1], &dummy[5], &dummy[9], &dummy[10], &dummy[11], &dummy[12], &dummy[13],
+                   &dummy[14], [&](float **, int64_t count) {
                  total += round_a(count);
                  return hipSuccess;
              });
@@ -84,7 +84,7 @@ struct Work {
         n = rows;
         ws_elems = ws_for(rows);
         int64_t off = 0;
-        each(rows, &phi, Z, H, &out, &dout, &dH, &dZ, &part, &ws, [&](float **p, int64_t count) {
+        (void)each(rows, &phi, Z, H, &out, &dout, &dH, &dZ, &part, &ws, [&](float **p, int64_t count) {
             *p = base + off;
             off += round_a(count);
             return hipSuccess;

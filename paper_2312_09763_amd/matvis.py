@@ -27,7 +27,7 @@ FLAG_NO_GRAPH = 1
 FLAG_UNFUSED = 2
 FLAG_POLARISED_SKY = 4
 
-STEPS = ("sky", "beam", "zform", "herk", "reduce", "other")
+STEPS = ("sky", "beam", "zform", "herk", "reduce", "other", "herk_pairs")
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 BEAM_MODES = {"bilinear": BILINEAR, "bicubic": BICUBIC, "surrogate": SURROGATE}
 MLP_N_PARAMS = 83848  # learned-beam parameter count (include/matvis.h)
@@ -47,7 +47,7 @@ class _Config(ctypes.Structure):
                 ("beam_mode", ctypes.c_int32), ("n_za", ctypes.c_int32), ("n_az", ctypes.c_int32),
                 ("dza_rad", ctypes.c_double), ("daz_rad", ctypes.c_double), ("src_chunk", ctypes.c_int64),
                 ("batch_time", ctypes.c_int32), ("batch_freq", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("ksplit", ctypes.c_int64)]
+                ("ksplit", ctypes.c_int64), ("tile", ctypes.c_int32)]
 
 
 _lib = None
@@ -83,7 +83,7 @@ def load_library():
     L.matvis_step_herk.restype = ctypes.c_int
     L.matvis_autotune.argtypes = [ctypes.POINTER(_Config), _P, _P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P,
                                   ctypes.c_int64, _P, _P, _P, _P, ctypes.c_char_p, ctypes.POINTER(_Config),
-                                  ctypes.POINTER(ctypes.c_double)]
+                                  ctypes.POINTER(ctypes.c_double), _P, ctypes.c_double, ctypes.c_double]
     L.matvis_autotune.restype = ctypes.c_int
     L.matvis_profile_enable.argtypes = [_P, ctypes.c_int32]
     L.matvis_profile_enable.restype = ctypes.c_int
@@ -152,6 +152,7 @@ class Config:
     unfused: bool = False  # FP32 / BF16X3: separate Z-formation step (Z in device memory)
     ksplit: int = 0        # columns per product work item (multiple of 64); 0 = automatic
     polarised_sky: bool = False  # src_flux is [4][n_freq][n_src] (I, Q, U, V); needs n_ax = 2
+    tile: int = 0          # product kernel variant (bits 0-3: forming split in 32-antenna units); 0 = automatic
 
     def _c(self) -> _Config:
         return _Config(self.n_ant, self.n_feed, self.n_ax, self.n_beam, self.max_src, self.max_time, self.max_freq,
@@ -159,7 +160,7 @@ class Config:
                        self.n_az, self.dza_rad, self.daz_rad, self.src_chunk, self.batch_time, self.batch_freq,
                        (0 if self.use_graph else FLAG_NO_GRAPH) | (FLAG_UNFUSED if self.unfused else 0) |
                        (FLAG_POLARISED_SKY if self.polarised_sky else 0),
-                       self.ksplit)
+                       self.ksplit, self.tile)
 
 
 def _ptr(t) -> Optional[int]:
@@ -354,8 +355,9 @@ class Context:
 
 
 def autotune(cfg: Config, antpos, freqs, lsts, src_radec, src_flux, beam_grid, beam_idx=None, vis=None,
-             cache_path: Optional[str] = None, stream=None):
-    """matvis_autotune: (tuned Config, ms per simulate call).  ``vis`` is scratch output."""
+             cache_path: Optional[str] = None, stream=None, surrogate=None, nu_range=(100e6, 200e6)):
+    """matvis_autotune: (tuned Config, ms per simulate call).  ``vis`` is scratch output;
+    ``surrogate`` the learned beam's parameters when cfg.beam_mode is "surrogate"."""
     import torch
     L = load_library()
     n_freq, n_time, n_src = freqs.shape[0], lsts.shape[0], src_radec.shape[1]
@@ -368,10 +370,11 @@ def autotune(cfg: Config, antpos, freqs, lsts, src_radec, src_flux, beam_grid, b
     st = L.matvis_autotune(ctypes.byref(cfg._c()), _ptr(antpos), _ptr(beam_idx), _ptr(freqs), n_freq, _ptr(lsts),
                            n_time, _ptr(src_radec), n_src, _ptr(src_flux), _ptr(beam_grid), _ptr(vis),
                            _stream_handle(stream), cache_path.encode() if cache_path else None, ctypes.byref(best),
-                           ctypes.byref(ms))
+                           ctypes.byref(ms), _ptr(surrogate), float(nu_range[0]), float(nu_range[1]))
     if st != OK:
         raise MatvisError(st, "matvis_autotune failed")
     tuned = dataclasses.replace(cfg, ksplit=int(best.ksplit), batch_time=int(best.batch_time),
+                                src_chunk=int(best.src_chunk), tile=int(best.tile),
                                 unfused=bool(best.flags & FLAG_UNFUSED))
     return tuned, float(ms.value)
 

@@ -312,6 +312,24 @@ def beam_grid(kind: str, freqs: np.ndarray, step_deg: float, n_feed: int, n_ax: 
     return g
 
 
+def antenna_beams(freqs: np.ndarray, step_deg: float, n_beam: int, seed: int = 0,
+                  dtype=np.complex64) -> np.ndarray:
+    """n_beam distinct crossed-dipole Jones beams on the az/za grid, one per antenna
+    (Sec. 3.5 allows a beam per antenna: beam index a_i): beam b has its own power
+    FWHM 60 deg x (1 + 0.05 g_b) at 150 MHz and chromatic phase 0.1 x (1 + 0.2 h_b),
+    g_b, h_b ~ N(0, 1) seeded.  Returns [n_beam, n_freq, 2, 2, n_za, n_az]."""
+    n_za, n_az, dza, daz = grid_axes(step_deg)
+    za = (np.arange(n_za) * dza)[:, None] * np.ones((1, n_az))
+    az = np.ones((n_za, 1)) * (np.arange(n_az) * daz)[None, :]
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 9000 + int(seed)))
+    g, h = rng.normal(0.0, 1.0, n_beam), rng.normal(0.0, 1.0, n_beam)
+    out = np.empty((n_beam, len(freqs), 2, 2, n_za, n_az), dtype=dtype)
+    for b in range(n_beam):
+        for f, nu in enumerate(freqs):
+            out[b, f] = dipole_beam(za, az, nu, fwhm150_deg=60.0 * (1.0 + 0.05 * g[b]), chrom=0.1 * (1.0 + 0.2 * h[b]))
+    return out
+
+
 # --------------------------------------------------------------------------
 # Workloads
 # --------------------------------------------------------------------------

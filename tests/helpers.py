@@ -26,10 +26,11 @@ def gpu_simulate(wl, precision, **cfgkw):
     if precision.endswith("-unfused"):
         precision = precision[:-len("-unfused")]
         cfgkw["unfused"] = True
+    beam_idx = cfgkw.pop("beam_idx", None)
     cfg = mv.config_for(wl, precision, **cfgkw)
     d = mv.device_inputs(wl, precision)
     with mv.Context(cfg) as ctx:
-        vis = ctx.simulate(**d)
+        vis = ctx.simulate(**d, beam_idx=beam_idx)
         ctx.finish()
         torch.cuda.synchronize()
         V = vis.cpu().numpy().astype(np.complex128)

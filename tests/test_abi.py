@@ -115,3 +115,18 @@ def test_binding_refuses_without_library(monkeypatch):
     monkeypatch.setattr(mv, "LIB_PATH", "/nonexistent/libmatvis.so")
     with pytest.raises(RuntimeError):
         mv.load_library()
+
+
+def test_autotune_learned_beam_needs_parameters():
+    cfg = mv.Config(n_ant=4, max_src=10, beam_mode="surrogate", precision="bf16x3")
+    best = mv._Config()
+    ms = ctypes.c_double()
+    st = mv.load_library().matvis_autotune(ctypes.byref(cfg._c()), None, None, None, 1, None, 1, None, 10, None, None,
+                                           None, None, None, ctypes.byref(best), ctypes.byref(ms), None, 1e8, 2e8)
+    assert st == mv.EINVAL
+
+
+@pytest.mark.parametrize("tile", [1, 5, 32, -1])
+def test_init_rejects_unknown_tile(tile):
+    st, h = _init(tile=tile)
+    assert st == mv.EINVAL and not h.value

@@ -20,23 +20,54 @@ def test_autotune_picks_cached_candidate_and_stays_accurate(tmp_path, precision)
     d = mv.device_inputs(wl, precision)
     cache = str(tmp_path / "tune.json")
     tuned, ms = mv.autotune(cfg, **d, cache_path=cache)
-    say(f"autotune {precision}: ksplit={tuned.ksplit} batch_time={tuned.batch_time} unfused={tuned.unfused} {ms:.3f} ms")
-    # 0: the library's own choice, also a candidate
-    allowed = {"fp32": {0, 1024, 2048}, "bf16x3": {0, 2048, 4096, 8192}}[precision]
-    assert tuned.ksplit in allowed and tuned.batch_time in (0, 2, 4) and ms > 0
+    say(f"autotune {precision}: tile={tuned.tile} ksplit={tuned.ksplit} src_chunk={tuned.src_chunk} "
+        f"batch_time={tuned.batch_time} unfused={tuned.unfused} {ms:.3f} ms")
+    # candidates: 0 (the library's choice) and, on the product over sources, half and a
+    # quarter of the path's default k-split (8192 FP32, 20480 BF16X3), the 64-antenna
+    # forming split, times per batch 1..8 (<= 5 here); no chunk below 3001 sources
+    allowed = {"fp32": {0, 4096, 2048}, "bf16x3": {0, 10240, 5120}}[precision]
+    assert tuned.ksplit in allowed and tuned.batch_time in (0, 1, 2, 4) and tuned.tile in (0, 2)
+    assert tuned.src_chunk == 0 and ms > 0
     text = open(cache).read()
     entries = json.loads(text)
     assert len(entries) == 1
     (key, val), = entries.items()
-    assert key.startswith("gfx950|N256|ax2|src3001|t5|f3")
-    assert val["ksplit"] == tuned.ksplit
+    assert key == f"gfx950|path3|N256|ax2|nb1|fl0|src2^11|t5|f3|p{ {'fp32': 1, 'bf16x3': 2}[precision] }|b1"
+    assert (val["ksplit"], val["tile"], val["src_chunk"]) == (tuned.ksplit, tuned.tile, tuned.src_chunk)
     # a second call is answered from the cache
     tuned2, ms2 = mv.autotune(cfg, **d, cache_path=cache)
-    assert (tuned2.ksplit, tuned2.batch_time, tuned2.unfused) == (tuned.ksplit, tuned.batch_time, tuned.unfused)
+    assert (tuned2.ksplit, tuned2.batch_time, tuned2.unfused, tuned2.tile, tuned2.src_chunk) == \
+        (tuned.ksplit, tuned.batch_time, tuned.unfused, tuned.tile, tuned.src_chunk)
     assert abs(ms2 - ms) < 1e-3
     # the tuned configuration is still within the precision's tolerance
-    V = gpu_simulate(wl, precision, ksplit=tuned.ksplit, batch_time=tuned.batch_time, unfused=tuned.unfused)
+    V = gpu_simulate(wl, precision, ksplit=tuned.ksplit, batch_time=tuned.batch_time, unfused=tuned.unfused,
+                     tile=tuned.tile, src_chunk=tuned.src_chunk)
     ref = oracle_vis(wl, grid=grid_as_used(wl, precision))
     ef, ec = errors(V, ref)
     say(f"  err_F={ef:.3e} err_CS={ec:.3e}")
     assert ef <= TOL[precision] and ec <= TOL[precision]
+
+
+@pytest.mark.parametrize("tile", [2, 3])
+def test_forming_split_variants_agree(tile):
+    """The kernel variants the autotuner picks among give the same visibilities:
+    the forming split only reschedules work, so the result is bitwise the same."""
+    wl = synth.workload(2, n_ant=128, n_src=700, n_time=2, n_freq=2)
+    V0 = gpu_simulate(wl, "bf16x3")
+    V1 = gpu_simulate(wl, "bf16x3", tile=tile)
+    say(f"forming split {32 * tile} antennas: bitwise equal {np.array_equal(V0, V1)}")
+    assert np.array_equal(V0, V1)
+    ws = synth.workload(3, n_src=3072, n_time=1, n_freq=2)
+    for t in (2, 4):
+        assert np.array_equal(gpu_simulate(ws, "bf16x3"), gpu_simulate(ws, "bf16x3", tile=t))
+
+
+def test_autotune_learned_beam(tmp_path):
+    import torch
+    wl = synth.workload(2, n_ant=96, n_src=2000, n_time=2, n_freq=2)
+    cfg = mv.config_for(wl, "bf16x3", beam_mode="surrogate")
+    d = mv.device_inputs(wl, "bf16x3")
+    P = torch.from_numpy(synth.surrogate_init(0)).cuda()
+    tuned, ms = mv.autotune(cfg, **d, cache_path=str(tmp_path / "t.json"), surrogate=P)
+    say(f"autotune with the learned beam: tile={tuned.tile} ksplit={tuned.ksplit} {ms:.3f} ms")
+    assert ms > 0 and tuned.beam_mode == "surrogate"

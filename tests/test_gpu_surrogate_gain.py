@@ -27,7 +27,7 @@ import torch
 import oracle
 from oracle import metrics
 from paper_2312_09763_amd import matvis as mv
-from paper_2312_09763_amd import synth
+from paper_2312_09763_amd import learned_beam, synth
 
 from helpers import sample_pairs, sampled_err_cs, say
 
@@ -52,22 +52,10 @@ def _jones_rows(j):
 
 @pytest.fixture(scope="module")
 def trained():
-    wl = synth.workload(2, n_ant=4, n_src=10, n_time=1)  # 16 channels, 100-200 MHz, dipole, 0.5 deg
-    grid = _dev(wl.beam[0].astype(np.complex64), np.complex64)
-    freqs = _dev(wl.freqs, np.float64)
-
-    def samples(n, seed):
-        rng = np.random.Generator(np.random.PCG64(seed))
-        za, az = synth.hemisphere_points(rng, n)
-        chan = rng.integers(0, wl.n_freq, n).astype(np.int32)
-        return mv.beam_samples(grid, wl.dza, wl.daz, _dev(za, np.float64), _dev(az, np.float64),
-                               _dev(chan, np.int32), bicubic=True, chan_freq=freqs, nu_range=(NU0, NU1))
-
-    y, x = samples(1 << 20, 1)
-    yh, xh = samples(100_000, 2)
-    P = _dev(synth.surrogate_init(0, sigma_v=1.0, az_max=4, sigma_w=0.5), np.float32)
     say("training the learned beam: 2^20 samples, 60 epochs, batch 1024")
-    hist = mv.train_surrogate(P, x, y, batch=1024, epochs=60, lr0=3e-3, lr1=3e-5, seed=1)
+    P, hist, wl, grid = learned_beam.train(epochs=60, n_samples=1 << 20, batch=1024, seed=1)
+    freqs = _dev(wl.freqs, np.float64)
+    yh, xh = learned_beam.samples(wl, grid, freqs, 100_000, 2)
     say(f"  loss {hist[0]:.3e} -> {hist[-1]:.3e}")
     return dict(wl=wl, grid=grid, P=P, xh=xh, yh=yh, hist=hist)
 
