@@ -150,7 +150,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n-time", type=int, default=2, help="LSTs in the headline's instance sample")
     ap.add_argument("--n-freq", type=int, default=8, help="channels in the headline's instance sample")
-    ap.add_argument("--train-epochs", type=int, default=60)
+    ap.add_argument("--train-epochs", type=int, default=60,
+                    help="epochs of the learned beam's training (0: untrained weights, for profiling runs only)")
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true", help="use the library's defaults")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -190,9 +191,12 @@ def main():
     log(f"workload5 sample: {wl.n_ant} antennas x {wl.n_feed} feeds, {wl.n_src} pixels, LSTs {wl.lsts}, "
         f"channels {np.round(wl.freqs / 1e6, 2)} MHz ({time.perf_counter() - t0:.1f} s to generate)")
     t0 = time.perf_counter()
-    P, hist, _, _ = learned_beam.train(epochs=args.train_epochs)
+    if args.train_epochs > 0:
+        P, hist, _, _ = learned_beam.train(epochs=args.train_epochs)
+    else:  # profiling runs only: the step's time does not depend on the weights
+        P, hist = torch.from_numpy(synth.surrogate_init(0, sigma_v=1.0, az_max=4, sigma_w=0.5)).cuda(), [float("nan")]
     train_s = time.perf_counter() - t0
-    log(f"learned beam trained: {args.train_epochs} epochs of 2^20 samples, loss {hist[0]:.3e} -> {hist[-1]:.3e} "
+    log(f"learned beam: {args.train_epochs} epochs of 2^20 samples, loss {hist[0]:.3e} -> {hist[-1]:.3e} "
         f"({train_s:.1f} s)")
     d = mv.device_inputs(wl, prec)
     base = mv.config_for(wl, prec, beam_mode="surrogate")
@@ -243,8 +247,8 @@ def main():
     log(f"per-step device ms {steps_ms}; block-pair launch {launch_ms:.3f} ms x {pair_n / args.profile_steps:.0f} "
         f"per step at {achieved:.1f} TFLOP/s ({achieved / PEAK_TFLOPS[prec]:.3f} of peak); whole product "
         f"{prod_ms:.2f} ms/step at {prod_tf / PEAK_TFLOPS[prec]:.3f} of peak")
-    kname = "k_herk_coh<2, true, 96>"
-    rec = profile_record("herk_coh_pairs_bf16x3_workload5")
+    kname = "k_herk_pairs"
+    rec = profile_record("herk_pairs_bf16x3_workload5")
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[prec],
                 "traffic": rec["traffic_bytes_per_launch"] if rec else None,

@@ -221,7 +221,7 @@ extern "C" matvis_status matvis_autotune(const matvis_config *base, const double
         {&ksplits, [](matvis_config &c, long long v) { c.ksplit = v; }},
         {&chunks, [](matvis_config &c, long long v) { c.src_chunk = v; }},
         {&tbs, [](matvis_config &c, long long v) { c.batch_time = (int32_t)v; }},
-        {&fuse, [keep](matvis_config &c, long long v) { c.flags = (c.flags & keep) | (int32_t)v; }},
+        {&fuse, [](matvis_config &c, long long v) { c.flags = (c.flags & ~(MATVIS_FLAG_UNFUSED | MATVIS_FLAG_NO_GRAPH)) | (int32_t)v; }},
     };
     for (const Axis &ax : axes)
         for (long long v : *ax.vals) {
