@@ -527,7 +527,8 @@ def workloads_section(args):
 def redundancy_section(args):
     """Full product V = Z Z^H against the sub-matrix product of App. A for the unique
     baselines of a redundant 350-antenna hexagon (the diffuse-sky array), BF16X3,
-    FP32 and FP64 with Z in device memory; per-step device times from the profiled pass."""
+    FP32 and FP64 with Z in device memory, and BF16X3 and FP32 with Z formed in the
+    product's stages; per-step device times from the profiled pass."""
     import torch
     from paper_2312_09763_amd import matvis as mv
     from paper_2312_09763_amd import synth
@@ -536,8 +537,9 @@ def redundancy_section(args):
     res = {"workload": f"{wl.n_ant}-antenna hexagon, {wl.n_src} equal-area pixels, {wl.n_time} LSTs x "
                        f"{wl.n_freq} channels, scalar Gaussian beam",
            "n_ant": wl.n_ant, "pairs": wl.n_ant * (wl.n_ant + 1) // 2, "unique_pairs": len(reps)}
-    for prec in ("bf16x3", "fp32", "fp64"):
-        cfg = mv.config_for(wl, prec, unfused=(prec != "fp64"))
+    for key in ("bf16x3", "fp32", "fp64", "bf16x3_fused", "fp32_fused"):
+        prec = key.replace("_fused", "")
+        cfg = mv.config_for(wl, prec, unfused=(prec != "fp64" and not key.endswith("_fused")))
         d = mv.device_inputs(wl, prec)
         with mv.Context(cfg) as ctx:
             size = ctx.set_pairs(reps, 3)
@@ -564,10 +566,10 @@ def redundancy_section(args):
                 r[f"{mode}_reduce_ms"] = prof["reduce"][0]
             r["product_speedup"] = r["full_product_ms"] / r["pairs_product_ms"]
             r["step_speedup"] = r["full_ms_per_step"] / r["pairs_ms_per_step"]
-            log(f"redundancy {prec}: {len(reps)} unique pairs, compression {r['compression']:.1f}, product "
+            log(f"redundancy {key}: {len(reps)} unique pairs, compression {r['compression']:.1f}, product "
                 f"{r['full_product_ms']:.2f} -> {r['pairs_product_ms']:.2f} ms, step {r['full_ms_per_step']:.2f} -> "
                 f"{r['pairs_ms_per_step']:.2f} ms")
-            res[prec] = r
+            res[key] = r
     return res
 
 

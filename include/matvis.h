@@ -179,10 +179,11 @@ matvis_status matvis_submatrix_plan(const int32_t *pair_a, const int32_t *pair_b
 /* Plan the sub-matrix product for the pairs (pair_a[u], pair_b[u]) (host
  * arrays, antennas in [0, n_ant); any pairs, usually the representatives of
  * matvis_redundant_groups) with n_sub sub-matrices, and upload the plan to
- * the context's device.  Needs Z in device memory (precision FP64, or FP32 /
- * BF16X3 with MATVIS_FLAG_UNFUSED): MATVIS_EUNSUPPORTED otherwise.  Allocates the
- * plan's scratch (so call it outside graph capture); replaces an earlier
- * plan.  *size_out (may be NULL) receives the total sub-matrix size
+ * the context's device.  Any precision: with Z in device memory (FP64, or
+ * MATVIS_FLAG_UNFUSED) the sub-matrix rows are gathered from it; otherwise
+ * (FP32 / BF16X3) they are formed in the product's stages from the beam and
+ * the fringe phase, as the full product forms Z.  Allocates the plan's
+ * scratch (so call it outside graph capture); replaces an earlier plan.  *size_out (may be NULL) receives the total sub-matrix size
  * sum_x |A_x| |B_x| in antenna pairs. */
 matvis_status matvis_set_pairs(matvis_ctx *ctx, const int32_t *pair_a, const int32_t *pair_b, int32_t n_pair,
                                int32_t n_sub, int64_t *size_out);

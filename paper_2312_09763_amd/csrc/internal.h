@@ -247,8 +247,18 @@ struct SubmatArgs {
     int64_t ksplit;          // columns per k-split (multiple of 16)
     int32_t max_splits;
     void *part;              // [n_inst][max_splits][n_tiles][ST][ST] complex partials
+    // Z formed in the stages instead of read (launch_submat_fused, FP32 / BF16X3):
+    // Z[(a, p), (m, k)] = B[inst][beam(a)][p][k][m] F_a(m) from these inputs
+    const double *antc;      // [n_ant][3] centred ENU
+    const int32_t *bidx;     // [n_ant] sanitised beam index
+    const double *freqs;     // [n_freq]
+    const double *s_hat;     // [nslots][3][ld_src]
+    const void *B;           // sqrt(I) A (or A M), complex64 [n_inst][n_beam][n_feed][n_ax][ld_src]
+    int64_t ld_src;
+    int32_t n_feed, n_beam, f0;
 };
 hipError_t launch_submat(int prec, const SubmatArgs &a, hipStream_t s);
+hipError_t launch_submat_fused(int prec, const SubmatArgs &a, hipStream_t s);
 struct SubmatReduceArgs {
     const void *part;
     int32_t n_tiles, max_splits, st;

@@ -64,6 +64,9 @@ struct HD : HG<PREC, HT<PREC>::ST> {};
 
 __device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
 // Items of instance i: nsplit_i * n_st, with K_i = n_ax * visible count.
 __device__ inline int64_t inst_k(const int32_t *count, int64_t fixed_k, int n_ax, int nfb, int i) {
     return count ? (int64_t)n_ax * count[i / nfb] : fixed_k;
@@ -440,6 +443,122 @@ __global__ void __launch_bounds__(256, 2) k_submat(SubmatArgs a) {
             }
 }
 
+// The same sub-matrix product with Z formed in the stages (FP32 and BF16X3):
+// every staged element of the tile's A and B rows is
+//   Z[(a, p), (m, k)] = B_{beam(a), p, k}(m) F_a(m),  F_a(m) = exp(-2 pi i nu x_a . s_m / c)
+// (Eq. littlez with B = sqrt(I) A from the beam step), the phase range-reduced
+// in FP64 and its sine and cosine taken on the hardware in revolutions, so Z
+// never goes through device memory.  Thread t stages row t / 4 (A rows, then
+// B rows) for four consecutive columns; the next stage's inputs are loaded
+// before the current stage's products and turned into Z after them.
+template <int PREC, int STS>
+__global__ void __launch_bounds__(256, 2) k_submat_fused(SubmatArgs a) {
+    typedef HG<PREC, STS> D;
+    constexpr int ST = D::ST, WT = D::WT, KC = D::KC, RS = D::RS, TI = D::TI;
+    static_assert(2 * ST * (KC / 4) == 256, "one thread per staged row and four columns");
+    __shared__ __attribute__((aligned(16))) unsigned char lds[D::LDS];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const int wr = wave >> 1, wc = wave & 1, l16 = lane & 15, lk = lane >> 4;
+    const int64_t item = blockIdx.x;
+    const int s = (int)(item % a.max_splits);
+    const int tile = (int)((item / a.max_splits) % a.n_tiles);
+    const int inst = (int)(item / ((int64_t)a.max_splits * a.n_tiles));
+    const int64_t K = inst_k(a.count, a.fixed_k, a.n_ax, a.nfb, inst);
+    const int64_t Kr = ((K + KC - 1) / KC) * KC;
+    const int64_t kb = (int64_t)s * a.ksplit;
+    if (kb >= Kr) return;  // an empty k-split: the reduction sums only ceil(K / ksplit) of them
+    const int64_t ke = kb + a.ksplit < Kr ? kb + a.ksplit : Kr;
+    const int nf = a.n_feed, nx = a.n_ax;
+    const int r = tid / (KC / 4), cq = tid % (KC / 4);  // staged row, column group
+    const int zrow = a.rows[(int64_t)tile * 2 * ST + r];  // a * n_feed + p, or -1
+    const int ant = zrow < 0 ? 0 : zrow / nf, p = zrow < 0 ? 0 : zrow % nf;
+    const int tslot = inst / a.nfb;
+    const double nu_c = a.freqs[a.f0 + inst % a.nfb] / kSpeedOfLight;
+    const double ux = nu_c * a.antc[3 * ant], uy = nu_c * a.antc[3 * ant + 1], uz = nu_c * a.antc[3 * ant + 2];
+    const double *sh = a.s_hat + (int64_t)tslot * 3 * a.ld_src;
+    const float2 *Bm = (const float2 *)a.B +
+                       ((((int64_t)inst * a.n_beam + a.bidx[ant]) * nf + p) * nx) * a.ld_src;  // [k][m], stride ld_src
+
+    typedef f32x4 Acc;
+    Acc acc_re[TI][TI], acc_im[TI][TI];
+    for (int i = 0; i < TI; i++)
+        for (int j = 0; j < TI; j++)
+            for (int e = 0; e < 4; e++) {
+                acc_re[i][j][e] = 0.f;
+                acc_im[i][j][e] = 0.f;
+            }
+    // inputs of this thread's four columns k0 + 4 cq + e: the source direction and its beam value
+    double sx[4], sy[4], sz[4];
+    float2 bv[4];
+    float2 z[4];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int64_t col = k0 + 4 * cq + e;
+            sx[e] = sy[e] = sz[e] = 0.0;
+            bv[e] = make_float2(0.f, 0.f);
+            if (zrow >= 0 && col < K) {
+                const int64_t m = col / nx;
+                sx[e] = sh[m];
+                sy[e] = sh[a.ld_src + m];
+                sz[e] = sh[2 * a.ld_src + m];
+                bv[e] = Bm[(col % nx) * a.ld_src + m];
+            }
+        }
+    };
+    auto form = [&]() {
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const double ph = ux * sx[e] + uy * sy[e] + uz * sz[e];
+            const float rr = (float)__builtin_amdgcn_fract(ph);
+            const float fi = __builtin_amdgcn_sinf(-rr), fr = __builtin_amdgcn_cosf(-rr);
+            z[e] = make_float2(bv[e].x * fr - bv[e].y * fi, bv[e].x * fi + bv[e].y * fr);
+        }
+    };
+    auto store = [&]() {
+        unsigned char *row = lds + r * RS;
+        if constexpr (PREC == PB3) {  // hi plane then lo plane, four bf16 pairs each
+            uint32_t h[4], l[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const f32x2_t zz = {z[e].x, z[e].y};
+                const bf16x2_t hh = __builtin_convertvector(zz, bf16x2_t);
+                const f32x2_t rem = zz - __builtin_convertvector(hh, f32x2_t);
+                const bf16x2_t ll = __builtin_convertvector(rem, bf16x2_t);
+                h[e] = __builtin_bit_cast(uint32_t, hh);
+                l[e] = __builtin_bit_cast(uint32_t, ll);
+            }
+            *(u32x4 *)(row + cq * 16) = u32x4{h[0], h[1], h[2], h[3]};
+            *(u32x4 *)(row + KC * 4 + cq * 16) = u32x4{l[0], l[1], l[2], l[3]};
+        } else {
+            *(float4 *)(row + cq * 32) = make_float4(z[0].x, z[0].y, z[1].x, z[1].y);
+            *(float4 *)(row + cq * 32 + 16) = make_float4(z[2].x, z[2].y, z[3].x, z[3].y);
+        }
+    };
+    const int arow = wr * WT, brow = ST + wc * WT;
+    load(kb);
+    form();
+    for (int64_t k0 = kb; k0 < ke; k0 += KC) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        const bool more = k0 + KC < ke;
+        if (more) load(k0 + KC);
+        mma_stage<PREC, D>(lds, arow, brow, l16, lk, PREC == PB3, acc_re, acc_im);
+        if (more) form();
+    }
+    float2 *P = (float2 *)a.part + (((int64_t)inst * a.max_splits + s) * a.n_tiles + tile) * ST * ST;
+#pragma unroll
+    for (int i = 0; i < TI; i++)
+#pragma unroll
+        for (int j = 0; j < TI; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int rr = arow + 16 * i + 4 * lk + e;
+                P[(int64_t)rr * ST + wc * WT + 16 * j + l16] = make_float2(acc_re[i][j][e], acc_im[i][j][e]);
+            }
+}
+
 // V of every requested pair: the k-split partials of its tile element summed in
 // FP64 in split order, earlier source chunks carried in vacc.
 template <int PREC>
@@ -566,6 +685,18 @@ hipError_t launch_submat(int prec, const SubmatArgs &a, hipStream_t s) {
         k_submat<P32, kSubmatTile><<<(unsigned)items, 256, 0, s>>>(a);
     else if (prec == PB3)
         k_submat<PB3, kSubmatTile><<<(unsigned)items, 256, 0, s>>>(a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_submat_fused(int prec, const SubmatArgs &a, hipStream_t s) {
+    const int64_t items = (int64_t)a.n_inst * a.n_tiles * a.max_splits;
+    if (items <= 0) return hipSuccess;
+    if (prec == P32)
+        k_submat_fused<P32, kSubmatTile><<<(unsigned)items, 256, 0, s>>>(a);
+    else if (prec == PB3)
+        k_submat_fused<PB3, kSubmatTile><<<(unsigned)items, 256, 0, s>>>(a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -479,7 +479,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 ha.grid = c->herk_grid;
                 if (!pairs) STEP(c, MATVIS_STEP_OTHER, s, launch_worklist(prec, ha, c->fused ? 1 : 0, s));
 
-                if (c->fused) {
+                if (c->fused && !pairs) {
                     FusedArgs fa{};
                     fa.antc = c->antc;
                     fa.bidx = c->bidx;
@@ -550,7 +550,20 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                     sa.ksplit = c->ksplit;
                     sa.max_splits = c->max_splits;
                     sa.part = c->pr_part;
-                    STEP(c, MATVIS_STEP_HERK, s, launch_submat(prec, sa, s));
+                    if (c->fused) {  // Z formed in the stages from B = sqrt(I) A and the fringe phase
+                        sa.antc = c->antc;
+                        sa.bidx = c->bidx;
+                        sa.freqs = freqs;
+                        sa.s_hat = c->s_hat;
+                        sa.B = c->A;
+                        sa.ld_src = c->chunk;
+                        sa.n_feed = g.n_feed;
+                        sa.n_beam = g.n_beam;
+                        sa.f0 = f0;
+                        STEP(c, MATVIS_STEP_HERK, s, launch_submat_fused(prec, sa, s));
+                    } else {
+                        STEP(c, MATVIS_STEP_HERK, s, launch_submat(prec, sa, s));
+                    }
                     SubmatReduceArgs sr{};
                     sr.part = c->pr_part;
                     sr.n_tiles = c->pr_tiles;
@@ -694,9 +707,6 @@ matvis_status matvis_set_pairs(matvis_ctx *c, const int32_t *pair_a, const int32
     c->err.clear();
     const matvis_config &g = c->cfg;
     if (!pair_a || !pair_b || n_pair <= 0 || n_sub <= 0) return fail(c, MATVIS_EINVAL, "need pairs and n_sub >= 1");
-    if (c->fused)
-        return fail(c, MATVIS_EUNSUPPORTED,
-                    "the sub-matrix product reads Z from device memory: FP64, or MATVIS_FLAG_UNFUSED");
     for (int u = 0; u < n_pair; u++)
         if (pair_a[u] < 0 || pair_a[u] >= g.n_ant || pair_b[u] < 0 || pair_b[u] >= g.n_ant)
             return fail(c, MATVIS_EINVAL, "pair antenna outside [0, n_ant)");

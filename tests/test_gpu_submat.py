@@ -1,10 +1,11 @@
 """Redundancy-aware sub-matrix product (App. A, Eq. Vpx) on the GPU.
 
 matvis_simulate_pairs for the representatives of matvis_redundant_groups
-against the oracle's direct sum at those pairs, for FP64, FP32 and BF16X3 (Z in
-device memory), one to three sub-matrices, a polarised beam and sky, and
-sources in several chunks; plus the equality with matvis_simulate at the same
-pairs and, physically, between the members of one redundant group.
+against the oracle's direct sum at those pairs, for FP64, FP32 and BF16X3 with
+Z in device memory and for FP32 and BF16X3 with Z formed in the product's
+stages, one to three sub-matrices, a polarised beam and sky, and sources in
+several chunks; plus the equality with matvis_simulate at the same pairs and,
+physically, between the members of one redundant group.
 """
 import numpy as np
 import pytest
@@ -28,8 +29,8 @@ def _err(V, ref, reps):
     return float((np.abs(V - ref).max(axis=(1, 2, 3)) / scale).max())
 
 
-def _run_pairs(wl, precision, reps, n_sub, stokes=None, **kw):
-    unfused = precision != "fp64"
+def _run_pairs(wl, precision, reps, n_sub, stokes=None, fused=False, **kw):
+    unfused = precision != "fp64" and not fused
     cfg = mv.config_for(wl, precision, unfused=unfused, polarised_sky=stokes is not None, **kw)
     d = mv.device_inputs(wl, precision, stokes=stokes)
     with mv.Context(cfg) as ctx:
@@ -43,19 +44,21 @@ def _run_pairs(wl, precision, reps, n_sub, stokes=None, **kw):
     return out.reshape((-1,) + out.shape[2:]), full.reshape((-1,) + full.shape[2:]), size
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp32-fused", "bf16x3-fused"])
 @pytest.mark.parametrize("n_sub", [1, 2, 3])
 def test_pairs_match_oracle_and_full_product(precision, n_sub):
     wl = synth.workload(1, n_src=1500, n_time=2, n_freq=2)
     _, reps = mv.redundant_groups(wl.antpos, None, 1e-6)
-    V, full, size = _run_pairs(wl, precision, reps, n_sub)
+    fused = precision.endswith("-fused")
+    precision = precision.replace("-fused", "")
+    V, full, size = _run_pairs(wl, precision, reps, n_sub, fused=fused)
     ref = oracle.simulate_pairs(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, wl.flux, grid_as_used(wl, precision),
                                 wl.latitude, wl.dza, wl.daz, wl.interp,
                                 instances=[(t, f) for t in range(wl.n_time) for f in range(wl.n_freq)], pairs=reps)
     e = _err(V, ref, reps)
     a, b = np.array(reps).T
     ef = float(np.abs(V - full[:, a, b]).max() / np.abs(full).max())
-    say(f"{precision} n_sub={n_sub}: {len(reps)} unique of {wl.n_ant * (wl.n_ant + 1) // 2} pairs, "
+    say(f"{precision}{' fused' if fused else ''} n_sub={n_sub}: {len(reps)} unique of {wl.n_ant * (wl.n_ant + 1) // 2} pairs, "
         f"sub-matrix size {size} of {wl.n_ant ** 2}; error vs oracle {e:.2e}, vs the full product {ef:.2e}")
     assert e <= TOL[precision]
     assert ef <= {"fp64": 1e-13, "fp32": 2e-6, "bf16x3": 3e-5}[precision]
@@ -76,24 +79,24 @@ def test_redundant_pairs_are_equal():
     assert np.abs(Vp - Vr).max() <= 1e-10 * np.abs(V).max()
 
 
-def test_polarised_pairs_in_chunks():
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3-fused"])
+def test_polarised_pairs_in_chunks(precision):
     wl = synth.workload(2, n_ant=19, n_src=900, n_time=2, n_freq=2)
     st = synth.polarised_stokes(wl.flux, wl.freqs, seed=21)
     _, reps = mv.redundant_groups(wl.antpos, None, 1e-6)
-    V, full, _ = _run_pairs(wl, "fp64", reps, 2, stokes=st, src_chunk=256)
-    ref = oracle.simulate_pairs(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, st, wl.beam, wl.latitude, wl.dza, wl.daz,
-                                wl.interp, instances=[(t, f) for t in range(2) for f in range(2)], pairs=reps)
+    fused = precision.endswith("-fused")
+    precision = precision.replace("-fused", "")
+    V, full, _ = _run_pairs(wl, precision, reps, 2, stokes=st, src_chunk=256, fused=fused)
+    ref = oracle.simulate_pairs(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, st, grid_as_used(wl, precision),
+                                wl.latitude, wl.dza, wl.daz, wl.interp,
+                                instances=[(t, f) for t in range(2) for f in range(2)], pairs=reps)
     e = _err(V, ref, reps)
-    say(f"polarised sky, 2 feeds, sources in 4 chunks: error vs oracle {e:.2e}")
-    assert e <= TOL["fp64"]
+    say(f"polarised sky {precision}{' fused' if fused else ''}, 2 feeds, sources in 4 chunks: error vs oracle {e:.2e}")
+    assert e <= TOL[precision]
 
 
-def test_plan_needs_z_in_device_memory_and_simulate_needs_a_plan():
+def test_simulate_pairs_needs_a_plan():
     wl = synth.workload(1, n_ant=7, n_src=50, n_time=1, n_freq=1)
-    with mv.Context(mv.config_for(wl, "fp32")) as ctx:   # fused: Z never reaches device memory
-        with pytest.raises(mv.MatvisError) as e:
-            ctx.set_pairs([(0, 1)], 1)
-        assert e.value.status == mv.EUNSUPPORTED
     with mv.Context(mv.config_for(wl, "fp64")) as ctx:
         with pytest.raises(mv.MatvisError) as e:
             ctx._n_pairs = 1
