@@ -525,15 +525,17 @@ struct RowGeom {
 typedef RowGeom<FL<PB3>::RS, FL<PB3>::PLANEB, kKC / 16> GeomPair;  // 32 complex per stage
 typedef RowGeom<16 * 4 * 2 + 16, 16 * 4, 1> GeomCoh;               // 16 complex per stage
 
-// Off-diagonal block: rows 16 (rb + i), columns 16 (cb + j), i, j < 4.
-template <typename L, int NACC>
+// Off-diagonal block: rows 16 (rb + i), columns 16 (cb + j), i < NR, j < NC
+// (4 x 4 tiles, or 3 x 3 on a short diagonal block); tile (i, j) accumulates
+// in slot i * kTI + j.
+template <typename L, int NACC, int NR = kTI, int NC = kTI>
 __device__ __forceinline__ void consume_sq_b3(const unsigned char *buf, int rb, int cb, int l16, int lk,
                                               f32x4 (&re)[NACC], f32x4 (&im)[NACC]) {
 #pragma unroll
     for (int ks = 0; ks < L::NKS; ks++) {
-        u32x4 ah[kTI], al[kTI];
+        u32x4 ah[NR], al[NR];
 #pragma unroll
-        for (int i = 0; i < kTI; i++) {
+        for (int i = 0; i < NR; i++) {
             const unsigned char *p = buf + (16 * (rb + i) + l16) * L::RS + ks * 64 + lk * 16;
             ah[i] = *(const u32x4 *)p;
             al[i] = *(const u32x4 *)(p + L::PLANEB);
@@ -541,9 +543,9 @@ __device__ __forceinline__ void consume_sq_b3(const unsigned char *buf, int rb, 
         const unsigned char *pc = buf + (16 * cb + l16) * L::RS + ks * 64 + lk * 16;
         u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
 #pragma unroll
-        for (int j = 0; j < kTI; j++) {
+        for (int j = 0; j < NC; j++) {
             const u32x4 bh = nh, bl = nl;
-            if (j + 1 < kTI) {
+            if (j + 1 < NC) {
                 const unsigned char *p = pc + 16 * (j + 1) * L::RS;
                 nh = *(const u32x4 *)p;
                 nl = *(const u32x4 *)(p + L::PLANEB);
@@ -551,13 +553,13 @@ __device__ __forceinline__ void consume_sq_b3(const unsigned char *buf, int rb, 
             __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this column's products
             const u32x4 wh = bf16_rot_col(bh), wl = bf16_rot_col(bl);
             // one product term for every row before the next, so that MFMAs into the
-            // same accumulator are eight issues apart
+            // same accumulator are 2 NR issues apart
 #pragma unroll
-            for (int i = 0; i < kTI; i++) mfma_pair(ah[i], bh, wh, re[i * kTI + j], im[i * kTI + j]);
+            for (int i = 0; i < NR; i++) mfma_pair(ah[i], bh, wh, re[i * kTI + j], im[i * kTI + j]);
 #pragma unroll
-            for (int i = 0; i < kTI; i++) mfma_pair(ah[i], bl, wl, re[i * kTI + j], im[i * kTI + j]);
+            for (int i = 0; i < NR; i++) mfma_pair(ah[i], bl, wl, re[i * kTI + j], im[i * kTI + j]);
 #pragma unroll
-            for (int i = 0; i < kTI; i++) mfma_pair(al[i], bh, wh, re[i * kTI + j], im[i * kTI + j]);
+            for (int i = 0; i < NR; i++) mfma_pair(al[i], bh, wh, re[i * kTI + j], im[i * kTI + j]);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -599,6 +601,31 @@ struct TriPair {
         return p >= ncol ? -1 : slot(order[p]) < 0 ? p : next_loaded(p + 1);
     }
 };
+
+// Row sets of the triangle waves on a short diagonal block of at most 96
+// antennas (six tile rows): {5, 0, 3} (eleven tiles) and {4, 1, 2} (ten).
+template <int S>
+struct TriSet6 {
+    static constexpr int NR = 3;
+    static constexpr int r[3] = {S == 0 ? 5 : 4, S == 0 ? 0 : 1, S == 0 ? 3 : 2};
+    static constexpr int base[3] = {0, r[0] + 1, r[0] + r[1] + 2};
+    static constexpr int ncol = S == 0 ? 6 : 5;
+    static constexpr int order[6] = {S == 0 ? 0 : 1, S == 0 ? 1 : 0, S == 0 ? 3 : 2,
+                                     S == 0 ? 2 : 3, S == 0 ? 5 : 4, S == 0 ? 4 : -1};
+    static constexpr int slot(int c) { return r[0] == c ? 0 : r[1] == c ? 1 : r[2] == c ? 2 : -1; }
+    static constexpr int next_loaded(int p) {
+        return p >= ncol ? -1 : slot(order[p]) < 0 ? p : next_loaded(p + 1);
+    }
+};
+
+// Calls f(slot, row, column) for every tile of a triangle row set.
+template <typename T, typename F>
+__device__ __forceinline__ void for_tri_tiles(F f) {
+#pragma unroll
+    for (int k = 0; k < T::NR; k++)
+#pragma unroll
+        for (int c = 0; c <= T::r[k]; c++) f(T::base[k] + c, T::r[k], c);
+}
 
 // One 128-row diagonal triangle starting at LDS row o: tiles (r, c), c <= r, r in the set.
 template <typename L, typename T, int NACC>
@@ -660,26 +687,26 @@ __device__ __forceinline__ void consume_tri_b3(const unsigned char *buf, int o, 
 // complex64 per element, re/im interleaved): per 4-deep k group,
 // re += a.re b.re + a.im b.im and im += a.im b.re - a.re b.im on
 // v_mfma_f32_16x16x4f32, one complex element per lane.
-template <typename L, int NACC>
+template <typename L, int NACC, int NR = kTI, int NC = kTI>
 __device__ __forceinline__ void consume_sq_f32(const unsigned char *buf, int rb, int cb, int l16, int lk,
                                                f32x4 (&re)[NACC], f32x4 (&im)[NACC]) {
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
-        float2 av[kTI], bv[kTI];
+        float2 av[NR], bv[NC];
 #pragma unroll
-        for (int i = 0; i < kTI; i++) av[i] = *(const float2 *)(buf + (16 * (rb + i) + l16) * L::RS + (kk + lk) * 8);
+        for (int i = 0; i < NR; i++) av[i] = *(const float2 *)(buf + (16 * (rb + i) + l16) * L::RS + (kk + lk) * 8);
 #pragma unroll
-        for (int j = 0; j < kTI; j++) bv[j] = *(const float2 *)(buf + (16 * (cb + j) + l16) * L::RS + (kk + lk) * 8);
+        for (int j = 0; j < NC; j++) bv[j] = *(const float2 *)(buf + (16 * (cb + j) + l16) * L::RS + (kk + lk) * 8);
 #pragma unroll
-        for (int i = 0; i < kTI; i++) {
+        for (int i = 0; i < NR; i++) {
             const float nre = -av[i].x;
 #pragma unroll
-            for (int j = 0; j < kTI; j++) {
+            for (int j = 0; j < NC; j++) {
                 re[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, re[i * kTI + j], 0, 0, 0);
                 im[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].x, im[i * kTI + j], 0, 0, 0);
             }
 #pragma unroll
-            for (int j = 0; j < kTI; j++) {
+            for (int j = 0; j < NC; j++) {
                 re[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, re[i * kTI + j], 0, 0, 0);
                 im[i * kTI + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nre, bv[j].y, im[i * kTI + j], 0, 0, 0);
             }
@@ -966,7 +993,7 @@ struct CohSrc {
     float lx, ly;    // C10 / sqrt C00 (all four 0 past the split)
 };
 
-template <int PREC, bool OFF, int SQ_ANT = 96>
+template <int PREC, bool OFF, int SQ_ANT = 96, bool SHORT = false>
 __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
     typedef GeomCoh L;  // 144-byte rows: hi + lo bf16 planes, or one complex64 plane (FP32)
     constexpr int RS = L::RS;
@@ -993,7 +1020,13 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
     // and V^11_IJ = P1_I P1_J^H; kind Y, V^10_IJ = L_I P0_J^H and V^10_JI =
     // L_J P0_I^H (the conjugate of the (0, 1) entries).
     const int nb = Np / (2 * kST);
-    const int n_kind = OFF ? nb * (nb - 1) : nb;
+    // A last diagonal block of at most 96 antennas (a short block) has a launch of
+    // its own (SHORT): six tile rows, the square waves 3 x 3 tiles of V^10 each and
+    // the triangle waves the row sets of TriSet6; its square waves form 64
+    // antennas and its triangle waves 32.  The other launch skips that block.
+    constexpr bool short_blk = SHORT;
+    const bool has_short = !OFF && a.n_ant - (nb - 1) * kST <= 96;
+    const int n_kind = OFF ? nb * (nb - 1) : SHORT ? 1 : has_short ? nb - 1 : nb;
     const int total = a.work[a.n_inst] * n_kind;
     const int per_xcd = a.grid / 8;
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -1004,6 +1037,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
     // square waves: V^10 rows 16 (sq_rb + i) of L against 16 (sq_cb + j) of P0 (block units)
     const int sq_r0 = 4 * (wave >> 1), sq_c0 = 4 * (wave & 1);
     const int sq_rb = 2 * 8 + sq_r0, sq_cb = sq_c0;
+    const int sh_r0 = 3 * (wave >> 1), sh_c0 = 3 * (wave & 1);  // short diagonal block: 3 x 3 tiles
     // triangle waves: plane T (V^TT), row set S
     const int tri_t = (wave - 4) >> 1, tri_s = (wave - 4) & 1;
     const int tri_o = tri_t * kST;
@@ -1023,7 +1057,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
         const int kind = local % n_kind;
         constexpr bool off = OFF;
         const bool kind_y = off && (kind & 1);
-        int I = kind, J = kind;
+        int I = SHORT ? nb - 1 : kind, J = I;
         if (off) {  // pairs (1, 0), (2, 0), (2, 1), (3, 0), ...
             int q = kind >> 1;
             I = 1;
@@ -1100,7 +1134,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
         // The three planes of this thread's two sources for its NA antennas.  No
         // masks: a source past the split has zero coherency factors, and rows of
         // padding antennas (u = 0) only reach outputs that are never stored.
-        auto produce_n = [&](unsigned char *buf, int stage, auto na) {
+        auto produce_n = [&](unsigned char *buf, int stage, auto na, int a0) {
             constexpr int NA = decltype(na)::value;
             CohSrc w[2];
             w[0] = src[stage & 1][2 * mp];
@@ -1197,10 +1231,14 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
         auto produce = [&](unsigned char *buf, int stage) {
             if constexpr (OFF)
                 produce_off(buf, stage);
+            else if (short_blk && sq)
+                produce_n(buf, stage, std::integral_constant<int, 2>{}, tid / (SPS / 2));
+            else if (short_blk)
+                produce_n(buf, stage, std::integral_constant<int, 1>{}, 64 + (tid - 256) / (SPS / 2));
             else if (sq)
-                produce_n(buf, stage, std::integral_constant<int, SQ_ANT / 32>{});
+                produce_n(buf, stage, std::integral_constant<int, SQ_ANT / 32>{}, a0);
             else
-                produce_n(buf, stage, std::integral_constant<int, (kST - SQ_ANT) / 32>{});
+                produce_n(buf, stage, std::integral_constant<int, (kST - SQ_ANT) / 32>{}, a0);
         };
 
         constexpr int NACC = OFF ? 16 : 18;
@@ -1221,14 +1259,26 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
                 else
                     consume_sq_f32<L>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im);
             } else if constexpr (PREC == PB3) {
-                if (sq)
+                if (short_blk && sq)
+                    consume_sq_b3<L, NACC, 3, 3>(buf, 16 + sh_r0, sh_c0, l16, lk, acc_re, acc_im);
+                else if (short_blk && tri_s == 0)
+                    consume_tri_b3<L, TriSet6<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else if (short_blk)
+                    consume_tri_b3<L, TriSet6<1>>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else if (sq)
                     consume_sq_b3<L>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
                 else if (tri_s == 0)
                     consume_tri_b3<L, TriSet<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
                 else
                     consume_tri_b3<L, TriSet<1>>(buf, tri_o, l16, lk, acc_re, acc_im);
             } else {
-                if (sq)
+                if (short_blk && sq)
+                    consume_sq_f32<L, NACC, 3, 3>(buf, 16 + sh_r0, sh_c0, l16, lk, acc_re, acc_im);
+                else if (short_blk && tri_s == 0)
+                    consume_tri_f32<L, TriSet6<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else if (short_blk)
+                    consume_tri_f32<L, TriSet6<1>>(buf, tri_o, l16, lk, acc_re, acc_im);
+                else if (sq)
                     consume_sq_f32<L>(buf, sq_rb, sq_cb, l16, lk, acc_re, acc_im);
                 else if (tri_s == 0)
                     consume_tri_f32<L, TriSet<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
@@ -1283,36 +1333,42 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
                             P[(int64_t)(2 * Bc) * ld + 2 * A + 1] = make_float2(vr, -vi);
                     }
         } else if (sq) {
+            // V^10 tile (R, C) of the block from slot i * kTI + j
+            const int nt = short_blk ? 3 : kTI, r0 = short_blk ? sh_r0 : sq_r0, c0 = short_blk ? sh_c0 : sq_c0;
 #pragma unroll
             for (int i = 0; i < kTI; i++)
 #pragma unroll
                 for (int j = 0; j < kTI; j++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        const int ra = I * kST + 16 * (sq_r0 + i) + 4 * lk + e, cb = I * kST + 16 * (sq_c0 + j) + l16;
+                        const int ra = I * kST + 16 * (r0 + i) + 4 * lk + e, cb = I * kST + 16 * (c0 + j) + l16;
                         const float vr = acc_re[i * kTI + j][e], vi = acc_im[i * kTI + j][e];
-                        if (ra >= a.n_ant || cb >= a.n_ant) continue;
+                        if (i >= nt || j >= nt || ra >= a.n_ant || cb >= a.n_ant) continue;
                         if (ra >= cb)
                             P[(int64_t)(2 * ra + 1) * ld + 2 * cb] = make_float2(vr, vi);
                         else
                             P[(int64_t)(2 * cb) * ld + 2 * ra + 1] = make_float2(vr, -vi);
                     }
         } else {
-            const int rows[4] = {tri_s == 0 ? 0 : 2, tri_s == 0 ? 7 : 5, tri_s == 0 ? 1 : 3, tri_s == 0 ? 6 : 4};
-#pragma unroll
-            for (int t = 0; t < 18; t++) {
-                int k = 0, b = 0;
-                while (t >= b + rows[k] + 1) {
-                    b += rows[k] + 1;
-                    k++;
-                }
-                const int R = rows[k], C = t - b;
+            // V^TT tile (R, C) of the block, R >= C, from its triangle slot
+            auto store = [&](int t, int R, int C) {
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
                     const int ra = I * kST + 16 * R + 4 * lk + e, cb = I * kST + 16 * C + l16;
                     if (ra >= a.n_ant || cb >= a.n_ant) continue;
                     P[(int64_t)(2 * ra + tri_t) * ld + 2 * cb + tri_t] = make_float2(acc_re[t][e], acc_im[t][e]);
                 }
+            };
+            if (short_blk) {
+                if (tri_s == 0)
+                    for_tri_tiles<TriSet6<0>>(store);
+                else
+                    for_tri_tiles<TriSet6<1>>(store);
+            } else {
+                if (tri_s == 0)
+                    for_tri_tiles<TriSet<0>>(store);
+                else
+                    for_tri_tiles<TriSet<1>>(store);
             }
         }
     }
@@ -1909,16 +1965,25 @@ hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s, int wh
     const int split = a.tile & 15;  // rows per stage formed by the square waves, in units of 32 (0: default)
     if (path == MATVIS_PATH_SOURCES) {
         if (first) {
+            // the full diagonal blocks, then a short last block (at most 96 antennas)
+            const int nb = a.n_rows_pad / (2 * kST);
+            const bool has_short = a.n_ant - (nb - 1) * kST <= 96;
             if (prec == PB3) {
-                if (split == 2)
-                    k_herk_coh<PB3, false, 64><<<a.grid, 512, 0, s>>>(a);
-                else
-                    k_herk_coh<PB3, false, 96><<<a.grid, 512, 0, s>>>(a);
+                if (nb > 1 || !has_short) {
+                    if (split == 2)
+                        k_herk_coh<PB3, false, 64><<<a.grid, 512, 0, s>>>(a);
+                    else
+                        k_herk_coh<PB3, false, 96><<<a.grid, 512, 0, s>>>(a);
+                }
+                if (has_short) k_herk_coh<PB3, false, 96, true><<<a.grid, 512, 0, s>>>(a);
             } else {
-                if (split == 2)
-                    k_herk_coh<P32, false, 64><<<a.grid, 512, 0, s>>>(a);
-                else
-                    k_herk_coh<P32, false, 96><<<a.grid, 512, 0, s>>>(a);
+                if (nb > 1 || !has_short) {
+                    if (split == 2)
+                        k_herk_coh<P32, false, 64><<<a.grid, 512, 0, s>>>(a);
+                    else
+                        k_herk_coh<P32, false, 96><<<a.grid, 512, 0, s>>>(a);
+                }
+                if (has_short) k_herk_coh<P32, false, 96, true><<<a.grid, 512, 0, s>>>(a);
             }
         }
         if (pairs && a.n_rows_pad > 2 * kST) {  // pairs of antenna blocks
