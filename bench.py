@@ -194,7 +194,7 @@ def main():
     if args.train_epochs > 0:
         P, hist, _, _ = learned_beam.train(epochs=args.train_epochs)
     else:  # profiling runs only: the step's time does not depend on the weights
-        P, hist = torch.from_numpy(synth.surrogate_init(0, sigma_v=1.0, az_max=4, sigma_w=0.5)).cuda(), [float("nan")]
+        P, hist = torch.from_numpy(synth.surrogate_init(0, sigma_v=1.0, az_max=4)).cuda(), [float("nan")]
     train_s = time.perf_counter() - t0
     log(f"learned beam: {args.train_epochs} epochs of 2^20 samples, loss {hist[0]:.3e} -> {hist[-1]:.3e} "
         f"({train_s:.1f} s)")

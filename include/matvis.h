@@ -219,21 +219,27 @@ void matvis_destroy(matvis_ctx *ctx);
  *
  * The network maps normalised inputs x = (u, v, w) = (az / 2 pi,
  * za / (pi / 2), (nu - nu_min) / (nu_max - nu_min)) to the 2 x 2 complex
- * Jones matrix J[p][k] (8 reals: re, im of (0,0), (0,1), (1,0), (1,1)):
- *   phi = (sin 2 pi Bff x, cos 2 pi Bff x)      Bff [128][3], integer az
+ * Jones matrix J[p][k] (8 reals o = 0..7: re, im of (0,0), (0,1), (1,0), (1,1)):
+ *   phi = (sin 2 pi Bff (u, v), cos 2 pi Bff (u, v))   Bff [128][2], integer az
  *                                               column (features periodic in az)
- *   h1 = SiLU(W1 phi + b1), h2..h4 = SiLU(W h + b) (width 128), out = W5 h4 + b5.
+ *   h1 = SiLU(W1 phi + b1), h2..h4 = SiLU(W h + b) (width 128),
+ *   g = W5 h4 + b5 [64],  out_o = sum_{k<8} T_k(2 w - 1) g[8 o + k]
+ * (T_k Chebyshev polynomials of the first kind): the direction enters through
+ * the network, the frequency through a degree-7 series per output, so the
+ * simulator evaluates the network once per source and time and sums the
+ * series for every channel.
  * Parameters are one FP32 device vector of MATVIS_MLP_N_PARAMS floats in the
  * order Bff, W1, b1, W2, b2, W3, b3, W4, b4, W5, b5 (row-major weights
  * [out][in]).  The four hidden-layer products round both operands to bf16
- * and accumulate in FP32; features, biases, SiLU and the head (W5, b5) are
- * FP32.  The Fourier matrix is fixed (its gradient is zero and Adam leaves
- * it).
+ * and accumulate in FP32; features, biases, SiLU and the series are FP32;
+ * the head (W5, b5) is FP32 in training and split hi / lo into three bf16
+ * products in inference.  The Fourier matrix is fixed (its gradient is zero
+ * and Adam leaves it).
  * All arrays are device arrays; scalars and loss histories are host values.
  * ------------------------------------------------------------------------- */
-#define MATVIS_MLP_N_PARAMS 83848
+#define MATVIS_MLP_N_PARAMS 90944
 
-/* out [n][8] = network(x [n][3]).  Allocates a bf16 copy of the weights.
+/* out [n][8] = network(x [n][3]), each row at its own w.  Allocates a bf16 copy of the weights.
  * params and out must be 16-byte aligned (MATVIS_EINVAL otherwise). */
 matvis_status matvis_mlp_forward(const float *params, const float *x, int64_t n, float *out, void *stream);
 
@@ -248,7 +254,7 @@ matvis_status matvis_mlp_loss_grad(const float *params, const float *x, const fl
  * allocate (code under HIP graph capture, tight training loops, harnesses that
  * forbid hipMalloc).  Same arguments, kernels and results as
  * matvis_mlp_loss_grad, but the activation workspace is a fixed array of the
- * library's (32 MB of device memory, held on every GPU the library runs on
+ * library's (34 MB of device memory, held on every GPU the library runs on
  * until the process ends), so n is limited to 4096 rows: larger n returns
  * MATVIS_EINVAL with a message on stderr.  No hipMalloc, hipFree or memset
  * node is issued.  Asynchronous on `stream` (it does not synchronise).

@@ -7,14 +7,18 @@ The learned beam is not part of the paper: it stands in for the beam step of
 Alg. 2 (Sec. 3.4 gives the beam's role, a complex 2 x 2 Jones matrix per
 direction and channel).  The network, as the library documents it:
 
-    x   = (az / 2 pi, za / (pi / 2), (nu - nu_min) / (nu_max - nu_min))
-    phi = (sin 2 pi B x, cos 2 pi B x)                  B [128][3], fixed
+    x   = (u, v, w) = (az / 2 pi, za / (pi / 2), (nu - nu_min) / (nu_max - nu_min))
+    phi = (sin 2 pi B (u, v), cos 2 pi B (u, v))        B [128][2], fixed
     h1  = SiLU(W1 phi + b1); h_{l+1} = SiLU(W_{l+1} h_l + b_{l+1}), l = 1..3
-    out = W5 h4 + b5 = (re, im) of J[0][0], J[0][1], J[1][0], J[1][1]
+    g   = W5 h4 + b5                                     [64] = 8 outputs x 8 coefficients
+    out_o = sum_k T_k(2 w - 1) g[8 o + k],  o = 0..7     (re, im) of J[0][0], J[0][1], J[1][0], J[1][1]
 
-with SiLU(z) = z / (1 + e^-z) and the loss L = mean over rows and the 8
-outputs of (out - y)^2.  The parameter vector stores B, W1, b1, ..., W5, b5
-in that order, weights row-major [out][in].
+with T_k the Chebyshev polynomials of the first kind (T_0 = 1, T_1 = t,
+T_{k+1} = 2 t T_k - T_{k-1}): the direction enters through the features and
+the frequency only through a degree-7 polynomial per output.  SiLU(z) =
+z / (1 + e^-z); the loss L = mean over rows and the 8 outputs of
+(out - y)^2.  The parameter vector stores B, W1, b1, ..., W5, b5 in that
+order, weights row-major [out][in].
 
 ``forward`` is the definition in float64; with ``bf16=True`` the operands of
 the four hidden-layer products (features, activations, W1..W4) are first
@@ -29,10 +33,11 @@ import math
 
 import numpy as np
 
-N_FREQ, N_FEAT, N_HID, N_OUT = 128, 256, 128, 8
-_SHAPES = (("B", (N_FREQ, 3)), ("W1", (N_HID, N_FEAT)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
-           ("W3", (N_HID, N_HID)), ("b3", (N_HID,)), ("W4", (N_HID, N_HID)), ("b4", (N_HID,)), ("W5", (N_OUT, N_HID)),
-           ("b5", (N_OUT,)))
+N_FREQ, N_FEAT, N_HID, N_OUT, N_BASIS = 128, 256, 128, 8, 8
+N_NET = N_OUT * N_BASIS  # network outputs: the basis coefficients of every output
+_SHAPES = (("B", (N_FREQ, 2)), ("W1", (N_HID, N_FEAT)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
+           ("W3", (N_HID, N_HID)), ("b3", (N_HID,)), ("W4", (N_HID, N_HID)), ("b4", (N_HID,)), ("W5", (N_NET, N_HID)),
+           ("b5", (N_NET,)))
 N_PARAMS = sum(int(np.prod(s)) for _, s in _SHAPES)
 
 
@@ -80,13 +85,30 @@ def _silu(z):
 
 
 def features(P: dict, x) -> np.ndarray:
-    """phi [n][256]: sines then cosines of 2 pi B x."""
-    arg = 2.0 * math.pi * (np.asarray(x, dtype=np.float64) @ P["B"].T)
+    """phi [n][256]: sines then cosines of 2 pi B (u, v)."""
+    arg = 2.0 * math.pi * (np.asarray(x, dtype=np.float64)[:, :2] @ P["B"].T)
     return np.concatenate([np.sin(arg), np.cos(arg)], axis=1)
 
 
+def chebyshev(x) -> np.ndarray:
+    """T [n][N_BASIS]: T_k(2 w - 1) of the frequency input w = x[:, 2], by the three-term recurrence."""
+    t = 2.0 * np.asarray(x, dtype=np.float64)[:, 2] - 1.0
+    T = np.empty((t.shape[0], N_BASIS))
+    T[:, 0] = 1.0
+    T[:, 1] = t
+    for k in range(2, N_BASIS):
+        T[:, k] = 2.0 * t * T[:, k - 1] - T[:, k - 2]
+    return T
+
+
+def combine(g, x) -> np.ndarray:
+    """out [n][8]: out_o = sum_k T_k(2 w - 1) g[8 o + k]."""
+    g = np.asarray(g, dtype=np.float64).reshape(-1, N_OUT, N_BASIS)
+    return np.einsum("nok,nk->no", g, chebyshev(x))
+
+
 def forward(p, x, bf16: bool = False, keep: bool = False):
-    """Network outputs [n][8] (and, with keep, the pre-activations and activations)."""
+    """Network outputs [n][8] (and, with keep, the coefficients g, the pre-activations and activations)."""
     P = unpack(p)
     r = round_bf16 if bf16 else (lambda a: a)
     h = features(P, x)
@@ -96,8 +118,9 @@ def forward(p, x, bf16: bool = False, keep: bool = False):
         h = _silu(z)
         zs.append(z)
         hs.append(h)
-    out = h @ P["W5"].T + P["b5"]
-    return (out, zs, hs) if keep else out
+    g = h @ P["W5"].T + P["b5"]
+    out = combine(g, x)
+    return (out, g, zs, hs) if keep else out
 
 
 def loss(p, x, y, bf16: bool = False) -> float:
@@ -109,15 +132,16 @@ def loss_grad(p, x, y):
     """(gradient [N_PARAMS], loss) of the float64 network; B gets a zero gradient (it is not trained)."""
     P = unpack(p)
     y = np.asarray(y, dtype=np.float64)
-    out, zs, hs = forward(p, x, keep=True)
+    out, _, zs, hs = forward(p, x, keep=True)
     n = out.shape[0]
     d = out - y
     L = float(np.mean(d * d))
     g = {"B": np.zeros_like(P["B"])}
     dout = 2.0 * d / (N_OUT * n)            # dL/dout
-    g["W5"] = dout.T @ hs[4]
-    g["b5"] = dout.sum(axis=0)
-    dh = dout @ P["W5"]                     # dL/dh4
+    dg = (dout[:, :, None] * chebyshev(x)[:, None, :]).reshape(n, N_NET)  # dL/dg[8 o + k] = T_k dL/dout_o
+    g["W5"] = dg.T @ hs[4]
+    g["b5"] = dg.sum(axis=0)
+    dh = dg @ P["W5"]                       # dL/dh4
     for l in range(4, 0, -1):
         z = zs[l - 1]
         s = 1.0 / (1.0 + np.exp(-z))
@@ -132,11 +156,11 @@ def adam_step(p, g, m1, m2, step: int, lr: float, b1: float = 0.9, b2: float = 0
     """One Adam update (Kingma and Ba, 2015, Algorithm 1) of every trained parameter.
 
     m1 and m2 (first and second moments) are updated in place; returns the new
-    parameter vector.  The Fourier matrix B (the first 384 entries) is fixed.
+    parameter vector.  The Fourier matrix B (the first 256 entries) is fixed.
     """
     p = np.array(p, dtype=np.float64)
     g = np.asarray(g, dtype=np.float64)
-    t = slice(N_FREQ * 3, None)
+    t = slice(N_FREQ * 2, None)
     m1[t] = b1 * m1[t] + (1.0 - b1) * g[t]
     m2[t] = b2 * m2[t] + (1.0 - b2) * g[t] * g[t]
     mh = m1[t] / (1.0 - b1 ** step)

@@ -10,9 +10,10 @@
 // Inference (k_mlp_infer) is one persistent launch: every workgroup holds
 // the bf16 hidden weights in LDS and each wave runs the whole network on 64
 // points at a time with the activations in registers, so only the inputs and
-// the 8 outputs touch HBM.  In the
-// simulator it replaces beam interpolation: it reads the visible sources'
-// (za, az) and writes B = sqrt(I) J in the layout of the beam step.
+// the outputs touch HBM.  In the simulator it replaces beam interpolation:
+// it reads the visible sources' (za, az) of one time, evaluates the network
+// once, and writes B = sqrt(I) J of every channel of the batch (the
+// Chebyshev sums of the frequency head) in the layout of the beam step.
 #include <algorithm>
 
 #include "beam_interp.h"
@@ -40,8 +41,8 @@ __global__ void k_features(const float *__restrict__ x, int64_t n, const float *
     if (idx >= n * kFreq) return;
     const int64_t m = idx / kFreq;
     const int j = (int)(idx % kFreq);
-    const float *b = P + kOffBff + 3 * j;
-    const float arg = b[0] * x[3 * m] + b[1] * x[3 * m + 1] + b[2] * x[3 * m + 2];
+    const float *b = P + kOffBff + kBffCols * j;
+    const float arg = b[0] * x[3 * m] + b[1] * x[3 * m + 1];
     float s, c;
     sincos_rev(arg, s, c);
     phi[m * kFeat + j] = s;
@@ -149,15 +150,37 @@ __global__ void k_silu_bwd(const float *__restrict__ dH, const float *__restrict
     dZ[i] = dH[i] * s * (1.0f + z * (1.0f - s));
 }
 
-// Mean squared error over n x 8 outputs: dOut = 2 (out - y) / (8 n); per-block partial sums of squares.
-__global__ void __launch_bounds__(256) k_loss_grad(const float *__restrict__ out, const float *__restrict__ y,
-                                                   int64_t n, float *__restrict__ dout, float *__restrict__ part) {
+// T_0..T_{kBasis-1} of the first kind at t (three-term recurrence)
+__device__ inline void chebyshev(float t, float (&T)[kBasis]) {
+    T[0] = 1.0f;
+    T[1] = t;
+#pragma unroll
+    for (int k = 2; k < kBasis; k++) T[k] = 2.0f * t * T[k - 1] - T[k - 2];
+}
+
+// One thread per (row m, output o): out = sum_k T_k(2 w - 1) net[m][8 o + k]
+// with w = x[m][2]; mean squared error over n x 8 outputs, dnet = T_k dOut with
+// dOut = 2 (out - y) / (8 n); per-block partial sums of squares.
+__global__ void __launch_bounds__(256) k_loss_grad(const float *__restrict__ net, const float *__restrict__ x,
+                                                   const float *__restrict__ y, int64_t n, float *__restrict__ dnet,
+                                                   float *__restrict__ part) {
     __shared__ float red[256];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float sq = 0.f;
     if (i < n * kOut) {
-        const float d = out[i] - y[i];
-        dout[i] = 2.0f * d / (float)(kOut * n);
+        const int64_t m = i / kOut;
+        const int o = (int)(i % kOut);
+        float T[kBasis];
+        chebyshev(2.0f * x[3 * m + 2] - 1.0f, T);
+        const float *g = net + m * kNet + o * kBasis;
+        float out = 0.f;
+#pragma unroll
+        for (int k = 0; k < kBasis; k++) out += T[k] * g[k];
+        const float d = out - y[i];
+        const float dout = 2.0f * d / (float)(kOut * n);
+        float *dg = dnet + m * kNet + o * kBasis;
+#pragma unroll
+        for (int k = 0; k < kBasis; k++) dg[k] = T[k] * dout;
         sq = d * d;
     }
     red[threadIdx.x] = sq;
@@ -276,12 +299,19 @@ __global__ void k_beam_samples(const float2 *__restrict__ grid, int n_feed, int 
 // 32 kb + {4 lk .. 4 lk + 3, 16 + 4 lk .. 16 + 4 lk + 3}, and the LDS image
 // of the next layer's weights permutes its columns the same way, so no
 // activation ever leaves the registers.  The image of W1..W4 (160 KB, bf16,
-// built by pack_weights) is resident in LDS for the whole persistent launch;
-// the head (W5, b5) runs in FP32 on v_mfma_f32_16x16x4f32.
+// built by pack_weights) is resident in LDS for the whole persistent launch.
+// The head takes hi and lo bf16 parts of W5 (from device memory) and of the
+// last activations, three products accumulating in FP32 (the lo lo term,
+// about 2^-16 of the product, is dropped): its accumulator tile (rt, pt)
+// holds coefficient rows 16 rt + 4 lk + e = 8 o + k, i.e. output
+// o = 2 rt + lk / 2 and terms k = 4 (lk & 1) + e, so a lane's partial basis
+// sum plus its partner's (lane ^ 16) is output o.
 constexpr int kBlk = 512;                                    // bf16 per 1 KB operand block
 constexpr int kImgW1Blocks = (kHid / 16) * (kFeat / 32);     // 64: block h * 8 + kb
 constexpr int kImgLayerBlocks = (kHid / 16) * (kHid / 32);   // 32 per layer 2..4: block h * 4 + kb
 static_assert((int64_t)(kImgW1Blocks + 3 * kImgLayerBlocks) * kBlk == mlp::kWbElems, "image covers W1..W4");
+constexpr int kImgW5Blocks = (kNet / 16) * (kHid / 32) * 2;  // 32: (row tile, k block, hi / lo)
+static_assert((int64_t)kImgW5Blocks * kBlk == mlp::kW5Elems, "image covers W5 hi and lo");
 constexpr int kIPts = 64;    // points per wave task
 constexpr int kIWaves = 8;   // waves per workgroup (two per SIMD)
 
@@ -292,7 +322,18 @@ __device__ __host__ inline int image_col(bool first, int kb, int lk, int e) {
 
 __global__ void k_pack_image(const float *__restrict__ P, __bf16 *__restrict__ img) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int)mlp::kWbElems) return;
+    if (i >= (int)mlp::kImgElems) return;
+    if (i >= (int)mlp::kWbElems) {
+        // W5 hi / lo: block (rt * 4 + kb) * 2 + plane holds rows 16 rt + l16, the
+        // columns of k block kb in the order of the hidden layers' operands
+        const int j = i - (int)mlp::kWbElems;
+        const int blk = j / kBlk, r = j % kBlk, L = r / 8, e = r % 8, l16 = L & 15, lk = L >> 4;
+        const int plane = blk & 1, kb = (blk >> 1) & 3, rt = blk >> 3;
+        const float w = P[kOffW5 + (int64_t)(16 * rt + l16) * kHid + image_col(false, kb, lk, e)];
+        const __bf16 hi = (__bf16)w;
+        img[i] = plane ? (__bf16)(w - (float)hi) : hi;
+        return;
+    }
     const int blk = i / kBlk, r = i % kBlk, L = r / 8, e = r % 8, l16 = L & 15, lk = L >> 4;
     int h, kb, K, col;
     const float *W;
@@ -316,13 +357,14 @@ __global__ void k_pack_image(const float *__restrict__ P, __bf16 *__restrict__ i
 // SiLU with the hardware reciprocal (one rounding more than the division)
 __device__ inline float silu_fast(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
-__device__ inline bf16x8 lds_block(const __bf16 *img, int blk, int lane) {
-    return *(const bf16x8 *)(img + blk * kBlk + lane * 8);
+// operand block blk of the LDS image; loff = this lane's byte offset (lane * 16)
+__device__ inline bf16x8 lds_block(const __bf16 *img, int blk, int loff) {
+    return *(const bf16x8 *)((const char *)img + loff + blk * kBlk * 2);
 }
 
 // Hidden layer 2..4 (image blocks from blk0): out = SiLU(W in + b) as B operands.
 __device__ inline void hidden_layer(const __bf16 *img, int blk0, const float *__restrict__ b, const bf16x8 (&in)[4][4],
-                                    bf16x8 (&out)[4][4], int lane, int lk) {
+                                    bf16x8 (&out)[4][4], int loff, int lk) {
 #pragma unroll
     for (int hh = 0; hh < 2; hh++) {
         f32x4 acc[4][4];
@@ -336,7 +378,7 @@ __device__ inline void hidden_layer(const __bf16 *img, int blk0, const float *__
         for (int kb = 0; kb < 4; kb++)
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                const bf16x8 w = lds_block(img, blk0 + (4 * hh + i) * 4 + kb, lane);
+                const bf16x8 w = lds_block(img, blk0 + (4 * hh + i) * 4 + kb, loff);
 #pragma unroll
                 for (int pt = 0; pt < 4; pt++)
                     acc[i][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, in[kb][pt], acc[i][pt], 0, 0, 0);
@@ -351,11 +393,11 @@ __device__ inline void hidden_layer(const __bf16 *img, int blk0, const float *__
 }
 
 struct InferArgs {
-    const float *P;        // FP32 parameters (Fourier matrix, biases, output layer)
-    const __bf16 *Wb;      // LDS image of the bf16 W1..W4 (pack_weights)
+    const float *P;        // FP32 parameters (Fourier matrix, biases)
+    const __bf16 *Wb;      // image: bf16 W1..W4 (copied to LDS), then W5 hi / lo
     double nu0, nu1;
     int64_t n_tasks;       // 64-point tasks
-    int64_t tiles;         // simulator mode: tasks per instance
+    int64_t tiles;         // simulator mode: tasks per time of the batch
     // plain mode: x [n][3] normalised inputs, out [n][8]
     const float *x;
     float *out;
@@ -375,6 +417,21 @@ struct InferArgs {
     Batch bt;
 };
 
+// J[p][0], J[p][1] (re, im each; p = lk, valid in lanes lk < 2) of point 16 pt + l16
+// from the head accumulators and this lane's four basis values Tl[e] = T_{4 (lk & 1) + e}.
+__device__ inline f32x4 basis_sum(const f32x4 (&D)[4][2], int pt, const float (&Tl)[4], int lk) {
+    float s[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) {
+        float v = Tl[0] * D[rt][pt][0];
+#pragma unroll
+        for (int e = 1; e < 4; e++) v += Tl[e] * D[rt][pt][e];
+        s[rt] = v + __shfl_xor(v, 16);  // output 2 rt + lk / 2
+    }
+    const float a = (lk & 1) ? s[2] : s[0], b = (lk & 1) ? s[3] : s[1];  // re parts in lanes lk < 2
+    return f32x4{a, __shfl_xor(a, 32), b, __shfl_xor(b, 32)};
+}
+
 template <bool SIM>
 __global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
     __shared__ __attribute__((aligned(16))) __bf16 img[mlp::kWbElems];
@@ -387,13 +444,11 @@ __global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
     const int64_t nw = (int64_t)gridDim.x * kIWaves;
 #pragma unroll 1
     for (int64_t t = (int64_t)blockIdx.x * kIWaves + wave; t < a.n_tasks; t += nw) {
-        int inst = 0, slot = 0, f = 0;
+        int slot = 0;
         int64_t m0, nrow;
-        if (SIM) {
-            inst = (int)(t / a.tiles);
+        if (SIM) {  // 64 visible sources of one time of the batch, every channel
+            slot = (int)(t / a.tiles);
             m0 = (t % a.tiles) * kIPts;
-            slot = inst / a.bt.nfb;
-            f = a.bt.f0 + inst % a.bt.nfb;
             nrow = a.count[slot];
             if (m0 >= nrow) continue;
         } else {
@@ -404,6 +459,12 @@ __global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
         // they would pin ~160 registers, so the pointer is made opaque here.
         const float *P = a.P;
         asm volatile("" : "+s"(P));
+        // The same for the operand addresses: LDS blocks at loff + 1 KB blk, W5
+        // blocks from w5: formed where they are read, not held across the loop.
+        int loff = lane * 16;
+        asm volatile("" : "+v"(loff));
+        const __bf16 *w5 = a.Wb + mlp::kWbElems;
+        asm volatile("" : "+s"(w5));
         // inputs of this lane's four points (16 pt + l16)
         float xu[4], xv[4], xw[4];
 #pragma unroll
@@ -414,9 +475,8 @@ __global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
                 if (SIM) {
                     const double za = a.za_az[(int64_t)slot * 2 * a.ld_src + m];
                     const double az = a.za_az[(int64_t)slot * 2 * a.ld_src + a.ld_src + m];
-                    xu[pt] = (float)(az / (2.0 * M_PI));
-                    xv[pt] = (float)(za / (0.5 * M_PI));
-                    xw[pt] = (float)((a.freqs[f] - a.nu0) / (a.nu1 - a.nu0));
+                    xu[pt] = (float)(az * (0.5 / M_PI));
+                    xv[pt] = (float)(za * (2.0 / M_PI));
                 } else {
                     xu[pt] = a.x[3 * m];
                     xv[pt] = a.x[3 * m + 1];
@@ -434,10 +494,10 @@ __global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
         }
 #pragma unroll 1
         for (int kb = 0; kb < 4; kb++) {
-            float bf[24];
-            const f32x4 *bsrc = (const f32x4 *)(P + kOffBff + 3 * (32 * kb + 8 * lk));
+            float bf[16];
+            const f32x4 *bsrc = (const f32x4 *)(P + kOffBff + kBffCols * (32 * kb + 8 * lk));
 #pragma unroll
-            for (int q = 0; q < 6; q++) {
+            for (int q = 0; q < 4; q++) {
                 const f32x4 v = bsrc[q];
                 bf[4 * q] = v[0];
                 bf[4 * q + 1] = v[1];
@@ -450,13 +510,13 @@ __global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
 #pragma unroll
                 for (int e = 0; e < 8; e++) {
                     float s, c;
-                    sincos_rev(bf[3 * e] * xu[pt] + bf[3 * e + 1] * xv[pt] + bf[3 * e + 2] * xw[pt], s, c);
+                    sincos_rev(bf[2 * e] * xu[pt] + bf[2 * e + 1] * xv[pt], s, c);
                     S[pt][e] = (__bf16)s;
                     C[pt][e] = (__bf16)c;
                 }
 #pragma unroll
             for (int h = 0; h < 8; h++) {
-                const bf16x8 ws = lds_block(img, h * 8 + kb, lane), wc = lds_block(img, h * 8 + kb + 4, lane);
+                const bf16x8 ws = lds_block(img, h * 8 + kb, loff), wc = lds_block(img, h * 8 + kb + 4, loff);
 #pragma unroll
                 for (int pt = 0; pt < 4; pt++) {
                     acc1[h][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ws, S[pt], acc1[h][pt], 0, 0, 0);
@@ -471,61 +531,95 @@ __global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
             for (int pt = 0; pt < 4; pt++)
 #pragma unroll
                 for (int e = 0; e < 4; e++) hA[h / 2][pt][4 * (h % 2) + e] = (__bf16)silu_fast(acc1[h][pt][e]);
-        hidden_layer(img, kImgW1Blocks, P + kOffB2, hA, hB, lane, lk);
-        hidden_layer(img, kImgW1Blocks + kImgLayerBlocks, P + kOffB3, hB, hA, lane, lk);
-        // layer 4 in FP32 after SiLU, fed half by half to the FP32 head
-        f32x4 D[4];
-        {
-            const f32x4 b5 = lk < 2 ? *(const f32x4 *)(P + kOffB5 + 4 * lk) : f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int pt = 0; pt < 4; pt++) D[pt] = b5;
-        }
+        hidden_layer(img, kImgW1Blocks, P + kOffB2, hA, hB, loff, lk);
+        hidden_layer(img, kImgW1Blocks + kImgLayerBlocks, P + kOffB3, hB, hA, loff, lk);
+        // Layer 4, the head and the outputs for two point tiles at a time (points
+        // 16 (2 pp + j) + l16, j < 2), which keeps the head's accumulators in registers.
         const int blk4 = kImgW1Blocks + 2 * kImgLayerBlocks;
 #pragma unroll
-        for (int hh = 0; hh < 2; hh++) {
-            f32x4 acc[4][4];
+        for (int pp = 0; pp < 2; pp++) {
+            f32x4 acc[8][2];
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const f32x4 bv = *(const f32x4 *)(P + kOffB4 + 16 * (4 * hh + i) + 4 * lk);
+            for (int i = 0; i < 8; i++) {
+                const f32x4 bv = *(const f32x4 *)(P + kOffB4 + 16 * i + 4 * lk);
 #pragma unroll
-                for (int pt = 0; pt < 4; pt++) acc[i][pt] = bv;
+                for (int j = 0; j < 2; j++) acc[i][j] = bv;
             }
 #pragma unroll
             for (int kb = 0; kb < 4; kb++)
 #pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    const bf16x8 w = lds_block(img, blk4 + (4 * hh + i) * 4 + kb, lane);
+                for (int i = 0; i < 8; i++) {
+                    const bf16x8 w = lds_block(img, blk4 + i * 4 + kb, loff);
 #pragma unroll
-                    for (int pt = 0; pt < 4; pt++)
-                        acc[i][pt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, hA[kb][pt], acc[i][pt], 0, 0, 0);
+                    for (int j = 0; j < 2; j++)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, hA[kb][2 * pp + j], acc[i][j], 0, 0, 0);
                 }
+            f32x4 D[4][2];
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                // head operand: W5[o = l16][16 h + 4 lk + e] for k slot lk of block (h, e)
-                const int h = 4 * hh + i;
-                const f32x4 w5 = l16 < kOut ? *(const f32x4 *)(P + kOffW5 + l16 * kHid + 16 * h + 4 * lk)
-                                            : f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int rt = 0; rt < 4; rt++) {
+                const f32x4 b5 = *(const f32x4 *)(P + kOffB5 + 16 * rt + 4 * lk);
 #pragma unroll
-                for (int pt = 0; pt < 4; pt++)
-#pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        D[pt] = __builtin_amdgcn_mfma_f32_16x16x4f32(w5[e], silu_fast(acc[i][pt][e]), D[pt], 0, 0, 0);
+                for (int j = 0; j < 2; j++) D[rt][j] = b5;
             }
-        }
-        // outputs 4 lk + e (lk = 0, 1) of point 16 pt + l16: (re, im) of components 2 lk, 2 lk + 1
-        if (lk < 2) {
 #pragma unroll
-            for (int pt = 0; pt < 4; pt++) {
-                const int64_t m = m0 + 16 * pt + l16;
-                if (m >= nrow) continue;
-                if (SIM) {
+            for (int kb = 0; kb < 4; kb++) {  // head k block kb: unit tiles 2 kb, 2 kb + 1 after SiLU
+                bf16x8 sh[2], sl[2];
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+#pragma unroll
+                    for (int e = 0; e < 8; e++) {
+                        const float v = silu_fast(acc[2 * kb + e / 4][j][e % 4]);
+                        const __bf16 hi = (__bf16)v;
+                        sh[j][e] = hi;
+                        sl[j][e] = (__bf16)(v - (float)hi);
+                    }
+#pragma unroll
+                for (int rt = 0; rt < 4; rt++) {
+                    const bf16x8 wh = *(const bf16x8 *)(w5 + ((rt * 4 + kb) * 2) * kBlk + lane * 8);
+                    const bf16x8 wl = *(const bf16x8 *)(w5 + ((rt * 4 + kb) * 2 + 1) * kBlk + lane * 8);
+#pragma unroll
+                    for (int j = 0; j < 2; j++) {
+                        D[rt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, sh[j], D[rt][j], 0, 0, 0);
+                        D[rt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, sl[j], D[rt][j], 0, 0, 0);
+                        D[rt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, sh[j], D[rt][j], 0, 0, 0);
+                    }
+                }
+            }
+            if (!SIM) {
+                // each point at its own frequency
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    const int pt = 2 * pp + j;
+                    float T[kBasis], Tl[4];
+                    chebyshev(2.0f * xw[2 * pp + j] - 1.0f, T);
+#pragma unroll
+                    for (int e = 0; e < 4; e++) Tl[e] = (lk & 1) ? T[4 + e] : T[e];
+                    const f32x4 J = basis_sum(D, j, Tl, lk);
+                    const int64_t m = m0 + 16 * pt + l16;
+                    if (lk < 2 && m < nrow) *(f32x4 *)(a.out + m * kOut + 4 * lk) = J;
+                }
+                continue;
+            }
+            // every channel of the batch for this time
+#pragma unroll 1
+            for (int fi = 0; fi < a.bt.nfb; fi++) {
+                const int inst = slot * a.bt.nfb + fi, f = a.bt.f0 + fi;
+                float T[kBasis], Tl[4];
+                chebyshev((float)(2.0 * (a.freqs[f] - a.nu0) / (a.nu1 - a.nu0) - 1.0), T);
+#pragma unroll
+                for (int e = 0; e < 4; e++) Tl[e] = (lk & 1) ? T[4 + e] : T[e];
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    f32x4 J = basis_sum(D, j, Tl, lk);  // (re, im) of J[lk][0], J[lk][1]
+                    const int64_t m = m0 + 16 * (2 * pp + j) + l16;
+                    if (lk >= 2 || m >= nrow) continue;
                     float sq = 1.0f;
-                    f32x4 J = D[pt];  // (re, im) of J[lk][0], J[lk][1]
                     if (a.idx) {
                         const int64_t o = (int64_t)f * a.n_src + a.idx[(int64_t)slot * a.ld_src + m];
                         if (a.pol) {
                             const PolSqrt pm = pol_sqrt(a.flux[o], a.flux[o + a.stokes_stride],
-                                                        a.flux[o + 2 * a.stokes_stride], a.flux[o + 3 * a.stokes_stride]);
+                                                        a.flux[o + 2 * a.stokes_stride],
+                                                        a.flux[o + 3 * a.stokes_stride]);
                             float o0x, o0y, o1x, o1y;
                             apply_pol_sqrt<float>(pm, J[0], J[1], J[2], J[3], o0x, o0y, o1x, o1y);
                             J = f32x4{o0x, o0y, o1x, o1y};
@@ -542,8 +636,6 @@ __global__ void __launch_bounds__(kIWaves * kWave) k_mlp_infer(InferArgs a) {
                                           a.ld_src + m;
                         *dst = make_float2(sq * J[2 * cc], sq * J[2 * cc + 1]);
                     }
-                } else {
-                    *(f32x4 *)(a.out + m * kOut + 4 * lk) = D[pt];
                 }
             }
         }
@@ -607,9 +699,10 @@ hipError_t silu_bwd(const float *dH, const float *Z, float *dZ, int64_t n, hipSt
     return hipGetLastError();
 }
 
-hipError_t loss_grad(const float *out, const float *y, int64_t n, float *dout, float *part, float *loss, hipStream_t s) {
+hipError_t loss_grad(const float *net, const float *x, const float *y, int64_t n, float *dnet, float *part,
+                     float *loss, hipStream_t s) {
     const int nb = (int)((n * kOut + 255) / 256);
-    k_loss_grad<<<nb, 256, 0, s>>>(out, y, n, dout, part);
+    k_loss_grad<<<nb, 256, 0, s>>>(net, x, y, n, dnet, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_finish_loss<<<1, 64, 0, s>>>(part, nb, n, loss);
@@ -650,7 +743,7 @@ hipError_t to_bf16(const float *in, __bf16 *out, int64_t n, hipStream_t s) {
 }
 
 hipError_t pack_weights(const float *P, __bf16 *Wb, hipStream_t s) {
-    k_pack_image<<<(unsigned)((kWbElems + 255) / 256), 256, 0, s>>>(P, Wb);
+    k_pack_image<<<(unsigned)((kImgElems + 255) / 256), 256, 0, s>>>(P, Wb);
     return hipGetLastError();
 }
 
@@ -708,7 +801,7 @@ hipError_t infer_sim(const float *P, const __bf16 *Wb, double nu0, double nu1, c
     a.n_beam = n_beam;
     a.bt = bt;
     a.tiles = (max_m + kIPts - 1) / kIPts;
-    a.n_tasks = a.tiles * bt.n_inst;
+    a.n_tasks = a.tiles * bt.ntb;  // one task per 64 sources of one time: every channel of the batch
     k_mlp_infer<true><<<infer_grid(a.n_tasks), kIWaves * kWave, 0, s>>>(a);
     return hipGetLastError();
 }

@@ -348,7 +348,7 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
                                                                      cfg->n_feed * cfg->n_ax, cfg->n_za, cfg->n_az));
     if (cfg->beam_mode == MATVIS_BEAM_SURROGATE) {
         ALLOC(c->sur_P, sizeof(float) * kNParams * cfg->n_beam);
-        ALLOC(c->sur_Wb, sizeof(__bf16) * mlp::kWbElems * cfg->n_beam);
+        ALLOC(c->sur_Wb, sizeof(__bf16) * mlp::kImgElems * cfg->n_beam);
     }
 #undef ALLOC
     // Rows N..Np-1 of Z are never written by the kernels and must read as zero.
@@ -449,7 +449,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 if (g.beam_mode == MATVIS_BEAM_SURROGATE)
                     for (int b = 0; b < g.n_beam; b++)  // one network per unique beam
                         STEP(c, MATVIS_STEP_BEAM, s,
-                             mlp::infer_sim(c->sur_P + (size_t)b * kNParams, c->sur_Wb + (size_t)b * mlp::kWbElems,
+                             mlp::infer_sim(c->sur_P + (size_t)b * kNParams, c->sur_Wb + (size_t)b * mlp::kImgElems,
                                             c->sur_nu0, c->sur_nu1, c->za_az, c->count, ia.idx, flux, n_src, pol,
                                             ia.stokes_stride, freqs, c->chunk, ns, c->A, g.n_feed, g.n_ax, b,
                                             g.n_beam, bt, s));
@@ -804,7 +804,7 @@ matvis_status matvis_set_surrogate(matvis_ctx *c, const float *params, double nu
     c->graph_order.clear();
     HIPCHK(c, hipMemcpy(c->sur_P, params, sizeof(float) * kNParams * c->cfg.n_beam, hipMemcpyDeviceToDevice));
     for (int b = 0; b < c->cfg.n_beam; b++)
-        HIPCHK(c, mlp::pack_weights(c->sur_P + (size_t)b * kNParams, c->sur_Wb + (size_t)b * mlp::kWbElems, nullptr));
+        HIPCHK(c, mlp::pack_weights(c->sur_P + (size_t)b * kNParams, c->sur_Wb + (size_t)b * mlp::kImgElems, nullptr));
     HIPCHK(c, hipDeviceSynchronize());
     c->sur_nu0 = nu_min_hz;
     c->sur_nu1 = nu_max_hz;

@@ -46,8 +46,8 @@ struct Work {
         hipError_t e = one(phi, rows * kFeat);
         for (int l = 0; l < 4 && e == hipSuccess; l++) e = one(&Z[l], rows * kHid);
         for (int l = 0; l < 4 && e == hipSuccess; l++) e = one(&H[l], rows * kHid);
-        if (e == hipSuccess) e = one(out, rows * kOut);
-        if (e == hipSuccess) e = one(dout, rows * kOut);
+        if (e == hipSuccess) e = one(out, rows * kNet);   // network outputs (basis coefficients)
+        if (e == hipSuccess) e = one(dout, rows * kNet);
         if (e == hipSuccess) e = one(dH, rows * kHid);
         if (e == hipSuccess) e = one(dZ, rows * kHid);
         if (e == hipSuccess) e = one(part, (rows * kOut + 255) / 256 + 1);
@@ -110,16 +110,17 @@ hipError_t loss_grad_impl(const float *P, const float *x, const float *y, bool b
     for (int l = 1; l < 4; l++)
         RET(mlp::gemm(bf16, w.H[l - 1], kHid, 1, P + offW[l - 1], kHid, 1, ni, kHid, kHid, P + offB[l - 1], w.Z[l],
                       w.H[l], 1, w.ws, w.ws_elems, s));
-    // the linear head stays in FP32, as in inference
-    RET(mlp::gemm(false, w.H[3], kHid, 1, P + kOffW5, kHid, 1, ni, kOut, kHid, P + kOffB5, w.out, nullptr, 0,
+    // the linear head in FP32 (inference splits it hi / lo), then the Chebyshev
+    // sums of the frequency head and the squared error
+    RET(mlp::gemm(false, w.H[3], kHid, 1, P + kOffW5, kHid, 1, ni, kNet, kHid, P + kOffB5, w.out, nullptr, 0,
                   w.ws, w.ws_elems, s));
-    RET(mlp::loss_grad(w.out, y, n, w.dout, w.part, loss, s));
+    RET(mlp::loss_grad(w.out, x, y, n, w.dout, w.part, loss, s));
     RET(mlp::fill(grad, kOffW1, 0.f, s));  // the Fourier matrix is not trained
     // output layer
-    RET(mlp::gemm(false, w.dout, 1, kOut, w.H[3], 1, kHid, kOut, kHid, ni, nullptr, grad + kOffW5, nullptr, 0,
+    RET(mlp::gemm(false, w.dout, 1, kNet, w.H[3], 1, kHid, kNet, kHid, ni, nullptr, grad + kOffW5, nullptr, 0,
                   w.ws, w.ws_elems, s));
-    RET(mlp::colsum(w.dout, n, kOut, grad + kOffB5, w.ws, w.ws_elems, s));
-    RET(mlp::gemm(false, w.dout, kOut, 1, P + kOffW5, 1, kHid, ni, kHid, kOut, nullptr, w.dH, nullptr, 0,
+    RET(mlp::colsum(w.dout, n, kNet, grad + kOffB5, w.ws, w.ws_elems, s));
+    RET(mlp::gemm(false, w.dout, kNet, 1, P + kOffW5, 1, kHid, ni, kHid, kNet, nullptr, w.dH, nullptr, 0,
                   w.ws, w.ws_elems, s));
     // hidden layers 4..2
     const int64_t gW[4] = {kOffW1, kOffW2, kOffW3, kOffW4}, gB[4] = {kOffB1, kOffB2, kOffB3, kOffB4};
@@ -143,12 +144,12 @@ hipError_t loss_grad_impl(const float *P, const float *x, const float *y, bool b
 
 // ---- The allocation-free loss / gradient (matvis_mlp_loss_grad_noalloc) ----
 // Its workspace is one file-scope device array of kNoAllocRows rows' worth of
-// activations (31.7 MB), which every GPU the library runs on holds until the
+// activations (33.6 MB), which every GPU the library runs on holds until the
 // process ends.  Host code never uses the array's name as an address: its
 // device address is looked up once per device (hipGetSymbolAddress, with that
 // device current) and kept in noalloc_ptr.
 static constexpr int64_t kNoAllocRows = 4096;
-static constexpr int64_t kNoAllocFloats = 7930048;  // Work::floats_for(kNoAllocRows), checked below
+static constexpr int64_t kNoAllocFloats = 8388800;  // Work::floats_for(kNoAllocRows), checked below
 static __device__ __align__(256) float scratch[kNoAllocFloats];
 
 static constexpr int kMaxDevices = 64;
@@ -179,7 +180,7 @@ matvis_status matvis_mlp_forward(const float *params, const float *x, int64_t n,
     if (n == 0) return MATVIS_OK;
     hipStream_t s = (hipStream_t)stream;
     __bf16 *wb = nullptr;
-    CK(hipMalloc(&wb, sizeof(__bf16) * mlp::kWbElems));
+    CK(hipMalloc(&wb, sizeof(__bf16) * mlp::kImgElems));
     hipError_t e = mlp::pack_weights(params, wb, s);
     if (e == hipSuccess) e = mlp::infer_plain(params, wb, x, n, out, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -42,6 +42,6 @@ def train(epochs: int = 60, n_samples: int = 1 << 20, batch: int = 1024, seed: i
     grid = torch.from_numpy(np.ascontiguousarray(wl.beam[0], dtype=np.complex64)).cuda()
     freqs = torch.from_numpy(np.ascontiguousarray(wl.freqs, dtype=np.float64)).cuda()
     y, x = samples(wl, grid, freqs, n_samples, seed)
-    P = torch.from_numpy(synth.surrogate_init(0, sigma_v=1.0, az_max=4, sigma_w=0.5)).cuda()
+    P = torch.from_numpy(synth.surrogate_init(0, sigma_v=1.0, az_max=4)).cuda()
     hist = mv.train_surrogate(P, x, y, batch=batch, epochs=epochs, lr0=3e-3, lr1=3e-5, seed=seed)
     return P, hist, wl, grid

@@ -30,7 +30,7 @@ FLAG_POLARISED_SKY = 4
 STEPS = ("sky", "beam", "zform", "herk", "reduce", "other", "herk_pairs")
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 BEAM_MODES = {"bilinear": BILINEAR, "bicubic": BICUBIC, "surrogate": SURROGATE}
-MLP_N_PARAMS = 83848  # learned-beam parameter count (include/matvis.h)
+MLP_N_PARAMS = 90944  # learned-beam parameter count (include/matvis.h)
 PRODUCT_PATHS = ("z_in_hbm", "fused", "fused_rows", "sources", "fused_blocks")  # matvis_product_path
 
 

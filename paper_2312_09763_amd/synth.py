@@ -458,19 +458,18 @@ def workload(cfg: int, n_ant=None, n_src=None, n_time=None, n_freq=None, seed_sa
 # Learned beam: random draws only (initial parameters and sample points)
 # --------------------------------------------------------------------------
 # Parameter-vector order of the learned beam: (name, shape) in storage order.
-SURROGATE_LAYOUT = (("Bff", (128, 3)), ("W1", (128, 256)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)),
-                    ("W3", (128, 128)), ("b3", (128,)), ("W4", (128, 128)), ("b4", (128,)), ("W5", (8, 128)),
-                    ("b5", (8,)))
-SURROGATE_N_PARAMS = sum(int(np.prod(s)) for _, s in SURROGATE_LAYOUT)  # 83848
+SURROGATE_LAYOUT = (("Bff", (128, 2)), ("W1", (128, 256)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)),
+                    ("W3", (128, 128)), ("b3", (128,)), ("W4", (128, 128)), ("b4", (128,)), ("W5", (64, 128)),
+                    ("b5", (64,)))
+SURROGATE_N_PARAMS = sum(int(np.prod(s)) for _, s in SURROGATE_LAYOUT)  # 90944
 
 
-def surrogate_init(seed: int, az_max: int = 4, sigma_v: float = 2.0, sigma_w: float = 0.5) -> np.ndarray:
-    """Initial learned-beam parameters (float32 [83848]).
+def surrogate_init(seed: int, az_max: int = 4, sigma_v: float = 2.0) -> np.ndarray:
+    """Initial learned-beam parameters (float32 [90944]).
 
-    Fourier matrix rows (az, za, nu columns): integer az frequencies uniform in
-    [-az_max, az_max] (features periodic in az), N(0, sigma_v^2) and
-    N(0, sigma_w^2) for the za and nu columns.  Weights and biases of every
-    layer uniform in +-1 / sqrt(fan_in).
+    Fourier matrix rows (az, za columns): integer az frequencies uniform in
+    [-az_max, az_max] (features periodic in az) and N(0, sigma_v^2) for the za
+    column.  Weights and biases of every layer uniform in +-1 / sqrt(fan_in).
     """
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + 7000 + int(seed)))
     parts = []
@@ -479,7 +478,6 @@ def surrogate_init(seed: int, az_max: int = 4, sigma_v: float = 2.0, sigma_w: fl
             b = np.empty(shape)
             b[:, 0] = rng.integers(-az_max, az_max + 1, shape[0])
             b[:, 1] = rng.normal(0.0, sigma_v, shape[0])
-            b[:, 2] = rng.normal(0.0, sigma_w, shape[0])
             parts.append(b.ravel())
         else:
             fan_in = {"W1": 256, "b1": 256, "W5": 128, "b5": 128}.get(name, 128)

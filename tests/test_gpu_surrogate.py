@@ -122,11 +122,11 @@ def test_adam_matches_reference():
     r1, r2 = m1.astype(np.float64), m2.astype(np.float64)
     q = om.adam_step(p, g, r1, r2, 3, 1e-3)
     out = P.cpu().numpy()
-    assert np.array_equal(out[:384], p[:384])
+    assert np.array_equal(out[:256], p[:256])
     np.testing.assert_allclose(out, q, rtol=1e-6, atol=1e-7)
     # FP32 moment updates: a few ulp of the larger term (|g| <~ 5)
-    np.testing.assert_allclose(M1.cpu().numpy()[384:], r1[384:], rtol=1e-6, atol=3e-7)
-    np.testing.assert_allclose(M2.cpu().numpy()[384:], r2[384:], rtol=1e-6, atol=3e-7)
+    np.testing.assert_allclose(M1.cpu().numpy()[256:], r1[256:], rtol=1e-6, atol=3e-7)
+    np.testing.assert_allclose(M2.cpu().numpy()[256:], r2[256:], rtol=1e-6, atol=3e-7)
 
 
 @pytest.fixture(scope="module")
@@ -197,7 +197,7 @@ def test_training_reduces_loss_and_is_reproducible(dipole, p0):
     assert np.array_equal(runs[0][1], runs[1][1])
     h = runs[0][1]
     assert np.all(np.isfinite(h)) and h[-1] < 0.2 * h[0]
-    assert np.array_equal(runs[0][0][:384], p0[:384])  # the Fourier matrix is fixed
+    assert np.array_equal(runs[0][0][:256], p0[:256])  # the Fourier matrix is fixed
 
 
 def test_training_steps_match_reference_adam_loop(dipole, p0):

@@ -156,3 +156,31 @@ def test_workload5_learned_beam_against_interpolated(trained, size, request):
     ecs, ef = sampled_err_cs(Vh, wl, "bf16x3", instances, pairs)
     say(f"  learned beam vs FP64 oracle with the interpolated beam: sampled err_CS {ecs:.2e}, err_F {ef:.2e}")
     assert ecs <= 1e-3
+
+
+def test_learned_beam_step_within_twice_bicubic_on_workload5():
+    # the beam step alone, on the benchmark's sample of workload 5 (2 LSTs x 8
+    # channels, 3 145 728 pixels): the network runs once per (source, time) and its
+    # frequency series serves the 8 channels; the step's time does not depend on
+    # the weights, so an untrained network is timed
+    wl = synth.workload(5, n_time=2, n_freq=8)
+    d = mv.device_inputs(wl, "bf16x3")
+    P = torch.from_numpy(synth.surrogate_init(0)).cuda()
+    times = {}
+    for mode in ("bicubic", "surrogate"):
+        with mv.Context(mv.config_for(wl, "bf16x3", beam_mode=mode)) as ctx:
+            if mode == "surrogate":
+                ctx.set_surrogate(P, NU0, NU1)
+            vis = ctx.simulate(**d)
+            ctx.finish()
+            best = float("inf")
+            for _ in range(2):
+                ctx.profile(True)
+                ctx.simulate(**d, vis=vis)
+                best = min(best, ctx.profile_read()["beam"][0])
+                ctx.profile(False)
+                ctx.finish()
+            times[mode] = best
+            del vis
+    say(f"workload 5 beam step (16 instances): bicubic {times['bicubic']:.3f} ms, learned {times['surrogate']:.3f} ms")
+    assert times["surrogate"] <= 2.0 * times["bicubic"]

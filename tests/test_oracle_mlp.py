@@ -2,7 +2,8 @@
 
 The learned beam is not in the paper, so the pins are mathematical: central
 finite differences and an independent reverse-mode engine (torch autograd in
-float64) for the gradient, closed forms for degenerate networks, periodicity
+float64) for the gradient, closed forms for degenerate networks, the
+frequency head against numpy's Chebyshev series and hand values, periodicity
 in azimuth, and bfloat16 rounding against torch's own conversion and hand
 values.
 """
@@ -34,7 +35,7 @@ def _data(n, seed=1):
 
 
 def test_layout_size_matches_documented_count():
-    assert om.N_PARAMS == 83848
+    assert om.N_PARAMS == 90944
     assert synth.SURROGATE_N_PARAMS == om.N_PARAMS
 
 
@@ -45,8 +46,8 @@ def test_gradient_matches_central_differences():
     assert L == pytest.approx(om.loss(p, x, y), rel=1e-14)
     rng = np.random.Generator(np.random.PCG64(5))
     # a sample of parameters from every trained block (skip the fixed B)
-    idx = rng.choice(np.arange(384, om.N_PARAMS), 60, replace=False)
-    idx = np.concatenate([idx, [384, 384 + 128 * 256, om.N_PARAMS - 1, om.N_PARAMS - 9]])
+    idx = rng.choice(np.arange(256, om.N_PARAMS), 60, replace=False)
+    idx = np.concatenate([idx, [256, 256 + 128 * 256, om.N_PARAMS - 1, om.N_PARAMS - 9, om.N_PARAMS - 64 - 1]])
     for i in idx:
         h = 1e-5 * max(1.0, abs(p[i]))
         pp, pm = p.copy(), p.copy()
@@ -63,11 +64,15 @@ def test_gradient_matches_torch_autograd():
     P = om.unpack(p)
     T = {k: torch.tensor(v, dtype=torch.float64, requires_grad=(k != "B")) for k, v in P.items()}
     xt = torch.tensor(x)
-    arg = 2 * math.pi * xt @ T["B"].T
+    arg = 2 * math.pi * xt[:, :2] @ T["B"].T
     h = torch.cat([torch.sin(arg), torch.cos(arg)], dim=1)
     for l in range(1, 5):
         h = torch.nn.functional.silu(torch.nn.functional.linear(h, T[f"W{l}"], T[f"b{l}"]))
-    out = torch.nn.functional.linear(h, T["W5"], T["b5"])
+    coef = torch.nn.functional.linear(h, T["W5"], T["b5"]).reshape(-1, 8, 8)
+    # Chebyshev basis from the trigonometric definition T_k(cos th) = cos(k th)
+    th = torch.arccos(2 * xt[:, 2] - 1)
+    basis = torch.cos(torch.arange(8, dtype=torch.float64)[None, :] * th[:, None])
+    out = (coef * basis[:, None, :]).sum(dim=2)
     lt = torch.nn.functional.mse_loss(out, torch.tensor(y))
     lt.backward()
     assert L == pytest.approx(lt.item(), rel=1e-13)
@@ -80,32 +85,53 @@ def test_gradient_matches_torch_autograd():
 
 
 def test_zero_hidden_weights_closed_form():
-    # all weights zero: h_l = SiLU(b_l) whatever the input, out = W5 SiLU(b4) + b5
+    # all weights zero: h_l = SiLU(b_l) whatever the input, g = W5 SiLU(b4) + b5,
+    # and each output a Chebyshev series in 2 w - 1 with coefficients g[8 o .. 8 o + 7]
     P = {k: v.copy() for k, v in om.unpack(_params(1)).items()}
     for l in range(1, 5):
         P[f"W{l}"][:] = 0.0
     p = om.pack(P)
     x, _ = _data(7)
     b4 = P["b4"]
-    expect = P["W5"] @ (b4 / (1 + np.exp(-b4))) + P["b5"]
-    np.testing.assert_allclose(om.forward(p, x), np.broadcast_to(expect, (7, 8)), rtol=1e-14, atol=1e-15)
+    g = P["W5"] @ (b4 / (1 + np.exp(-b4))) + P["b5"]
+    expect = np.stack([np.polynomial.chebyshev.chebval(2 * x[:, 2] - 1, g[8 * o:8 * o + 8]) for o in range(8)],
+                      axis=1)
+    np.testing.assert_allclose(om.forward(p, x), expect, rtol=1e-13, atol=1e-14)
 
 
 def test_single_path_network():
-    # one feature -> one unit per layer -> one output: out = silu^4 applied to sin(2 pi b.x)
+    # one feature -> one unit per layer -> one output through the constant
+    # basis term (T_0 = 1): out = silu^4 applied to sin(2 pi (u + 0.3 v))
     P = {k: np.zeros_like(v) for k, v in om.unpack(_params(0)).items()}
-    P["B"][0] = [1.0, 0.3, -0.2]
+    P["B"][0] = [1.0, 0.3]
     P["W1"][5, 0] = 1.0
     for l in (2, 3, 4):
         P[f"W{l}"][5, 5] = 1.0
-    P["W5"][2, 5] = 1.0
+    P["W5"][8 * 2, 5] = 1.0
     x, _ = _data(9)
-    t = np.sin(2 * math.pi * (x[:, 0] + 0.3 * x[:, 1] - 0.2 * x[:, 2]))
+    t = np.sin(2 * math.pi * (x[:, 0] + 0.3 * x[:, 1]))
     for _ in range(4):
         t = t / (1 + np.exp(-t))
     out = om.forward(om.pack(P), x)
     np.testing.assert_allclose(out[:, 2], t, rtol=1e-14, atol=1e-15)
     assert np.all(out[:, [0, 1, 3, 4, 5, 6, 7]] == 0)
+
+
+def test_frequency_head_hand_values():
+    # g = b5 alone (all weights zero, h4 = SiLU(0) = 0): output o is the series
+    # sum_k b5[8 o + k] T_k(t), t = 2 w - 1; hand values at w = 0, 1/2, 3/4, 1
+    # (t = -1, 0, 1/2, 1) for T_2 = 2 t^2 - 1, T_3 = 4 t^3 - 3 t and T_7
+    P = {k: np.zeros_like(v) for k, v in om.unpack(_params(0)).items()}
+    P["b5"][8 * 0 + 2] = 1.0   # output 0: T_2
+    P["b5"][8 * 5 + 3] = -2.0  # output 5: -2 T_3
+    P["b5"][8 * 7 + 7] = 0.5   # output 7: T_7 / 2
+    x = np.array([[0.3, 0.4, 0.0], [0.1, 0.9, 0.5], [0.7, 0.2, 0.75], [0.5, 0.5, 1.0]])
+    out = om.forward(om.pack(P), x)
+    np.testing.assert_allclose(out[:, 0], [1.0, -1.0, -0.5, 1.0], atol=1e-15)
+    np.testing.assert_allclose(out[:, 5], [2.0, 0.0, 2.0, -2.0], atol=1e-15)
+    # T_7(cos th) = cos 7 th: t = 1/2 (th = pi / 3) gives cos(7 pi / 3) = 1/2
+    np.testing.assert_allclose(out[:, 7], [-0.5, 0.0, 0.25, 0.5], atol=1e-14)
+    assert np.all(out[:, [1, 2, 3, 4, 6]] == 0)
 
 
 def test_periodic_in_azimuth():
@@ -154,13 +180,13 @@ def test_adam_first_step_is_signed_learning_rate():
     g[1000] = 0.0
     m1, m2 = np.zeros(om.N_PARAMS), np.zeros(om.N_PARAMS)
     q = om.adam_step(p, g, m1, m2, 1, 1e-2)
-    np.testing.assert_array_equal(q[:384], p[:384])
-    d = (p - q)[384:]
-    gs = g[384:]
+    np.testing.assert_array_equal(q[:256], p[:256])
+    d = (p - q)[256:]
+    gs = g[256:]
     np.testing.assert_allclose(d, 1e-2 * gs / (np.abs(gs) + 1e-8), rtol=1e-12, atol=1e-18)
-    assert d[1000 - 384] == 0.0
+    assert d[1000 - 256] == 0.0
     # a constant gradient keeps the step at lr (bias correction exact)
     for t in range(2, 6):
         q2 = om.adam_step(q, g, m1, m2, t, 1e-2)
-        np.testing.assert_allclose((q - q2)[384:], 1e-2 * gs / (np.abs(gs) + 1e-8), rtol=1e-9, atol=1e-15)
+        np.testing.assert_allclose((q - q2)[256:], 1e-2 * gs / (np.abs(gs) + 1e-8), rtol=1e-9, atol=1e-15)
         q = q2
