@@ -125,8 +125,16 @@ struct InterpArgs {
     // Stokes plane s starts at flux + s * stokes_stride
     int32_t pol;
     int64_t stokes_stride;
+    // launch_interp_tf only, optional: scratch for each (slot, source)'s stencil,
+    // interp_stencil_bytes(prec, ld_src, nslots) bytes; null -> formed in the kernel
+    void *stencil;
 };
 hipError_t launch_interp(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s);
+// stencil scratch of launch_interp_tf: the packed (first row, first column) and
+// the 4 row and 4 column weights of every (slot, source), in the precision's real type
+inline size_t interp_stencil_bytes(int prec, int64_t ld_src, int nslots) {
+    return (size_t)nslots * ld_src * (4 + 8 * (prec == P64 ? 8 : 4));
+}
 // Channel-interleaved copy of the beam grids, T[b][za][az][f][c] (c = feed * n_ax + axis),
 // so one grid point's channels and components are one contiguous run; runs are
 // (n_freq * ncomp) rounded up to even long, and the buffer needs
@@ -137,8 +145,10 @@ inline int64_t grid_interleave_elems(int n_beam, int n_freq, int ncomp, int n_za
     return (int64_t)n_beam * n_za * n_az * ((n_freq * ncomp + 1) & ~1) + 4;
 }
 // The beam step on the interleaved grid: a.grid = T with a.n_freq_grid channels;
-// one thread per (visible source, time slot, group of 4 channels of the batch).
-// Needs n_za >= 4.
+// a group of lanes per (visible source, time slot, group of 4 channels of the
+// batch).  With a.stencil set, each (slot, source)'s stencil is formed once by
+// a pass of its own instead of by every lane of every group.  Needs n_za >= 4
+// and n_za, n_az < 65536.
 hipError_t launch_interp_tf(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s);
 
 // ---- Z formation (kernels_z.hip) -------------------------------------------

@@ -95,12 +95,65 @@ __device__ inline int za_rows_bicubic(int j0, int n_za, R t, R eff[4]) {
     return base;
 }
 
+// Stencil of a source on the grid: the first of its NT rows and columns (rows
+// folded at the za ends for bicubic, columns wrapped in az) and the row and
+// column weights.
+template <typename R, int MODE>
+__device__ inline void stencil(double za, double az, const InterpArgs &a, int &rbase, int &kstart, R (&wr)[4],
+                               R (&wc)[4]) {
+    const double u = za / a.dza, v = az / a.daz;
+    int j0 = (int)floor(u);
+    j0 = j0 < 0 ? 0 : (j0 > a.n_za - 2 ? a.n_za - 2 : j0);
+    const R t = (R)(u - j0);
+    const double kf = floor(v);
+    const R sfr = (R)(v - kf);
+    int k0 = (int)kf % a.n_az;
+    if (k0 < 0) k0 += a.n_az;
+    if (MODE == BILINEAR) {
+        rbase = j0;
+        wr[0] = R(1) - t;
+        wr[1] = t;
+        wc[0] = R(1) - sfr;
+        wc[1] = sfr;
+        wr[2] = wr[3] = wc[2] = wc[3] = R(0);
+        kstart = k0;
+    } else {
+        rbase = za_rows_bicubic<R>(j0, a.n_za, t, wr);
+        keys_weights<R>(sfr, wc);
+        kstart = k0 == 0 ? a.n_az - 1 : k0 - 1;
+    }
+}
+
+// One thread per (slot, visible source): the stencil into the scratch of
+// interp_stencil_bytes, packed (rbase << 16 | first column) then the weights
+// wr[0..3], wc[0..3] as planes of ld_src.
+template <typename R, int MODE>
+__global__ void __launch_bounds__(256) k_stencil(InterpArgs a, Batch bt) {
+    const int slot = blockIdx.y;
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t M = a.count ? a.count[slot] : a.fixed_count;
+    if (m >= M) return;
+    const int64_t ns = (int64_t)bt.ntb * a.ld_src;
+    int rbase, kstart;
+    R wr[4], wc[4];
+    stencil<R, MODE>(a.za_az[(int64_t)slot * 2 * a.ld_src + m], a.za_az[(int64_t)slot * 2 * a.ld_src + a.ld_src + m],
+                     a, rbase, kstart, wr, wc);
+    int32_t *rc = (int32_t *)a.stencil;
+    R *w = (R *)(rc + ns);
+    rc[(int64_t)slot * a.ld_src + m] = (rbase << 16) | kstart;
+    for (int j = 0; j < 4; j++) {
+        w[((int64_t)slot * 8 + j) * a.ld_src + m] = wr[j];
+        w[((int64_t)slot * 8 + 4 + j) * a.ld_src + m] = wc[j];
+    }
+}
+
 // A group of LPS lanes per (visible source, time slot of the batch, 4 channels
 // of the batch): a tap's interleaved run T[b][j][k][f .. f + 3][0 .. ncomp) is
 // 4 ncomp complex values, and lane l of the group reads its l-th 16-byte piece
 // (two complex64 or one complex128), so a wave's load covers whole runs of
-// 64 / LPS sources.  Every lane of the group forms the same stencil weights.
-template <typename R, int MODE, int NCOMP>
+// 64 / LPS sources.  The group reads the source's stencil from the scratch
+// k_stencil wrote (ST), or every lane forms it.
+template <typename R, int MODE, int NCOMP, bool ST>
 __global__ void __launch_bounds__(256) k_interp_tf(InterpArgs a, Batch bt) {
     typedef typename CplxOf<R>::T C;
     constexpr int FG = 4;                            // channels per group
@@ -110,48 +163,40 @@ __global__ void __launch_bounds__(256) k_interp_tf(InterpArgs a, Batch bt) {
     // so each XCD is given one contiguous range of (channel group, slot, source
     // block) work; neighbouring (sky-cell ordered) sources then share one L2 and
     // the grid lines they have in common are fetched into it once.
-    const int64_t gx = gridDim.x, gy = gridDim.y;
-    const int64_t total = gx * gy * gridDim.z;
-    const int64_t lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    const int64_t xq = total / 8, xr = total % 8, xcd = lin % 8;
-    const int64_t task = xcd * xq + (xcd < xr ? xcd : xr) + lin / 8;
-    const int64_t bx = task % gx;
+    const uint32_t gx = gridDim.x, gy = gridDim.y;
+    const uint32_t total = gx * gy * gridDim.z;
+    const uint32_t lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const uint32_t xq = total / 8, xr = total % 8, xcd = lin % 8;
+    const uint32_t task = xcd * xq + (xcd < xr ? xcd : xr) + lin / 8;
+    const uint32_t bx = task % gx;
     const int slot = (int)((task / gx) % gy);
     const int fg = (int)(task / (gx * gy)) * FG;    // first channel of the group, relative to the batch
     const int l = threadIdx.x % LPS;
-    const int64_t m = bx * (blockDim.x / LPS) + threadIdx.x / LPS;
+    const int64_t m = (int64_t)bx * (blockDim.x / LPS) + threadIdx.x / LPS;
     const int64_t M = a.count ? a.count[slot] : a.fixed_count;
     if (m >= M || fg >= bt.nfb) return;
     const int nf = bt.nfb - fg < FG ? bt.nfb - fg : FG;
-    const double za = a.za_az[(int64_t)slot * 2 * a.ld_src + m];
-    const double az = a.za_az[(int64_t)slot * 2 * a.ld_src + a.ld_src + m];
-    const double u = za / a.dza, v = az / a.daz;
-    int j0 = (int)floor(u);
-    j0 = j0 < 0 ? 0 : (j0 > a.n_za - 2 ? a.n_za - 2 : j0);
-    const R t = (R)(u - j0);
-    const double kf = floor(v);
-    const R sfr = (R)(v - kf);
-    int k0 = (int)kf % a.n_az;
-    if (k0 < 0) k0 += a.n_az;
     constexpr int NT = MODE == BILINEAR ? 2 : 4;
-    R wr[NT], wc[NT];
-    int rbase, kc[NT];
-    if (MODE == BILINEAR) {
-        rbase = j0;
-        wr[0] = R(1) - t;
-        wr[1] = t;
-        wc[0] = R(1) - sfr;
-        wc[1] = sfr;
-        kc[0] = k0;
-        kc[1] = k0 + 1 == a.n_az ? 0 : k0 + 1;
-    } else {
-        rbase = za_rows_bicubic<R>(j0, a.n_za, t, wr);
-        keys_weights<R>(sfr, wc);
-        for (int d = 0; d < 4; d++) {
-            const int k = k0 - 1 + d;
-            kc[d] = k < 0 ? k + a.n_az : (k >= a.n_az ? k - a.n_az : k);
+    R wr[4], wc[4];
+    int rbase, kstart;
+    if constexpr (ST) {
+        const int32_t *rc = (const int32_t *)a.stencil;
+        const R *w = (const R *)(rc + (int64_t)bt.ntb * a.ld_src);
+        const int32_t p = rc[(int64_t)slot * a.ld_src + m];
+        rbase = (int)((uint32_t)p >> 16);
+        kstart = p & 0xffff;
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+            wr[j] = w[((int64_t)slot * 8 + j) * a.ld_src + m];
+            wc[j] = w[((int64_t)slot * 8 + 4 + j) * a.ld_src + m];
         }
+    } else {
+        stencil<R, MODE>(a.za_az[(int64_t)slot * 2 * a.ld_src + m], a.za_az[(int64_t)slot * 2 * a.ld_src + a.ld_src + m],
+                         a, rbase, kstart, wr, wc);
     }
+    int kc[NT];
+#pragma unroll
+    for (int d = 0; d < NT; d++) kc[d] = kstart + d >= a.n_az ? kstart + d - a.n_az : kstart + d;
     const int F = (a.n_freq_grid * NCOMP + 1) & ~1;  // run stride of one grid point (all channels, even)
     const int fabs0 = bt.f0 + fg;
     // this lane's elements e = l PER + p of the group's run: channel q = e / NCOMP, component e % NCOMP
@@ -244,12 +289,22 @@ hipError_t launch_tf_mode(const InterpArgs &a, const Batch &bt, hipStream_t s) {
     const int sources_per_block = 256 / lps;
     dim3 g((unsigned)((a.max_m + sources_per_block - 1) / sources_per_block), bt.n_inst / bt.nfb,
            (unsigned)((bt.nfb + 3) / 4));
-    if (ncomp == 4)
-        k_interp_tf<R, MODE, 4><<<g, 256, 0, s>>>(a, bt);
-    else if (ncomp == 2)
-        k_interp_tf<R, MODE, 2><<<g, 256, 0, s>>>(a, bt);
-    else
-        k_interp_tf<R, MODE, 1><<<g, 256, 0, s>>>(a, bt);
+    if (a.stencil) {
+        k_stencil<R, MODE><<<dim3((unsigned)((a.max_m + 255) / 256), (unsigned)bt.ntb), 256, 0, s>>>(a, bt);
+        if (ncomp == 4)
+            k_interp_tf<R, MODE, 4, true><<<g, 256, 0, s>>>(a, bt);
+        else if (ncomp == 2)
+            k_interp_tf<R, MODE, 2, true><<<g, 256, 0, s>>>(a, bt);
+        else
+            k_interp_tf<R, MODE, 1, true><<<g, 256, 0, s>>>(a, bt);
+    } else {
+        if (ncomp == 4)
+            k_interp_tf<R, MODE, 4, false><<<g, 256, 0, s>>>(a, bt);
+        else if (ncomp == 2)
+            k_interp_tf<R, MODE, 2, false><<<g, 256, 0, s>>>(a, bt);
+        else
+            k_interp_tf<R, MODE, 1, false><<<g, 256, 0, s>>>(a, bt);
+    }
     return hipGetLastError();
 }
 
@@ -269,7 +324,7 @@ hipError_t launch_grid_interleave(int prec, const void *grid, int n_beam, int n_
 
 hipError_t launch_interp_tf(int prec, int mode, const InterpArgs &a, const Batch &bt, hipStream_t s) {
     if (bt.n_inst <= 0 || a.max_m <= 0) return hipSuccess;
-    if (a.n_za < 4) return hipErrorInvalidValue;
+    if (a.n_za < 4 || a.n_za >= 65536 || a.n_az >= 65536) return hipErrorInvalidValue;
     if (prec == P64)
         return mode == BILINEAR ? launch_tf_mode<double, BILINEAR>(a, bt, s) : launch_tf_mode<double, BICUBIC>(a, bt, s);
     return mode == BILINEAR ? launch_tf_mode<float, BILINEAR>(a, bt, s) : launch_tf_mode<float, BICUBIC>(a, bt, s);

@@ -78,6 +78,7 @@ struct matvis_ctx {
     float *sur_P = nullptr;     // FP32 parameters, one network per unique beam
     __bf16 *sur_Wb = nullptr;   // bf16 W1..W4 LDS images, one per beam
     void *gridT = nullptr;      // channel-interleaved beam grids (grid beam modes, n_za >= 4)
+    void *stencil = nullptr;    // per (slot, source) beam stencils of the batch (with gridT)
     double sur_nu0 = 0, sur_nu1 = 1;
     bool sur_set = false;
 
@@ -186,6 +187,7 @@ matvis_status validate_cfg(const matvis_config *c, std::string &why) {
             return why = "the learned beam runs with FP32 or BF16X3 products", MATVIS_EUNSUPPORTED;
     } else {
         if (c->n_za < 3 || c->n_az < 3) return why = "beam grid must be at least 3 x 3", MATVIS_EINVAL;
+        if (c->n_za >= 32768 || c->n_az >= 32768) return why = "beam grid must be below 32768 x 32768", MATVIS_EINVAL;
         if (!(c->dza_rad > 0) || !(c->daz_rad > 0)) return why = "grid spacings must be positive", MATVIS_EINVAL;
         if (std::fabs((c->n_za - 1) * c->dza_rad - M_PI / 2) > 1e-9)
             return why = "(n_za - 1) * dza_rad must equal pi/2 (za rows 0..90 deg)", MATVIS_EINVAL;
@@ -343,9 +345,11 @@ matvis_status matvis_init(const matvis_config *cfg, matvis_ctx **out) {
     ALLOC(c->part, cbytes(prec) * B * (size_t)c->max_splits * c->Np * c->Np);
     if (c->chunk < cfg->max_src) ALLOC(c->vacc, sizeof(double) * 2 * B * (size_t)c->N * c->N);
     ALLOC(c->work, sizeof(int32_t) * (3 * B + 1));  // item prefix, then k-splits and columns per split
-    if (cfg->beam_mode != MATVIS_BEAM_SURROGATE && cfg->n_za >= 4)
+    if (cfg->beam_mode != MATVIS_BEAM_SURROGATE && cfg->n_za >= 4) {
         ALLOC(c->gridT, cbytes(prec) * (size_t)grid_interleave_elems(cfg->n_beam, cfg->max_freq,
                                                                      cfg->n_feed * cfg->n_ax, cfg->n_za, cfg->n_az));
+        ALLOC(c->stencil, interp_stencil_bytes(prec, c->chunk, c->ntb));
+    }
     if (cfg->beam_mode == MATVIS_BEAM_SURROGATE) {
         ALLOC(c->sur_P, sizeof(float) * kNParams * cfg->n_beam);
         ALLOC(c->sur_Wb, sizeof(__bf16) * mlp::kImgElems * cfg->n_beam);
@@ -433,6 +437,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 ia.dza = g.dza_rad;
                 ia.daz = g.daz_rad;
                 ia.za_az = c->za_az;
+                ia.stencil = c->stencil;
                 ia.count = c->count;
                 ia.ld_src = c->chunk;
                 ia.A = c->A;
