@@ -89,6 +89,7 @@ struct matvis_ctx {
     int32_t *pr_rows = nullptr;  // [tiles][2][ST] Z rows
     int32_t *pr_loc = nullptr;   // [n_pair][nf][nf][2]
     void *pr_part = nullptr;     // [B_cap][max_splits][tiles][ST][ST]
+    void *pr_Z = nullptr, *pr_Z_lo = nullptr;  // fused contexts: Z of a batch for the pairs, when it fits
     double *pr_vacc = nullptr;   // [B_cap][n_pair][nf][nf] complex128
 };
 
@@ -538,12 +539,19 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                 if (!c->fused) {
                     STEP(c, MATVIS_STEP_ZFORM, s, launch_zform(prec, za, bt, s));
                     if (!pairs) STEP(c, MATVIS_STEP_HERK, s, launch_herk(prec, ha, s));
+                } else if (pairs && c->pr_Z) {
+                    // the pairs of a fused context with room for a batch of Z: form Z once
+                    // (B already carries the sky) rather than once per sub-matrix tile
+                    za.flux = nullptr;
+                    za.Z = c->pr_Z;
+                    za.Z_lo = c->pr_Z_lo;
+                    STEP(c, MATVIS_STEP_ZFORM, s, launch_zform(prec, za, bt, s));
                 }
                 if (pairs) {
                     // App. A: only the planned sub-matrices, then the requested pairs
                     SubmatArgs sa{};
-                    sa.Z = c->Z;
-                    sa.Z_lo = c->Z_lo;
+                    sa.Z = c->fused ? c->pr_Z : c->Z;
+                    sa.Z_lo = c->fused ? c->pr_Z_lo : c->Z_lo;
                     sa.ldz = c->ldz;
                     sa.inst_stride = (int64_t)c->Np * c->ldz;
                     sa.rows = c->pr_rows;
@@ -555,7 +563,7 @@ matvis_status enqueue_simulate(matvis_ctx *c, const double *antpos, const int32_
                     sa.ksplit = c->ksplit;
                     sa.max_splits = c->max_splits;
                     sa.part = c->pr_part;
-                    if (c->fused) {  // Z formed in the stages from B = sqrt(I) A and the fringe phase
+                    if (c->fused && !c->pr_Z) {  // Z formed in the stages from B = sqrt(I) A and the fringe phase
                         sa.antc = c->antc;
                         sa.bidx = c->bidx;
                         sa.freqs = freqs;
@@ -765,7 +773,7 @@ matvis_status matvis_set_pairs(matvis_ctx *c, const int32_t *pair_a, const int32
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     c->graph_order.clear();
-    for (void *q : {(void *)c->pr_rows, (void *)c->pr_loc, c->pr_part, (void *)c->pr_vacc}) {
+    for (void *q : {(void *)c->pr_rows, (void *)c->pr_loc, c->pr_part, (void *)c->pr_vacc, c->pr_Z, c->pr_Z_lo}) {
         if (!q) continue;
         auto it = std::find(c->allocs.begin(), c->allocs.end(), q);
         if (it != c->allocs.end()) c->allocs.erase(it);
@@ -774,6 +782,7 @@ matvis_status matvis_set_pairs(matvis_ctx *c, const int32_t *pair_a, const int32
     c->pr_rows = c->pr_loc = nullptr;
     c->pr_part = nullptr;
     c->pr_vacc = nullptr;
+    c->pr_Z = c->pr_Z_lo = nullptr;
     c->pr_set = false;
     const int B_cap = c->ntb * c->nfb;
     matvis_status st;
@@ -783,6 +792,16 @@ matvis_status matvis_set_pairs(matvis_ctx *c, const int32_t *pair_a, const int32
         MATVIS_OK)
         return st;
     if ((st = dalloc(c, &c->pr_vacc, sizeof(double) * 2 * (size_t)B_cap * n_pair * nf * nf)) != MATVIS_OK) return st;
+    // Fused contexts: a sub-matrix tile reuses a formed Z row only within its 32
+    // rows, so forming Z once per batch in device memory is faster whenever it
+    // fits a fixed budget; otherwise the tiles form their rows in the stages.
+    if (c->fused) {
+        const size_t zplane = (g.precision == PB3 ? (size_t)4 : cbytes(g.precision)) * B_cap * c->Np * c->ldz;
+        if (zplane * (g.precision == PB3 ? 2 : 1) <= ((size_t)8 << 30)) {
+            if ((st = dalloc(c, &c->pr_Z, zplane)) != MATVIS_OK) return st;
+            if (g.precision == PB3 && (st = dalloc(c, &c->pr_Z_lo, zplane)) != MATVIS_OK) return st;
+        }
+    }
     HIPCHK(c, hipMemcpy(c->pr_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->pr_loc, loc.data(), sizeof(int32_t) * loc.size(), hipMemcpyHostToDevice));
     c->pr_n = n_pair;

@@ -2,9 +2,10 @@
 
 matvis_simulate_pairs for the representatives of matvis_redundant_groups
 against the oracle's direct sum at those pairs, for FP64, FP32 and BF16X3 with
-Z in device memory and for FP32 and BF16X3 with Z formed in the product's
-stages, one to three sub-matrices, a polarised beam and sky, and sources in
-several chunks; plus the equality with matvis_simulate at the same pairs and,
+Z in device memory, for FP32 and BF16X3 on fused contexts (Z of the batch
+formed once when it fits the pair plan's budget, and, for a context sized for
+4M sources, formed in the sub-matrix tiles' stages), one to three
+sub-matrices, a polarised beam and sky, and sources in several chunks; plus the equality with matvis_simulate at the same pairs and,
 physically, between the members of one redundant group.
 """
 import numpy as np
@@ -44,14 +45,17 @@ def _run_pairs(wl, precision, reps, n_sub, stokes=None, fused=False, **kw):
     return out.reshape((-1,) + out.shape[2:]), full.reshape((-1,) + full.shape[2:]), size
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp32-fused", "bf16x3-fused"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp32-fused", "bf16x3-fused", "bf16x3-fused-stages"])
 @pytest.mark.parametrize("n_sub", [1, 2, 3])
 def test_pairs_match_oracle_and_full_product(precision, n_sub):
     wl = synth.workload(1, n_src=1500, n_time=2, n_freq=2)
     _, reps = mv.redundant_groups(wl.antpos, None, 1e-6)
-    fused = precision.endswith("-fused")
-    precision = precision.replace("-fused", "")
-    V, full, size = _run_pairs(wl, precision, reps, n_sub, fused=fused)
+    fused = "-fused" in precision
+    # a context sized for 4M sources: its batch of Z exceeds the pair plan's budget,
+    # so the sub-matrix tiles form their Z rows in the stages
+    kw = {"max_src": 1 << 22} if precision.endswith("-stages") else {}
+    precision = precision.split("-")[0]
+    V, full, size = _run_pairs(wl, precision, reps, n_sub, fused=fused, **kw)
     ref = oracle.simulate_pairs(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, wl.flux, grid_as_used(wl, precision),
                                 wl.latitude, wl.dza, wl.daz, wl.interp,
                                 instances=[(t, f) for t in range(wl.n_time) for f in range(wl.n_freq)], pairs=reps)
