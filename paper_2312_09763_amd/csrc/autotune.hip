@@ -8,7 +8,8 @@
 //               over sources, BF16X3): one-sided or square-root weights;
 //   tile        the forming split: rows per stage formed by the multiply-first
 //               waves (paths that split the forming between two wave kinds);
-//   ksplit      Z columns per work item: the path's default and its halves
+//   ksplit      Z columns per work item: the path's default, two and four times it
+//               (fewer partial sums, longer FP32 accumulations), and its halves
 //               and quarters (never more than the default, so FP32
 //               accumulation is never less accurate than the default's);
 //   src_chunk   sources per chunk: the default and 2^18, 2^20;
@@ -193,7 +194,7 @@ extern "C" matvis_status matvis_autotune(const matvis_config *base, const double
     std::vector<long long> pair_kernels = {0};  // block-pair kernel, bit 4 (BF16X3, more than one block)
     if (over_sources && prec == mv::PB3 && base->n_ant > 128) pair_kernels.push_back(16);
     std::vector<long long> ksplits = {0};
-    for (int64_t d : {kdef / 2, kdef / 4})
+    for (int64_t d : {kdef * 2, kdef * 4, kdef / 2, kdef / 4})
         if (d >= 64 && d % 64 == 0) ksplits.push_back(d);
     std::vector<long long> chunks = {0};
     for (long long c : {1LL << 18, 1LL << 20})

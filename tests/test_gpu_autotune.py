@@ -22,10 +22,10 @@ def test_autotune_picks_cached_candidate_and_stays_accurate(tmp_path, precision)
     tuned, ms = mv.autotune(cfg, **d, cache_path=cache)
     say(f"autotune {precision}: tile={tuned.tile} ksplit={tuned.ksplit} src_chunk={tuned.src_chunk} "
         f"batch_time={tuned.batch_time} unfused={tuned.unfused} {ms:.3f} ms")
-    # candidates: 0 (the library's choice) and, on the product over sources, half and a
-    # quarter of the path's default k-split (8192 FP32, 20480 BF16X3), the 64-antenna
-    # forming split, times per batch 1..8 (<= 5 here); no chunk below 3001 sources
-    allowed = {"fp32": {0, 4096, 2048}, "bf16x3": {0, 10240, 5120}}[precision]
+    # candidates: 0 (the library's choice) and, on the product over sources, 2, 4, 1/2
+    # and 1/4 times the path's default k-split (8192 FP32, 20480 BF16X3), the
+    # 64-antenna forming split, times per batch 1..8 (<= 5 here); no chunk below 3001 sources
+    allowed = {"fp32": {0, 16384, 32768, 4096, 2048}, "bf16x3": {0, 40960, 81920, 10240, 5120}}[precision]
     assert tuned.ksplit in allowed and tuned.batch_time in (0, 1, 2, 4) and tuned.tile in (0, 2)
     assert tuned.src_chunk == 0 and ms > 0
     text = open(cache).read()
