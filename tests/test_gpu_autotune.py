@@ -71,3 +71,20 @@ def test_autotune_learned_beam(tmp_path):
     tuned, ms = mv.autotune(cfg, **d, cache_path=str(tmp_path / "t.json"), surrogate=P)
     say(f"autotune with the learned beam: tile={tuned.tile} ksplit={tuned.ksplit} {ms:.3f} ms")
     assert ms > 0 and tuned.beam_mode == "surrogate"
+
+
+@pytest.mark.parametrize("variant", [16])
+@pytest.mark.parametrize("n_ant", [301, 350])
+def test_block_pair_kernel_variants_match_oracle(variant, n_ant):
+    """The block-pair kernel variant of the product over sources (tile bit 4: the
+    two-sided square-root weights) against the oracle, on three 128-antenna blocks
+    with a short last block (45 or 94 antennas), beside the default kernel."""
+    wl = synth.workload(2, n_ant=n_ant, n_src=600, n_time=1, n_freq=2)
+    V = gpu_simulate(wl, "bf16x3", tile=variant)
+    V0 = gpu_simulate(wl, "bf16x3")
+    ref = oracle_vis(wl, grid=grid_as_used(wl, "bf16x3"))
+    ef, ec = errors(V, ref)
+    ef0, ec0 = errors(V0, ref)
+    say(f"block-pair variant {variant}, {n_ant} antennas: err_F={ef:.3e} err_CS={ec:.3e} "
+        f"(default kernel {ef0:.3e} / {ec0:.3e})")
+    assert ef <= 1e-5 and ec <= 1e-5
