@@ -82,6 +82,18 @@ def product_flops(path: str, n_ant: int, n_feed: int, n_ax: int, counts_t, n_fre
     return tot, tot, 0.0
 
 
+def hbm_steps(counts, n_time, n_src, n_comp, n_freq, steps_ms, cbytes=8):
+    """Achieved HBM rate of the bandwidth-bound steps on their algorithmic bytes: the sky
+    step reads X_eq per time (24 B per source) and writes index, s_hat and (za, az) per
+    visible source (4 + 24 + 16 B); the beam step reads (za, az) (16 B) and writes one
+    complex value per channel and component per visible source and time."""
+    vis = float(np.sum(counts))
+    by = {"sky": float(n_time * 24.0 * n_src + vis * 44.0), "beam": vis * (16.0 + cbytes * n_comp * n_freq)}
+    return {k: {"bytes_per_step": b, "ms_per_step": steps_ms[k],
+                "achieved_GBps": b / (steps_ms[k] / 1e3) / 1e9 if steps_ms[k] > 0 else None, "peak_GBps": HBM_GBS}
+            for k, b in by.items()}
+
+
 def profile_record(name: str):
     """A committed rocprofv3 summary (profiles/<name>.json): its HBM traffic and
     MFMA-busy figures, or None when it is missing or a source it depends on (the
@@ -160,6 +172,8 @@ def main():
                     help="only run a plain device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--secondary-steps", type=int, default=10, help="steps of the 128-antenna workload (0 = skip)")
     ap.add_argument("--side-steps", type=int, default=1, help="steps of each side-by-side variant (0 = skip)")
+    ap.add_argument("--side-precisions", default="bf16x3,fp32,fp64",
+                    help="precisions of the side-by-side runs with the interpolated beam")
     ap.add_argument("--workload-steps", type=int, default=2, help="calls on each other workload (0 = skip)")
     ap.add_argument("--redundancy-steps", type=int, default=2, help="App. A comparison steps (0 = skip)")
     args = ap.parse_args()
@@ -280,7 +294,7 @@ def main():
     log(f"error vs oracle: {err}")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl, grid)
-    side = side_by_side(args, wl, vis, stream) if args.side_steps > 0 else None
+    side = side_by_side(args, wl, vis, stream, cfg) if args.side_steps > 0 else None
     if side is not None:
         side["bf16x3+learned"] = {"ms_per_step": ms_step, "value": value, "product_path": path,
                                   "product_ms_per_step": prod_ms, "product_frac_of_peak": prod_tf / PEAK_TFLOPS[prec],
@@ -306,8 +320,9 @@ def main():
         "dtype": "bf16x3 (f32 accumulate)",
         "data": "synthetic",
         "config": {"workload": "learned beam on the diffuse sky: 350-antenna hex array (14.6 m), 2 feeds x 2 axes, "
-                               "3145728 equal-area pixels (nside 512) with log-normal brightness, Fourier-feature "
-                               "network beam trained on the 0.5 deg bicubic dipole beam, BF16X3 product; full "
+                               "3145728 equal-area pixels (nside 512) with log-normal brightness, learned beam "
+                               "(Fourier-feature network of the direction, Chebyshev series in frequency) trained "
+                               "on the 0.5 deg bicubic dipole beam, BF16X3 product; full "
                                "configuration 64 LSTs x 64 in-band channels (100-200 MHz of 128 over 50-250 MHz)",
                    "sample": f"{wl.n_time} LSTs x {wl.n_freq} channels = {wl.n_time * wl.n_freq} of the 4096 "
                              f"instances per step (LSTs {[round(x, 4) for x in wl.lsts.tolist()]} rad, channels "
@@ -319,6 +334,7 @@ def main():
                                     "train_s": round(train_s, 1)}},
         "roofline": roofline,
         "step_ms": steps_ms,
+        "hbm_steps": hbm_steps(counts, wl.n_time, wl.n_src, wl.n_feed * wl.n_ax, wl.n_freq, steps_ms),
         "error_vs_oracle": err,
         "cpu_baseline": cpu,
         "side_by_side": side,
@@ -356,15 +372,17 @@ def cpu_baseline(wl, grid):
     return res
 
 
-def side_by_side(args, wl, vis, stream):
+def side_by_side(args, wl, vis, stream, tuned):
     """The headline's sample through the FP64 interpolated path, FP32 and BF16X3 with the
-    bicubic-interpolated beam (Z in device memory on FP64; formed in the product otherwise)."""
+    bicubic-interpolated beam (Z in device memory on FP64; formed in the product otherwise).
+    BF16X3 takes the headline's tuned product configuration, FP32 and FP64 the defaults."""
     import torch
     from paper_2312_09763_amd import matvis as mv
     out = {}
-    for vprec in ("bf16x3", "fp32", "fp64"):
+    for vprec in [p for p in ("bf16x3", "fp32", "fp64") if p in args.side_precisions.split(",")]:
         vd = mv.device_inputs(wl, vprec)
-        with mv.Context(mv.config_for(wl, vprec)) as vctx:
+        kw = dict(ksplit=tuned.ksplit, batch_time=tuned.batch_time, tile=tuned.tile) if vprec == "bf16x3" else {}
+        with mv.Context(mv.config_for(wl, vprec, **kw)) as vctx:
             vvis = torch.empty(tuple(vis.shape), dtype=vctx.complex_dtype, device="cuda")
             vctx.simulate(**vd, vis=vvis)
             vctx.finish()
@@ -376,10 +394,14 @@ def side_by_side(args, wl, vis, stream):
             tot, _, _ = product_flops(vpath, wl.n_ant, wl.n_feed, wl.n_ax, counts, wl.n_freq)
             pms = vprof["herk"][0] + vprof["herk_pairs"][0]
             vtf = tot * PRODUCTS[vprec] / (pms / 1e3) / 1e12 if pms > 0 else None
+            vsteps = {k: round(v[0], 4) for k, v in vprof.items()}
             out[f"{vprec}+interpolated"] = {"ms_per_step": vms, "value": wl.work_units() / (vms / 1e3),
                                             "product_path": vpath, "product_ms_per_step": pms,
                                             "product_frac_of_peak": vtf / PEAK_TFLOPS[vprec] if vtf else None,
-                                            "beam_ms_per_step": vprof["beam"][0]}
+                                            "beam_ms_per_step": vprof["beam"][0],
+                                            "hbm_steps": hbm_steps(counts, wl.n_time, wl.n_src, wl.n_feed * wl.n_ax,
+                                                                   wl.n_freq, vsteps,
+                                                                   16 if vprec == "fp64" else 8)}
             log(f"side by side {vprec} + interpolated beam: {vms:.2f} ms/step, product {pms:.2f} ms")
             del vvis
         del vd
@@ -412,22 +434,15 @@ def secondary(args):
     achieved = tot * PRODUCTS[prec] * 2 / max(hn, 1) / (launch_ms / 1e3) / 1e12
     steps_ms = {s: round(v[0] / 2, 4) for s, v in prof.items()}
     n_comp = wl.n_feed * wl.n_ax * wl.beam.shape[0]
-    # algorithmic bytes: sky, X_eq read per time (24 B per source), index + s_hat + (za, az)
-    # written per visible source (4 + 24 + 16 B); beam, (za, az) read (16 B) and one complex64
-    # per channel and component written per visible source and time
-    sky_bytes = float(wl.n_time * 24.0 * wl.n_src + np.sum(counts) * 44.0)
-    beam_bytes = float(np.sum(counts) * (16.0 + 8.0 * n_comp * wl.n_freq))
     rec = profile_record("herk_coh_bf16x3_workload2")
     res = {"workload": "128-antenna polarised hex array, 50000 point sources, 32 LSTs x 16 channels 100-200 MHz, "
                        "dipole Jones beam 0.5 deg grid bicubic, BF16X3",
            "ms_per_step": ms, "value": wl.work_units() / (ms / 1e3), "product_path": path,
-           "roofline": {"bound": "mfma", "kernel": "k_herk_coh<2, false, 96>", "achieved": achieved,
+           "roofline": {"bound": "mfma", "kernel": "k_herk_coh<2, false, 96, false>", "achieved": achieved,
                         "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[prec],
                         "launch_ms": launch_ms, "traffic": rec["traffic_bytes_per_launch"] if rec else None},
            "step_ms": steps_ms,
-           "hbm_steps": {k: {"bytes_per_step": by, "ms_per_step": steps_ms[k],
-                             "achieved_GBps": by / (steps_ms[k] / 1e3) / 1e9 if steps_ms[k] > 0 else None,
-                             "peak_GBps": HBM_GBS} for k, by in (("sky", sky_bytes), ("beam", beam_bytes))}}
+           "hbm_steps": hbm_steps(counts, wl.n_time, wl.n_src, n_comp, wl.n_freq, steps_ms)}
     log(f"secondary (128 antennas, 50k sources): {ms:.3f} ms/step, product launch {launch_ms:.3f} ms "
         f"({achieved / PEAK_TFLOPS[prec]:.3f} of peak), steps {steps_ms}")
     return res
