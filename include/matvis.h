@@ -309,9 +309,10 @@ matvis_status matvis_set_surrogate(matvis_ctx *ctx, const float *params, double 
  * (tile), ksplit, src_chunk, batch_time and MATVIS_FLAG_UNFUSED choice, and
  * the time of one call in *best_ms (host pointers).  The search is coordinate
  * descent from the library's defaults over, in order: the block-pair kernel
- * (tile bit 4), the forming split (tile bits 0-3), ksplit (the path's default, half and a
- * quarter of it: never more than the default, so FP32 accumulation is as
- * accurate as with the default or more), src_chunk (default, 2^18, 2^20
+ * (tile bit 4), the forming split (tile bits 0-3), ksplit (the path's default, two and
+ * four times it, half and a quarter of it: the larger ones write fewer partial
+ * sums and accumulate more terms in FP32, whose rounding grows about as the
+ * square root of the split), src_chunk (default, 2^18, 2^20
  * sources), batch_time (default, 1, 2, 4, 8) and fused / unfused Z.  0, the
  * library's own choice, is a candidate on every axis, so the result is never
  * slower than the defaults as timed.  Candidates that do not fit in device

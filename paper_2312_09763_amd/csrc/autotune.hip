@@ -9,9 +9,9 @@
 //   tile        the forming split: rows per stage formed by the multiply-first
 //               waves (paths that split the forming between two wave kinds);
 //   ksplit      Z columns per work item: the path's default, two and four times it
-//               (fewer partial sums, longer FP32 accumulations), and its halves
-//               and quarters (never more than the default, so FP32
-//               accumulation is never less accurate than the default's);
+//               (fewer partial sums; each FP32 accumulator sees more terms, so
+//               its rounding grows about as the square root of the split), and
+//               its halves and quarters (more accurate than the default);
 //   src_chunk   sources per chunk: the default and 2^18, 2^20;
 //   batch_time  times per device batch: the default and 1, 2, 4, 8;
 //   unfused     Z formed inside the product or written to device memory.
