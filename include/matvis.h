@@ -102,8 +102,10 @@ typedef struct {
                              coherency weight on the rows only (the plain fringe rows
                              of the other block as columns), 1 splits it as square
                              roots over both sides (FP32 always uses the latter).
-                             Bits 0-3 only reschedule work; bit 4 changes the
-                             rounding (not the tolerance). */
+                             Bit 6: 16 sources per stage instead of 32 on
+                             MATVIS_PATH_FUSED_BLOCKS with BF16X3.
+                             Bits 0-3 and 6 only reschedule work; bit 4 changes
+                             the rounding (not the tolerance). */
 } matvis_config;
 
 #define MATVIS_FLAG_NO_GRAPH 1 /* launch kernels directly instead of replaying a captured hipGraph */
@@ -309,7 +311,8 @@ matvis_status matvis_set_surrogate(matvis_ctx *ctx, const float *params, double 
  * (tile), ksplit, src_chunk, batch_time and MATVIS_FLAG_UNFUSED choice, and
  * the time of one call in *best_ms (host pointers).  The search is coordinate
  * descent from the library's defaults over, in order: the block-pair kernel
- * (tile bit 4), the forming split (tile bits 0-3), ksplit (the path's default, two and
+ * (tile bit 4), the forming split (tile bits 0-3), the stage depth (tile bit 6), ksplit
+ * (the path's default, two and
  * four times it, half and a quarter of it: the larger ones write fewer partial
  * sums and accumulate more terms in FP32, whose rounding grows about as the
  * square root of the split), src_chunk (default, 2^18, 2^20

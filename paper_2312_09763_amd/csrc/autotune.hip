@@ -8,6 +8,7 @@
 //               over sources, BF16X3): one-sided or square-root weights;
 //   tile        the forming split: rows per stage formed by the multiply-first
 //               waves (paths that split the forming between two wave kinds);
+//   stage       sources per stage, 32 or 16 (BF16X3 three-block path);
 //   ksplit      Z columns per work item: the path's default, two and four times it
 //               (fewer partial sums; each FP32 accumulator sees more terms, so
 //               its rounding grows about as the square root of the split), and
@@ -193,6 +194,8 @@ extern "C" matvis_status matvis_autotune(const matvis_config *base, const double
     if (three_blocks) tiles.insert(tiles.end(), {2, 4});
     std::vector<long long> pair_kernels = {0};  // block-pair kernel, bit 4 (BF16X3, more than one block)
     if (over_sources && prec == mv::PB3 && base->n_ant > 128) pair_kernels.push_back(16);
+    std::vector<long long> stages = {0};  // stage depth, bit 6 (BF16X3 three-block path)
+    if (three_blocks && prec == mv::PB3) stages.push_back(64);
     std::vector<long long> ksplits = {0};
     for (int64_t d : {kdef * 2, kdef * 4, kdef / 2, kdef / 4})
         if (d >= 64 && d % 64 == 0) ksplits.push_back(d);
@@ -217,8 +220,9 @@ extern "C" matvis_status matvis_autotune(const matvis_config *base, const double
         std::function<void(matvis_config &, long long)> set;
     };
     const std::vector<Axis> axes = {
-        {&pair_kernels, [](matvis_config &c, long long v) { c.tile = (c.tile & 15) | (int32_t)v; }},
+        {&pair_kernels, [](matvis_config &c, long long v) { c.tile = (c.tile & ~16) | (int32_t)v; }},
         {&tiles, [](matvis_config &c, long long v) { c.tile = (c.tile & ~15) | (int32_t)v; }},
+        {&stages, [](matvis_config &c, long long v) { c.tile = (c.tile & ~64) | (int32_t)v; }},
         {&ksplits, [](matvis_config &c, long long v) { c.ksplit = v; }},
         {&chunks, [](matvis_config &c, long long v) { c.src_chunk = v; }},
         {&tbs, [](matvis_config &c, long long v) { c.batch_time = (int32_t)v; }},

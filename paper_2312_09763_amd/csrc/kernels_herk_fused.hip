@@ -1688,11 +1688,17 @@ struct SclSrc {
     float g, pad;    // |B| (0 past the split)
 };
 
-template <int PREC, int SQ_ROWS = 96>
+// SPS_: sources per stage, 16 or (BF16X3, the default there) 32: a deeper
+// stage halves the barriers and the per-stage operand loads per source (3-5 %
+// on the 350-antenna diffuse sky), the LDS holds 139 KB; the MFMAs accumulate
+// in the same source order either way.
+template <int PREC, int SQ_ROWS = 96, int SPS_ = 16>
 __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
-    typedef GeomCoh L;
+    static_assert(SPS_ == 16 || (SPS_ == 32 && PREC == PB3), "16 sources per stage, or 32 on BF16X3");
+    typedef typename std::conditional<SPS_ == 32, GeomPair, GeomCoh>::type L;
     constexpr int RS = L::RS;
-    constexpr int SPS = 16;
+    constexpr int SPS = SPS_;
+    constexpr int RSTEP = 512 / SPS;  // rows between a thread's rows
     constexpr int BUF = 2 * kST * RS;
     // SQ_ROWS: rows formed by the square waves of the 256 of a stage (the triangle
     // waves, with fewer products, form the rest); 96 by default, 64 and 128 as
@@ -1701,6 +1707,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
     __shared__ AntEntry tab[2 * kST];
     __shared__ SclSrc src[2][SPS];
+    static_assert(2 * BUF + sizeof(tab) + sizeof(src) <= 160 * 1024, "LDS of one CU");
 
     const int tid = threadIdx.x;
     const int lane = lane_id();
@@ -1784,7 +1791,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
             e.g = sqrtf(fb.x * fb.x + fb.y * fb.y);
             e.pad = 0.f;
         };
-        // rows a0 + 32 k (plane row >> 7) of this thread's two sources; rows of
+        // rows a0 + RSTEP k (plane row >> 7) of this thread's two sources; rows of
         // padding antennas (u = 0) only reach outputs that are never stored
         auto produce_n = [&](unsigned char *buf, int stage, auto na) {
             constexpr int NA = decltype(na)::value;
@@ -1793,7 +1800,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
             w[1] = src[stage & 1][2 * mp + 1];
 #pragma unroll
             for (int k = 0; k < NA; k++) {
-                const int as = a0 + 32 * k;
+                const int as = a0 + RSTEP * k;
                 const AntEntry e = tab[as];
                 float vr[2], vi[2];
 #pragma unroll
@@ -1818,9 +1825,9 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
         };
         auto produce = [&](unsigned char *buf, int stage) {
             if (sq)
-                produce_n(buf, stage, std::integral_constant<int, SQ_ROWS / 32>{});
+                produce_n(buf, stage, std::integral_constant<int, SQ_ROWS / RSTEP>{});
             else
-                produce_n(buf, stage, std::integral_constant<int, (2 * kST - SQ_ROWS) / 32>{});
+                produce_n(buf, stage, std::integral_constant<int, (2 * kST - SQ_ROWS) / RSTEP>{});
         };
 
         f32x4 acc_re[16], acc_im[16];
@@ -2001,7 +2008,14 @@ hipError_t launch_herk_fused(int prec, const FusedArgs &a, hipStream_t s, int wh
     if (path == MATVIS_PATH_FUSED_ROWS) return first ? launch_pair(a, s) : hipSuccess;
     if (path == MATVIS_PATH_FUSED_BLOCKS) {
         if (!first) return hipSuccess;
-        if (prec == PB3) {
+        if (prec == PB3 && !(a.tile & 64)) {  // 32 sources per stage unless bit 6 asks for 16
+            if (split == 2)
+                k_herk_blk3<PB3, 64, 32><<<a.grid, 512, 0, s>>>(a);
+            else if (split == 4)
+                k_herk_blk3<PB3, 128, 32><<<a.grid, 512, 0, s>>>(a);
+            else
+                k_herk_blk3<PB3, 96, 32><<<a.grid, 512, 0, s>>>(a);
+        } else if (prec == PB3) {
             if (split == 2)
                 k_herk_blk3<PB3, 64><<<a.grid, 512, 0, s>>>(a);
             else if (split == 4)

@@ -199,9 +199,9 @@ matvis_status validate_cfg(const matvis_config *c, std::string &why) {
         return why = "latitude out of range", MATVIS_EINVAL;
     if (c->src_chunk < 0 || c->batch_time < 0 || c->batch_freq < 0) return why = "negative batch sizes", MATVIS_EINVAL;
     if ((int64_t)c->n_ant * c->n_feed > 8192) return why = "n_ant * n_feed above 8192", MATVIS_EUNSUPPORTED;
-    if (c->tile < 0 || (c->tile & ~0x1f) != 0 || ((c->tile & 15) != 0 && ((c->tile & 15) < 2 || (c->tile & 15) > 4)))
-        return why = "tile: bits 0-3 (forming split) must be 0, 2, 3 or 4, bit 4 (block-pair kernel) 0 or 1, "
-                     "no other bits", MATVIS_EINVAL;
+    if (c->tile < 0 || (c->tile & ~0x5f) != 0 || ((c->tile & 15) != 0 && ((c->tile & 15) < 2 || (c->tile & 15) > 4)))
+        return why = "tile: bits 0-3 (forming split) must be 0, 2, 3 or 4, bit 4 (block-pair kernel) and bit 6 "
+                     "(stage depth) 0 or 1, no other bits", MATVIS_EINVAL;
     if (c->ksplit < 0 || c->ksplit % 64 != 0 || c->ksplit > ((int64_t)1 << 30))
         return why = "ksplit must be 0 or a positive multiple of 64", MATVIS_EINVAL;
     return MATVIS_OK;

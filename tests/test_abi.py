@@ -126,7 +126,7 @@ def test_autotune_learned_beam_needs_parameters():
     assert st == mv.EINVAL
 
 
-@pytest.mark.parametrize("tile", [1, 5, 32, -1])
+@pytest.mark.parametrize("tile", [1, 5, 32, 128, -1])
 def test_init_rejects_unknown_tile(tile):
     st, h = _init(tile=tile)
     assert st == mv.EINVAL and not h.value

@@ -88,3 +88,18 @@ def test_block_pair_kernel_variants_match_oracle(variant, n_ant):
     say(f"block-pair variant {variant}, {n_ant} antennas: err_F={ef:.3e} err_CS={ec:.3e} "
         f"(default kernel {ef0:.3e} / {ec0:.3e})")
     assert ef <= 1e-5 and ec <= 1e-5
+
+
+@pytest.mark.parametrize("split", [0, 2, 4])
+def test_stage_depth_variant_is_bitwise_the_same(split):
+    """16 sources per stage on the BF16X3 three-block path (tile bit 6) against the
+    default 32: the MFMAs of either stage depth accumulate in the same source order,
+    so V is bitwise the same; with each forming split, and against the oracle."""
+    ws = synth.workload(3, n_src=3072, n_time=2, n_freq=2)
+    V0 = gpu_simulate(ws, "bf16x3", tile=split | 64)
+    V1 = gpu_simulate(ws, "bf16x3", tile=split)
+    say(f"stage depth 16 against 32, forming split {split}: bitwise equal {np.array_equal(V0, V1)}")
+    assert np.array_equal(V0, V1)
+    ef, ec = errors(V1, oracle_vis(ws, grid=grid_as_used(ws, "bf16x3")))
+    say(f"  err_F={ef:.3e} err_CS={ec:.3e}")
+    assert ef <= TOL["bf16x3"] and ec <= TOL["bf16x3"]
