@@ -36,6 +36,14 @@ constexpr int kST = 128, kWT = 64, kKC = 32, kTI = 4;
 
 __device__ inline int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
+// Row of a forming thread (8 threads per row, two sources each): a wave's 8 rows
+// in the order 0, 4, 1, 5, 2, 6, 3, 7, so the two rows that 16 consecutive
+// lanes write are 4 rows (576 bytes) apart and fall in disjoint LDS banks.
+__device__ inline int wrow(int t) {
+    const int g = (t >> 3) & 7;
+    return ((t >> 6) << 3) + (((g & 1) << 2) | (g >> 1));
+}
+
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
@@ -1031,9 +1039,9 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
     const int per_xcd = a.grid / 8;
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int mp = tid % (SPS / 2);  // source pair
-    const int a0o = tid / (SPS / 2);  // off-diagonal items: antennas a0o + 64 k of the 256 of blocks I, J
+    const int a0o = wrow(tid);  // off-diagonal items: antennas a0o + 64 k of the 256 of blocks I, J
     // this thread's antennas: a0, a0 + 32, ... (SQ_ANT / 32 of them, or (kST - SQ_ANT) / 32)
-    const int a0 = sq ? tid / (SPS / 2) : SQ_ANT + (tid - 256) / (SPS / 2);
+    const int a0 = sq ? wrow(tid) : SQ_ANT + wrow(tid - 256);
     // square waves: V^10 rows 16 (sq_rb + i) of L against 16 (sq_cb + j) of P0 (block units)
     const int sq_r0 = 4 * (wave >> 1), sq_c0 = 4 * (wave & 1);
     const int sq_rb = 2 * 8 + sq_r0, sq_cb = sq_c0;
@@ -1232,9 +1240,9 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
             if constexpr (OFF)
                 produce_off(buf, stage);
             else if (short_blk && sq)
-                produce_n(buf, stage, std::integral_constant<int, 2>{}, tid / (SPS / 2));
+                produce_n(buf, stage, std::integral_constant<int, 2>{}, wrow(tid));
             else if (short_blk)
-                produce_n(buf, stage, std::integral_constant<int, 1>{}, 64 + (tid - 256) / (SPS / 2));
+                produce_n(buf, stage, std::integral_constant<int, 1>{}, 64 + wrow(tid - 256));
             else if (sq)
                 produce_n(buf, stage, std::integral_constant<int, SQ_ANT / 32>{}, a0);
             else
@@ -1461,7 +1469,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
     const int per_xcd = a.grid / 8;
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int mp = tid % (SPS / 2);   // source pair 2 mp, 2 mp + 1
-    const int a0 = tid / (SPS / 2);   // antennas a0 + 64 k of the 256 of blocks I (k < 2) and J
+    const int a0 = wrow(tid);         // antennas a0 + 64 k of the 256 of blocks I (k < 2) and J
     const int simd = wave & 3, pr = wave >> 2;
     const int rh = (simd >> 1) ^ pr, ch = simd & 1;
     const int o_rb = pr * 8 + 4 * rh, o_cb = 2 * 8 + 4 * ch, o_wb = 3 * 8 + 4 * ch;
@@ -1720,7 +1728,9 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
     const int per_xcd = a.grid / 8;
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int mp = tid % (SPS / 2);
-    const int a0 = sq ? tid / (SPS / 2) : SQ_ROWS + (tid - 256) / (SPS / 2);
+    // 16-source stages: 8 threads per row, rows permuted as in the two-block kernels
+    const int a0 = SPS == 16 ? (sq ? wrow(tid) : SQ_ROWS + wrow(tid - 256))
+                             : (sq ? tid / (SPS / 2) : SQ_ROWS + (tid - 256) / (SPS / 2));
     const int sq_r0 = 4 * (wave >> 1), sq_c0 = 4 * (wave & 1);
     const int tri_s = (wave - 4) & 3;
 
