@@ -44,6 +44,13 @@ __device__ inline int wrow(int t) {
     return ((t >> 6) << 3) + (((g & 1) << 2) | (g >> 1));
 }
 
+// The same for 160-byte rows: rows 0, 2, 1, 3, 4, 6, 5, 7 (two rows 320 bytes, 16
+// banks, apart)
+__device__ inline int wrow160(int t) {
+    const int g = (t >> 3) & 7;
+    return ((t >> 6) << 3) + (g & 4) + ((g & 1) << 1) + ((g >> 1) & 1);
+}
+
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
@@ -526,12 +533,16 @@ __device__ __forceinline__ void mfma_pair(const u32x4 &a, const u32x4 &b, const 
 
 // Staged-row geometry of the two-block kernels: RS bytes per row, hi plane
 // then lo plane of PLANEB bytes each, NKS k-steps of 16 complex per stage.
+// Operand reads are 16 bytes per lane from 16 rows at once; measured on the
+// LDS, 160-byte rows serve them without bank conflicts and 144-byte rows with
+// half of their cycles in conflicts, so 160 bytes where the stage buffers fit.
 template <int RS_, int PLANEB_, int NKS_>
 struct RowGeom {
     static constexpr int RS = RS_, PLANEB = PLANEB_, NKS = NKS_;
 };
 typedef RowGeom<FL<PB3>::RS, FL<PB3>::PLANEB, kKC / 16> GeomPair;  // 32 complex per stage
 typedef RowGeom<16 * 4 * 2 + 16, 16 * 4, 1> GeomCoh;               // 16 complex per stage
+typedef RowGeom<16 * 4 * 2 + 32, 16 * 4, 1> GeomCoh3;              // the same in 160-byte rows
 
 // Off-diagonal block: rows 16 (rb + i), columns 16 (cb + j), i < NR, j < NC
 // (4 x 4 tiles, or 3 x 3 on a short diagonal block); tile (i, j) accumulates
@@ -1003,10 +1014,13 @@ struct CohSrc {
 
 template <int PREC, bool OFF, int SQ_ANT = 96, bool SHORT = false>
 __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
-    typedef GeomCoh L;  // 144-byte rows: hi + lo bf16 planes, or one complex64 plane (FP32)
+    // 144-byte rows: hi + lo bf16 planes, or one complex64 plane (FP32); 160 bytes
+    // on the three-plane diagonal items of BF16X3
+    constexpr bool R160 = !OFF && PREC == PB3;
+    typedef typename std::conditional<R160, GeomCoh3, GeomCoh>::type L;
     constexpr int RS = L::RS;
     constexpr int SPS = 16;                 // sources per stage
-    constexpr int ROWS = 4 * kST;           // up to four planes of 128 antennas
+    constexpr int ROWS = (OFF ? 4 : 3) * kST;  // planes of 128 antennas
     constexpr int BUF = ROWS * RS;
     // SQ_ANT: antennas formed by the square waves (the rest by the triangle waves,
     // which have more products per stage); the split evens out the two waves of a
@@ -1041,7 +1055,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
     const int mp = tid % (SPS / 2);  // source pair
     const int a0o = wrow(tid);  // off-diagonal items: antennas a0o + 64 k of the 256 of blocks I, J
     // this thread's antennas: a0, a0 + 32, ... (SQ_ANT / 32 of them, or (kST - SQ_ANT) / 32)
-    const int a0 = sq ? wrow(tid) : SQ_ANT + wrow(tid - 256);
+    const int a0 = sq ? (R160 ? wrow160(tid) : wrow(tid)) : SQ_ANT + (R160 ? wrow160(tid - 256) : wrow(tid - 256));
     // square waves: V^10 rows 16 (sq_rb + i) of L against 16 (sq_cb + j) of P0 (block units)
     const int sq_r0 = 4 * (wave >> 1), sq_c0 = 4 * (wave & 1);
     const int sq_rb = 2 * 8 + sq_r0, sq_cb = sq_c0;
@@ -1240,9 +1254,9 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
             if constexpr (OFF)
                 produce_off(buf, stage);
             else if (short_blk && sq)
-                produce_n(buf, stage, std::integral_constant<int, 2>{}, wrow(tid));
+                produce_n(buf, stage, std::integral_constant<int, 2>{}, R160 ? wrow160(tid) : wrow(tid));
             else if (short_blk)
-                produce_n(buf, stage, std::integral_constant<int, 1>{}, 64 + wrow(tid - 256));
+                produce_n(buf, stage, std::integral_constant<int, 1>{}, 64 + (R160 ? wrow160(tid - 256) : wrow(tid - 256)));
             else if (sq)
                 produce_n(buf, stage, std::integral_constant<int, SQ_ANT / 32>{}, a0);
             else
@@ -1390,15 +1404,13 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
 // with w = C_00, C_11 (kind X: V^00_IJ, V^11_IJ), or w = C_10 and conj C_10
 // (kind Y: V^10_IJ, and V^01_IJ = the Hermitian partner of V^10_JI).  So the
 // columns of both products of an item are the unweighted fringe rows F_J, formed
-// and split once, and only the rows carry the weights.  A stage holds four
-// planes of 128 rows x 16 sources: w0 F_I, w1 F_I, F_J, and F_J rotated,
-// (re, im) -> (-im, re), for the imaginary parts, written at forming time so the
-// multiply loop runs MFMAs on LDS operands with no vector work on them.
+// and split once, and only the rows carry the weights.  A stage holds three
+// planes of 128 rows x 16 sources, w0 F_I, w1 F_I and F_J, in 160-byte rows
+// (conflict-free 16-byte operand reads; a fourth plane of F_J rotated for the
+// imaginary parts, which would save the rotation in the multiply loop, does not
+// fit two stages of 160-byte rows in the LDS and was slower at 144 bytes).
 // Against k_herk_coh<PREC, true> (both operands weighted by square roots of the
-// coherency) that is a quarter fewer rows to scale and split per stage and no
-// operand rotation in the multiply loop; on a SIMD the matrix and vector work
-// of its two waves largely take turns rather than overlap, so the vector
-// instructions saved are time saved.
+// coherency) that is a quarter fewer rows to scale and split per stage.
 //
 // Waves s and s + 4 share SIMD s: wave s takes product 0 and row half s >> 1 of
 // the 128 x 128 block, wave s + 4 product 1 and the other row half, both column
@@ -1412,10 +1424,10 @@ struct PairSrc {
     float c10x, c10y; // (all four 0 past the split)
 };
 
-// Rows 16 (rb + i), i < NR, of one plane against columns 16 (cb + j) and their
-// rotations 16 (wb + j), j < 4: re += a b, im += a rot(b) for the hi / lo terms.
+// Rows 16 (rb + i), i < NR, of one plane against columns 16 (cb + j), j < 4:
+// re += a b, im += a rot(b) for the hi / lo terms, rot(b) formed in registers.
 template <typename L, int NR>
-__device__ __forceinline__ void consume_pairs_b3(const unsigned char *buf, int rb, int cb, int wb, int l16, int lk,
+__device__ __forceinline__ void consume_pairs_b3(const unsigned char *buf, int rb, int cb, int l16, int lk,
                                                  f32x4 (&re)[16], f32x4 (&im)[16]) {
     u32x4 ah[NR], al[NR];
 #pragma unroll
@@ -1425,20 +1437,17 @@ __device__ __forceinline__ void consume_pairs_b3(const unsigned char *buf, int r
         al[i] = *(const u32x4 *)(p + L::PLANEB);
     }
     const unsigned char *pc = buf + (16 * cb + l16) * L::RS + lk * 16;
-    const unsigned char *pw = buf + (16 * wb + l16) * L::RS + lk * 16;
     u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
-    u32x4 mh = *(const u32x4 *)pw, ml = *(const u32x4 *)(pw + L::PLANEB);
 #pragma unroll
     for (int j = 0; j < kTI; j++) {
-        const u32x4 bh = nh, bl = nl, wh = mh, wl = ml;
+        const u32x4 bh = nh, bl = nl;
         if (j + 1 < kTI) {
-            const unsigned char *q = pc + 16 * (j + 1) * L::RS, *r = pw + 16 * (j + 1) * L::RS;
+            const unsigned char *q = pc + 16 * (j + 1) * L::RS;
             nh = *(const u32x4 *)q;
             nl = *(const u32x4 *)(q + L::PLANEB);
-            mh = *(const u32x4 *)r;
-            ml = *(const u32x4 *)(r + L::PLANEB);
         }
-        __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of this column's products
+        __builtin_amdgcn_sched_barrier(0);
+        const u32x4 wh = bf16_rot_col(bh), wl = bf16_rot_col(bl);
 #pragma unroll
         for (int i = 0; i < NR; i++) mfma_pair(ah[i], bh, wh, re[i * kTI + j], im[i * kTI + j]);
 #pragma unroll
@@ -1450,10 +1459,10 @@ __device__ __forceinline__ void consume_pairs_b3(const unsigned char *buf, int r
 }
 
 __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
-    typedef GeomCoh L;
+    typedef GeomCoh3 L;
     constexpr int RS = L::RS;
     constexpr int SPS = 16;         // sources per stage
-    constexpr int BUF = 4 * kST * RS;
+    constexpr int BUF = 3 * kST * RS;
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
     __shared__ AntEntry tab[2 * kST];
     __shared__ PairSrc src[2][SPS];
@@ -1469,10 +1478,10 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
     const int per_xcd = a.grid / 8;
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int mp = tid % (SPS / 2);   // source pair 2 mp, 2 mp + 1
-    const int a0 = wrow(tid);         // antennas a0 + 64 k of the 256 of blocks I (k < 2) and J
+    const int a0 = wrow160(tid);      // antennas a0 + 64 k of the 256 of blocks I (k < 2) and J
     const int simd = wave & 3, pr = wave >> 2;
     const int rh = (simd >> 1) ^ pr, ch = simd & 1;
-    const int o_rb = pr * 8 + 4 * rh, o_cb = 2 * 8 + 4 * ch, o_wb = 3 * 8 + 4 * ch;
+    const int o_rb = pr * 8 + 4 * rh, o_cb = 2 * 8 + 4 * ch;
     const bool mult_first = wave < 4;
 
     for (int item = slot_x; item < total; item += a.grid) {
@@ -1555,8 +1564,8 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
             e.c10x = fb[2].x * fb[0].x + fb[2].y * fb[0].y + fb[3].x * fb[1].x + fb[3].y * fb[1].y;
             e.c10y = fb[2].y * fb[0].x - fb[2].x * fb[0].y + fb[3].y * fb[1].x - fb[3].x * fb[1].y;
         };
-        // Weighted rows of block I (planes 0, 1) or plain and rotated rows of block
-        // J (planes 2, 3) for this thread's two sources.  Rows of block I past its
+        // Weighted rows of block I (planes 0, 1) or plain rows of block J (plane 2)
+        // for this thread's two sources.  Rows of block I past its
         // antennas are skipped (never multiplied); a source past the split has zero
         // weights, and its J rows only meet zero-weighted I rows.
         auto produce = [&](unsigned char *buf, int stage, auto ky) {
@@ -1601,14 +1610,9 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
 #pragma unroll
                     for (int qq = 0; qq < 2; qq++) split2(fr[qq], fi[qq], h[qq], l[qq]);
                     const int rj = as - kST;  // row of block J
-                    unsigned char *r2 = buf + (2 * kST + rj) * RS + mp * 8, *r3 = buf + (3 * kST + rj) * RS + mp * 8;
+                    unsigned char *r2 = buf + (2 * kST + rj) * RS + mp * 8;
                     *(uint2 *)r2 = make_uint2(h[0], h[1]);
                     *(uint2 *)(r2 + L::PLANEB) = make_uint2(l[0], l[1]);
-                    // (re, im) -> (-im, re) on each bf16 pair: swap the halves, negate the low one
-                    *(uint2 *)r3 = make_uint2(__builtin_amdgcn_alignbit(h[0], h[0], 16) ^ 0x00008000u,
-                                              __builtin_amdgcn_alignbit(h[1], h[1], 16) ^ 0x00008000u);
-                    *(uint2 *)(r3 + L::PLANEB) = make_uint2(__builtin_amdgcn_alignbit(l[0], l[0], 16) ^ 0x00008000u,
-                                                            __builtin_amdgcn_alignbit(l[1], l[1], 16) ^ 0x00008000u);
                 }
             }
         };
@@ -1619,12 +1623,12 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
                 acc_re[t][e] = 0.f;
                 acc_im[t][e] = 0.f;
             }
-        auto consume = [&](const unsigned char *buf) {
+        auto consume = [&](const unsigned char *buf) __attribute__((always_inline)) {
             switch (nrt) {
-                case 4: consume_pairs_b3<L, 4>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
-                case 3: consume_pairs_b3<L, 3>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
-                case 2: consume_pairs_b3<L, 2>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
-                case 1: consume_pairs_b3<L, 1>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
+                case 4: consume_pairs_b3<L, 4>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im); break;
+                case 3: consume_pairs_b3<L, 3>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im); break;
+                case 2: consume_pairs_b3<L, 2>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im); break;
+                case 1: consume_pairs_b3<L, 1>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im); break;
                 default: break;
             }
         };
