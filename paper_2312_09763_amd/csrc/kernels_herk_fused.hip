@@ -543,6 +543,7 @@ struct RowGeom {
 typedef RowGeom<FL<PB3>::RS, FL<PB3>::PLANEB, kKC / 16> GeomPair;  // 32 complex per stage
 typedef RowGeom<16 * 4 * 2 + 16, 16 * 4, 1> GeomCoh;               // 16 complex per stage
 typedef RowGeom<16 * 4 * 2 + 32, 16 * 4, 1> GeomCoh3;              // the same in 160-byte rows
+typedef RowGeom<FL<PB3>::RS + 16, FL<PB3>::PLANEB, kKC / 16> GeomPair3;  // 32 complex, 288-byte rows
 
 // Off-diagonal block: rows 16 (rb + i), columns 16 (cb + j), i < NR, j < NC
 // (4 x 4 tiles, or 3 x 3 on a short diagonal block); tile (i, j) accumulates
@@ -1702,12 +1703,14 @@ struct SclSrc {
 
 // SPS_: sources per stage, 16 or (BF16X3, the default there) 32: a deeper
 // stage halves the barriers and the per-stage operand loads per source (3-5 %
-// on the 350-antenna diffuse sky), the LDS holds 139 KB; the MFMAs accumulate
+// on the 350-antenna diffuse sky), the LDS holds 147 KB; the MFMAs accumulate
 // in the same source order either way.
 template <int PREC, int SQ_ROWS = 96, int SPS_ = 16>
 __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
     static_assert(SPS_ == 16 || (SPS_ == 32 && PREC == PB3), "16 sources per stage, or 32 on BF16X3");
-    typedef typename std::conditional<SPS_ == 32, GeomPair, GeomCoh>::type L;
+    // 288- and 160-byte rows on BF16X3 (conflict-free operand reads), 144 on FP32
+    typedef typename std::conditional<SPS_ == 32, GeomPair3,
+                                      typename std::conditional<PREC == PB3, GeomCoh3, GeomCoh>::type>::type L;
     constexpr int RS = L::RS;
     constexpr int SPS = SPS_;
     constexpr int RSTEP = 512 / SPS;  // rows between a thread's rows
@@ -1733,8 +1736,9 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int mp = tid % (SPS / 2);
     // 16-source stages: 8 threads per row, rows permuted as in the two-block kernels
-    const int a0 = SPS == 16 ? (sq ? wrow(tid) : SQ_ROWS + wrow(tid - 256))
-                             : (sq ? tid / (SPS / 2) : SQ_ROWS + (tid - 256) / (SPS / 2));
+    const int a0 = SPS == 32    ? (sq ? tid / (SPS / 2) : SQ_ROWS + (tid - 256) / (SPS / 2))
+                   : PREC == PB3 ? (sq ? wrow160(tid) : SQ_ROWS + wrow160(tid - 256))
+                                 : (sq ? wrow(tid) : SQ_ROWS + wrow(tid - 256));
     const int sq_r0 = 4 * (wave >> 1), sq_c0 = 4 * (wave & 1);
     const int tri_s = (wave - 4) & 3;
 
