@@ -553,15 +553,16 @@ __device__ __forceinline__ void consume_sq_b3(const unsigned char *buf, int rb, 
                                               f32x4 (&re)[NACC], f32x4 (&im)[NACC]) {
 #pragma unroll
     for (int ks = 0; ks < L::NKS; ks++) {
+        // loads in the order of first use: hi rows, the first column, lo rows
         u32x4 ah[NR], al[NR];
 #pragma unroll
-        for (int i = 0; i < NR; i++) {
-            const unsigned char *p = buf + (16 * (rb + i) + l16) * L::RS + ks * 64 + lk * 16;
-            ah[i] = *(const u32x4 *)p;
-            al[i] = *(const u32x4 *)(p + L::PLANEB);
-        }
+        for (int i = 0; i < NR; i++) ah[i] = *(const u32x4 *)(buf + (16 * (rb + i) + l16) * L::RS + ks * 64 + lk * 16);
         const unsigned char *pc = buf + (16 * cb + l16) * L::RS + ks * 64 + lk * 16;
         u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
+#pragma unroll
+        for (int i = 0; i < NR; i++)
+            al[i] = *(const u32x4 *)(buf + (16 * (rb + i) + l16) * L::RS + ks * 64 + lk * 16 + L::PLANEB);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 0; j < NC; j++) {
             const u32x4 bh = nh, bl = nl;
@@ -1430,15 +1431,15 @@ struct PairSrc {
 template <typename L, int NR>
 __device__ __forceinline__ void consume_pairs_b3(const unsigned char *buf, int rb, int cb, int l16, int lk,
                                                  f32x4 (&re)[16], f32x4 (&im)[16]) {
+    // loads in the order of first use: hi rows, the first column, lo rows
     u32x4 ah[NR], al[NR];
 #pragma unroll
-    for (int i = 0; i < NR; i++) {
-        const unsigned char *p = buf + (16 * (rb + i) + l16) * L::RS + lk * 16;
-        ah[i] = *(const u32x4 *)p;
-        al[i] = *(const u32x4 *)(p + L::PLANEB);
-    }
+    for (int i = 0; i < NR; i++) ah[i] = *(const u32x4 *)(buf + (16 * (rb + i) + l16) * L::RS + lk * 16);
     const unsigned char *pc = buf + (16 * cb + l16) * L::RS + lk * 16;
     u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
+#pragma unroll
+    for (int i = 0; i < NR; i++) al[i] = *(const u32x4 *)(buf + (16 * (rb + i) + l16) * L::RS + lk * 16 + L::PLANEB);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < kTI; j++) {
         const u32x4 bh = nh, bl = nl;
