@@ -17,7 +17,9 @@
 //   batch_time  times per device batch: the default and 1, 2, 4, 8;
 //   unfused     Z formed inside the product or written to device memory.
 // 0 is always a candidate (the library's own choice), so the result is never
-// slower than the defaults as timed.  Each candidate: a context, one call that
+// slower than the defaults as timed, and a value replaces the axis's current
+// one only when it is more than 0.5 % faster (about the spread of a two-call
+// timing), so near-ties keep the defaults.  Each candidate: a context, one call that
 // captures and warms the graph, two timed replays (HIP events).  Candidates
 // that do not fit in device memory are skipped.  Winners are cached in a JSON
 // file, one entry per line, keyed by what decides the product kernel and its
@@ -228,12 +230,15 @@ extern "C" matvis_status matvis_autotune(const matvis_config *base, const double
         {&tbs, [](matvis_config &c, long long v) { c.batch_time = (int32_t)v; }},
         {&fuse, [](matvis_config &c, long long v) { c.flags = (c.flags & ~(MATVIS_FLAG_UNFUSED | MATVIS_FLAG_NO_GRAPH)) | (int32_t)v; }},
     };
+    // a candidate replaces the current choice only when it is faster by more than
+    // the run-to-run spread of a two-call timing (~0.5 %), so ties keep the defaults
+    constexpr double kMargin = 0.995;
     for (const Axis &ax : axes)
         for (long long v : *ax.vals) {
             matvis_config c = cur;
             ax.set(c, v);
             const double ms = time_cfg(c);
-            if (ms < cur_ms) {
+            if (ms < cur_ms * kMargin) {
                 cur_ms = ms;
                 cur = c;
             }
