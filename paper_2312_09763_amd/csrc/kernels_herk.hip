@@ -36,15 +36,15 @@ template <int PREC>
 struct HT;
 template <>
 struct HT<P32> {
-    static constexpr int ST = 128, WT = 64, KC = 16, EB = 8, PLANES = 1;
+    static constexpr int ST = 128, KC = 16, EB = 8, PLANES = 1;
 };
 template <>
 struct HT<P64> {
-    static constexpr int ST = 64, WT = 32, KC = 16, EB = 16, PLANES = 1;
+    static constexpr int ST = 64, KC = 16, EB = 16, PLANES = 1;
 };
 template <>
 struct HT<PB3> {
-    static constexpr int ST = 128, WT = 64, KC = 16, EB = 4, PLANES = 2;
+    static constexpr int ST = 128, KC = 16, EB = 4, PLANES = 2;
 };
 
 // Stage geometry of a square ST_ tile computed by four waves (2 x 2 wave tiles).
