@@ -1406,50 +1406,61 @@ __global__ void __launch_bounds__(512, 1) k_herk_coh(FusedArgs a) {
 // with w = C_00, C_11 (kind X: V^00_IJ, V^11_IJ), or w = C_10 and conj C_10
 // (kind Y: V^10_IJ, and V^01_IJ = the Hermitian partner of V^10_JI).  So the
 // columns of both products of an item are the unweighted fringe rows F_J, formed
-// and split once, and only the rows carry the weights.  A stage holds three
-// planes of 128 rows x 16 sources, w0 F_I, w1 F_I and F_J, in 160-byte rows
-// (conflict-free 16-byte operand reads; a fourth plane of F_J rotated for the
-// imaginary parts, which would save the rotation in the multiply loop, does not
-// fit two stages of 160-byte rows in the LDS and was slower at 144 bytes).
-// Against k_herk_coh<PREC, true> (both operands weighted by square roots of the
-// coherency) that is a quarter fewer rows to scale and split per stage.
+// and split once, and only the rows carry the weights.  A stage holds four
+// planes of 128 rows x 16 sources: w0 F_I, w1 F_I, F_J, and F_J rotated,
+// (re, im) -> (-im, re), for the imaginary parts, written at forming time so the
+// multiply loop runs its MFMAs on LDS operands with no vector work on them.
+// Rows are 160 bytes (conflict-free 16-byte operand reads), so two stages fill
+// the 160 KB of LDS; the antenna table and the per-source weights live in the
+// 32 unused bytes at the end of rows, which the forming never writes and the
+// multiply never reads.  Against k_herk_coh<PREC, true> (both operands weighted
+// by square roots of the coherency) that is a quarter fewer rows to scale and
+// split per stage.
 //
 // Waves s and s + 4 share SIMD s: wave s takes product 0 and row half s >> 1 of
 // the 128 x 128 block, wave s + 4 product 1 and the other row half, both column
 // half s & 1 (16 tiles of 16 x 16 each).  When block I is the last, short block,
-// tile rows past its antennas are neither formed nor multiplied, and every
-// SIMD keeps one wave of each row half, so the saving is shared evenly.
+// tile rows past its antennas are neither formed nor multiplied, and its row
+// tiles are split evenly between the halves (3 + 3 for 94 antennas), so the two
+// waves of a SIMD still carry equal products and their multiply and forming
+// phases keep overlapping; an uneven split (4 + 2) leaves the lighter wave
+// idle at every barrier.
 // ---------------------------------------------------------------------------
+// Per-source direction and the item's two weights: (C_00, C_11) for kind X,
+// (Re, Im) of C_10 for kind Y, with C_pq = sum_k B_pk conj(B_qk) (0 past the split)
 struct PairSrc {
-    double x, y, z;   // s_hat
-    float c00, c11;   // coherency through the beam, C_pq = sum_k B_pk conj(B_qk)
-    float c10x, c10y; // (all four 0 past the split)
+    double x, y, z;  // s_hat
+    float w0, w1;
 };
 
-// Rows 16 (rb + i), i < NR, of one plane against columns 16 (cb + j), j < 4:
-// re += a b, im += a rot(b) for the hi / lo terms, rot(b) formed in registers.
+// Rows 16 (rb + i), i < NR, of one plane against columns 16 (cb + j) and their
+// rotations 16 (wb + j), j < 4: re += a b, im += a rot(b) for the hi / lo terms.
 template <typename L, int NR>
-__device__ __forceinline__ void consume_pairs_b3(const unsigned char *buf, int rb, int cb, int l16, int lk,
+__device__ __forceinline__ void consume_pairs_b3(const unsigned char *buf, int rb, int cb, int wb, int l16, int lk,
                                                  f32x4 (&re)[16], f32x4 (&im)[16]) {
-    // loads in the order of first use: hi rows, the first column, lo rows
+    // loads in the order of first use: hi rows, the first column's hi terms, lo
+    // terms, lo rows
     u32x4 ah[NR], al[NR];
 #pragma unroll
     for (int i = 0; i < NR; i++) ah[i] = *(const u32x4 *)(buf + (16 * (rb + i) + l16) * L::RS + lk * 16);
     const unsigned char *pc = buf + (16 * cb + l16) * L::RS + lk * 16;
-    u32x4 nh = *(const u32x4 *)pc, nl = *(const u32x4 *)(pc + L::PLANEB);
+    const unsigned char *pw = buf + (16 * wb + l16) * L::RS + lk * 16;
+    u32x4 nh = *(const u32x4 *)pc, mh = *(const u32x4 *)pw;
+    u32x4 nl = *(const u32x4 *)(pc + L::PLANEB), ml = *(const u32x4 *)(pw + L::PLANEB);
 #pragma unroll
     for (int i = 0; i < NR; i++) al[i] = *(const u32x4 *)(buf + (16 * (rb + i) + l16) * L::RS + lk * 16 + L::PLANEB);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < kTI; j++) {
-        const u32x4 bh = nh, bl = nl;
+        const u32x4 bh = nh, bl = nl, wh = mh, wl = ml;
         if (j + 1 < kTI) {
-            const unsigned char *q = pc + 16 * (j + 1) * L::RS;
+            const unsigned char *q = pc + 16 * (j + 1) * L::RS, *r = pw + 16 * (j + 1) * L::RS;
             nh = *(const u32x4 *)q;
+            mh = *(const u32x4 *)r;
             nl = *(const u32x4 *)(q + L::PLANEB);
+            ml = *(const u32x4 *)(r + L::PLANEB);
         }
         __builtin_amdgcn_sched_barrier(0);
-        const u32x4 wh = bf16_rot_col(bh), wl = bf16_rot_col(bl);
 #pragma unroll
         for (int i = 0; i < NR; i++) mfma_pair(ah[i], bh, wh, re[i * kTI + j], im[i * kTI + j]);
 #pragma unroll
@@ -1464,10 +1475,15 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
     typedef GeomCoh3 L;
     constexpr int RS = L::RS;
     constexpr int SPS = 16;         // sources per stage
-    constexpr int BUF = 3 * kST * RS;
+    constexpr int BUF = 4 * kST * RS;
+    constexpr int PAD = 2 * L::PLANEB;  // the unused end of a row
+    static_assert(2 * BUF <= 160 * 1024, "two stages exceed the LDS");
+    static_assert(sizeof(AntEntry) <= RS - PAD && sizeof(PairSrc) <= RS - PAD, "row padding too small");
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
-    __shared__ AntEntry tab[2 * kST];
-    __shared__ PairSrc src[2][SPS];
+    // antenna entry as (of the 256 of blocks I, J) at the end of row as of stage 0;
+    // the sources of stage parity st at the end of rows 16 st + m of stage 1
+    auto tab = [&](int as) -> AntEntry & { return *(AntEntry *)(lds + as * RS + PAD); };
+    auto src = [&](int st, int m) -> PairSrc & { return *(PairSrc *)(lds + BUF + (SPS * st + m) * RS + PAD); };
 
     const int tid = threadIdx.x;
     const int lane = lane_id();
@@ -1480,10 +1496,10 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
     const int per_xcd = a.grid / 8;
     const int slot_x = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int mp = tid % (SPS / 2);   // source pair 2 mp, 2 mp + 1
-    const int a0 = wrow160(tid);      // antennas a0 + 64 k of the 256 of blocks I (k < 2) and J
     const int simd = wave & 3, pr = wave >> 2;
     const int rh = (simd >> 1) ^ pr, ch = simd & 1;
-    const int o_rb = pr * 8 + 4 * rh, o_cb = 2 * 8 + 4 * ch;
+    const int a0 = wrow160(tid);      // antennas a0 + 64 k of the 256 of blocks I (k < 2) and J
+    const int o_cb = 2 * 8 + 4 * ch, o_wb = 3 * 8 + 4 * ch;
     const bool mult_first = wave < 4;
 
     for (int item = slot_x; item < total; item += a.grid) {
@@ -1507,8 +1523,11 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
         }
         const int J = q;
         const int n_i = a.n_ant - I * kST < kST ? a.n_ant - I * kST : kST;  // antennas of block I
-        int nrt = (n_i + 15) / 16 - 4 * rh;                              // this wave's row tiles
-        nrt = nrt < 0 ? 0 : nrt > kTI ? kTI : nrt;
+        // row tiles of block I (8, or fewer on the short last block), split evenly
+        // between the row halves so the two waves of a SIMD multiply alike
+        const int nt = (n_i + 15) / 16, nt0 = (nt + 1) / 2;
+        const int r0 = rh ? nt0 : 0, nrt = rh ? nt - nt0 : nt0;  // this wave's first tile and count
+        const int o_rb = pr * 8 + r0;
         const int tslot = inst / a.nfb;
         const int f = a.f0 + inst % a.nfb;
         const int64_t M = a.count[tslot];
@@ -1534,7 +1553,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
                     e.b = -1;
                 }
                 e.pad = 0;
-                tab[as] = e;
+                tab(as) = e;
             }
         }
 
@@ -1555,32 +1574,35 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
                 for (int c = 0; c < 4; c++) fb[c] = Bm[(int64_t)c * a.ld_src + m];
             }
         };
-        auto stash = [&](int stage) {
-            PairSrc &e = src[stage & 1][tid];
+        auto stash = [&](int stage, bool ky) {
+            PairSrc &e = src(stage & 1, tid);
             e.x = fx;
             e.y = fy;
             e.z = fz;
             // B components c = 2 p + k; C_10 = B_10 conj(B_00) + B_11 conj(B_01)
-            e.c00 = fb[0].x * fb[0].x + fb[0].y * fb[0].y + fb[1].x * fb[1].x + fb[1].y * fb[1].y;
-            e.c11 = fb[2].x * fb[2].x + fb[2].y * fb[2].y + fb[3].x * fb[3].x + fb[3].y * fb[3].y;
-            e.c10x = fb[2].x * fb[0].x + fb[2].y * fb[0].y + fb[3].x * fb[1].x + fb[3].y * fb[1].y;
-            e.c10y = fb[2].y * fb[0].x - fb[2].x * fb[0].y + fb[3].y * fb[1].x - fb[3].x * fb[1].y;
+            if (ky) {
+                e.w0 = fb[2].x * fb[0].x + fb[2].y * fb[0].y + fb[3].x * fb[1].x + fb[3].y * fb[1].y;
+                e.w1 = fb[2].y * fb[0].x - fb[2].x * fb[0].y + fb[3].y * fb[1].x - fb[3].x * fb[1].y;
+            } else {
+                e.w0 = fb[0].x * fb[0].x + fb[0].y * fb[0].y + fb[1].x * fb[1].x + fb[1].y * fb[1].y;
+                e.w1 = fb[2].x * fb[2].x + fb[2].y * fb[2].y + fb[3].x * fb[3].x + fb[3].y * fb[3].y;
+            }
         };
-        // Weighted rows of block I (planes 0, 1) or plain rows of block J (plane 2)
-        // for this thread's two sources.  Rows of block I past its
+        // Weighted rows of block I (planes 0, 1) or plain and rotated rows of block
+        // J (planes 2, 3) for this thread's two sources.  Rows of block I past its
         // antennas are skipped (never multiplied); a source past the split has zero
         // weights, and its J rows only meet zero-weighted I rows.
         auto produce = [&](unsigned char *buf, int stage, auto ky) {
             constexpr bool KY = decltype(ky)::value;
             PairSrc w[2];
-            w[0] = src[stage & 1][2 * mp];
-            w[1] = src[stage & 1][2 * mp + 1];
+            w[0] = src(stage & 1, 2 * mp);
+            w[1] = src(stage & 1, 2 * mp + 1);
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 const int as = a0 + 64 * k;
                 const bool in_i = k < 2;
                 if (in_i && as >= n_i) continue;
-                const AntEntry e = tab[as];
+                const AntEntry e = tab(as);
                 float fr[2], fi[2];
 #pragma unroll
                 for (int qq = 0; qq < 2; qq++) {
@@ -1594,12 +1616,12 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
 #pragma unroll
                     for (int qq = 0; qq < 2; qq++) {
                         if constexpr (KY) {  // w0 = C_10, w1 = conj C_10
-                            const float cx = w[qq].c10x, cy = w[qq].c10y;
+                            const float cx = w[qq].w0, cy = w[qq].w1;
                             split2(cx * fr[qq] - cy * fi[qq], cx * fi[qq] + cy * fr[qq], h0[qq], l0[qq]);
                             split2(cx * fr[qq] + cy * fi[qq], cx * fi[qq] - cy * fr[qq], h1[qq], l1[qq]);
                         } else {  // w0 = C_00, w1 = C_11
-                            split2(w[qq].c00 * fr[qq], w[qq].c00 * fi[qq], h0[qq], l0[qq]);
-                            split2(w[qq].c11 * fr[qq], w[qq].c11 * fi[qq], h1[qq], l1[qq]);
+                            split2(w[qq].w0 * fr[qq], w[qq].w0 * fi[qq], h0[qq], l0[qq]);
+                            split2(w[qq].w1 * fr[qq], w[qq].w1 * fi[qq], h1[qq], l1[qq]);
                         }
                     }
                     unsigned char *r0 = buf + as * RS + mp * 8, *r1 = buf + (kST + as) * RS + mp * 8;
@@ -1612,9 +1634,14 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
 #pragma unroll
                     for (int qq = 0; qq < 2; qq++) split2(fr[qq], fi[qq], h[qq], l[qq]);
                     const int rj = as - kST;  // row of block J
-                    unsigned char *r2 = buf + (2 * kST + rj) * RS + mp * 8;
+                    unsigned char *r2 = buf + (2 * kST + rj) * RS + mp * 8, *r3 = buf + (3 * kST + rj) * RS + mp * 8;
                     *(uint2 *)r2 = make_uint2(h[0], h[1]);
                     *(uint2 *)(r2 + L::PLANEB) = make_uint2(l[0], l[1]);
+                    // (re, im) -> (-im, re) on each bf16 pair: swap the halves, negate the low one
+                    *(uint2 *)r3 = make_uint2(__builtin_amdgcn_alignbit(h[0], h[0], 16) ^ 0x00008000u,
+                                              __builtin_amdgcn_alignbit(h[1], h[1], 16) ^ 0x00008000u);
+                    *(uint2 *)(r3 + L::PLANEB) = make_uint2(__builtin_amdgcn_alignbit(l[0], l[0], 16) ^ 0x00008000u,
+                                                            __builtin_amdgcn_alignbit(l[1], l[1], 16) ^ 0x00008000u);
                 }
             }
         };
@@ -1627,19 +1654,19 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
             }
         auto consume = [&](const unsigned char *buf) __attribute__((always_inline)) {
             switch (nrt) {
-                case 4: consume_pairs_b3<L, 4>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im); break;
-                case 3: consume_pairs_b3<L, 3>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im); break;
-                case 2: consume_pairs_b3<L, 2>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im); break;
-                case 1: consume_pairs_b3<L, 1>(buf, o_rb, o_cb, l16, lk, acc_re, acc_im); break;
+                case 4: consume_pairs_b3<L, 4>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
+                case 3: consume_pairs_b3<L, 3>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
+                case 2: consume_pairs_b3<L, 2>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
+                case 1: consume_pairs_b3<L, 1>(buf, o_rb, o_cb, o_wb, l16, lk, acc_re, acc_im); break;
                 default: break;
             }
         };
         auto run = [&](auto ky) {
             if (fetcher) {
                 fetch(0);
-                stash(0);
+                stash(0, decltype(ky)::value);
                 fetch(1);
-                stash(1);
+                stash(1, decltype(ky)::value);
             }
             __syncthreads();  // antenna table and the first two stages' sources ready
             produce(lds, 0, ky);
@@ -1652,8 +1679,8 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
                 if (mult_first) consume(cur);
                 if (more) produce(nxt, stg + 1, ky);
                 if (!mult_first) consume(cur);
-                // src[stg & 1] was last read by the producers of stage stg (one stage ago)
-                if (fetcher && stg + 2 < n_stage) stash(stg + 2);
+                // the sources of parity stg & 1 were last read by the producers of stage stg
+                if (fetcher && stg + 2 < n_stage) stash(stg + 2, decltype(ky)::value);
                 __syncthreads();
             }
         };
@@ -1675,7 +1702,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_pairs(FusedArgs a) {
             for (int j = 0; j < kTI; j++)
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    const int A = I * kST + 16 * (4 * rh + i) + 4 * lk + e, Bc = J * kST + 16 * (4 * ch + j) + l16;
+                    const int A = I * kST + 16 * (r0 + i) + 4 * lk + e, Bc = J * kST + 16 * (4 * ch + j) + l16;
                     if (i >= nrt || A >= a.n_ant || Bc >= a.n_ant) continue;
                     P[(int64_t)(2 * A + row_off) * ld + 2 * Bc + col_off] =
                         make_float2(acc_re[i * kTI + j][e], acc_im[i * kTI + j][e]);
