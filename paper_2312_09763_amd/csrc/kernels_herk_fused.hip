@@ -623,6 +623,27 @@ struct TriPair {
     }
 };
 
+// A tile set passed as a value (to pick a set at run time among instantiations)
+template <typename T>
+struct SetTag {
+    typedef T type;
+};
+
+// Row S alone of a two-row set, when row 7 - S lies wholly past the antennas of
+// a short last block (its tiles are neither multiplied nor stored).
+template <int S>
+struct TriSingle {
+    static constexpr int NR = 1;
+    static constexpr int r[1] = {S};
+    static constexpr int base[1] = {0};
+    static constexpr int ncol = S + 1;
+    static constexpr int order[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+    static constexpr int slot(int c) { return c == r[0] ? 0 : -1; }
+    static constexpr int next_loaded(int p) {
+        return p >= ncol ? -1 : slot(order[p]) < 0 ? p : next_loaded(p + 1);
+    }
+};
+
 // Row sets of the triangle waves on a short diagonal block of at most 96
 // antennas (six tile rows): {5, 0, 3} (eleven tiles) and {4, 1, 2} (ten).
 template <int S>
@@ -1767,7 +1788,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
     const int a0 = SPS == 32    ? (sq ? tid / (SPS / 2) : SQ_ROWS + (tid - 256) / (SPS / 2))
                    : PREC == PB3 ? (sq ? wrow160(tid) : SQ_ROWS + wrow160(tid - 256))
                                  : (sq ? wrow(tid) : SQ_ROWS + wrow(tid - 256));
-    const int sq_r0 = 4 * (wave >> 1), sq_c0 = 4 * (wave & 1);
+    const int sq_c0 = 4 * (wave & 1);
     const int tri_s = (wave - 4) & 3;
 
     for (int item = slot_x; item < total; item += a.grid) {
@@ -1785,6 +1806,15 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
         const int kind = local % n_kind;
         const int R = kind == 0 ? 1 : 2, C = kind == 1 ? 1 : 0, T = kind;
         const int tri_o = (T == C ? 0 : 1) * kST;
+        // Only the last block (2) can be short.  Its rows past the antennas are not
+        // formed; the square waves split its row tiles evenly (waves 0, 1 the first
+        // half, 2, 3 the rest), and a triangle wave drops the rows of its set that
+        // lie wholly past them.
+        const int n_r = a.n_ant - R * kST < kST ? a.n_ant - R * kST : kST;
+        const int n_t = a.n_ant - T * kST < kST ? a.n_ant - T * kST : kST;
+        const int nt_r = (n_r + 15) / 16, nt0 = (nt_r + 1) / 2, nt_t = (n_t + 15) / 16;
+        const int sq_r0 = (wave >> 1) ? nt0 : 0, sq_nr = (wave >> 1) ? nt_r - nt0 : nt0;
+        const int tri_nr = 7 - tri_s < nt_t ? 2 : tri_s < nt_t ? 1 : 0;
         const int tslot = inst / a.nfb;
         const int f = a.f0 + inst % a.nfb;
         const int64_t M = a.count[tslot];
@@ -1838,8 +1868,9 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
             e.pad = 0.f;
         };
         // rows a0 + RSTEP k (plane row >> 7) of this thread's two sources; rows of
-        // padding antennas (u = 0) only reach outputs that are never stored
-        auto produce_n = [&](unsigned char *buf, int stage, auto na) {
+        // block R past its antennas are skipped (never multiplied, or only into
+        // outputs that are never stored)
+        auto produce_n = [&](unsigned char *buf, int stage, auto na) __attribute__((always_inline)) {
             constexpr int NA = decltype(na)::value;
             SclSrc w[2];
             w[0] = src[stage & 1][2 * mp];
@@ -1847,6 +1878,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
 #pragma unroll
             for (int k = 0; k < NA; k++) {
                 const int as = a0 + RSTEP * k;
+                if (as >= kST + n_r) continue;
                 const AntEntry e = tab[as];
                 float vr[2], vi[2];
 #pragma unroll
@@ -1869,7 +1901,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
                 }
             }
         };
-        auto produce = [&](unsigned char *buf, int stage) {
+        auto produce = [&](unsigned char *buf, int stage) __attribute__((always_inline)) {
             if (sq)
                 produce_n(buf, stage, std::integral_constant<int, SQ_ROWS / RSTEP>{});
             else
@@ -1882,29 +1914,43 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
                 acc_re[t][e] = 0.f;
                 acc_im[t][e] = 0.f;
             }
-        auto consume = [&](const unsigned char *buf) {
-            if constexpr (PREC == PB3) {
-                if (sq)
-                    consume_sq_b3<L>(buf, 8 + sq_r0, sq_c0, l16, lk, acc_re, acc_im);
-                else if (tri_s == 0)
-                    consume_tri_b3<L, TriPair<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
-                else if (tri_s == 1)
-                    consume_tri_b3<L, TriPair<1>>(buf, tri_o, l16, lk, acc_re, acc_im);
-                else if (tri_s == 2)
-                    consume_tri_b3<L, TriPair<2>>(buf, tri_o, l16, lk, acc_re, acc_im);
-                else
-                    consume_tri_b3<L, TriPair<3>>(buf, tri_o, l16, lk, acc_re, acc_im);
-            } else {
-                if (sq)
-                    consume_sq_f32<L>(buf, 8 + sq_r0, sq_c0, l16, lk, acc_re, acc_im);
-                else if (tri_s == 0)
-                    consume_tri_f32<L, TriPair<0>>(buf, tri_o, l16, lk, acc_re, acc_im);
-                else if (tri_s == 1)
-                    consume_tri_f32<L, TriPair<1>>(buf, tri_o, l16, lk, acc_re, acc_im);
-                else if (tri_s == 2)
-                    consume_tri_f32<L, TriPair<2>>(buf, tri_o, l16, lk, acc_re, acc_im);
-                else
-                    consume_tri_f32<L, TriPair<3>>(buf, tri_o, l16, lk, acc_re, acc_im);
+        auto sq_n = [&](const unsigned char *buf, auto nr) __attribute__((always_inline)) {
+            constexpr int NR = decltype(nr)::value;
+            if constexpr (PREC == PB3)
+                consume_sq_b3<L, 16, NR, kTI>(buf, 8 + sq_r0, sq_c0, l16, lk, acc_re, acc_im);
+            else
+                consume_sq_f32<L, 16, NR, kTI>(buf, 8 + sq_r0, sq_c0, l16, lk, acc_re, acc_im);
+        };
+        auto tri_n = [&](const unsigned char *buf, auto set) __attribute__((always_inline)) {
+            typedef typename decltype(set)::type TS;
+            if constexpr (PREC == PB3)
+                consume_tri_b3<L, TS>(buf, tri_o, l16, lk, acc_re, acc_im);
+            else
+                consume_tri_f32<L, TS>(buf, tri_o, l16, lk, acc_re, acc_im);
+        };
+        auto consume = [&](const unsigned char *buf) __attribute__((always_inline)) {
+            if (sq) {
+                switch (sq_nr) {
+                    case 4: sq_n(buf, std::integral_constant<int, 4>{}); break;
+                    case 3: sq_n(buf, std::integral_constant<int, 3>{}); break;
+                    case 2: sq_n(buf, std::integral_constant<int, 2>{}); break;
+                    case 1: sq_n(buf, std::integral_constant<int, 1>{}); break;
+                    default: break;
+                }
+            } else if (tri_nr == 2) {
+                switch (tri_s) {
+                    case 0: tri_n(buf, SetTag<TriPair<0>>{}); break;
+                    case 1: tri_n(buf, SetTag<TriPair<1>>{}); break;
+                    case 2: tri_n(buf, SetTag<TriPair<2>>{}); break;
+                    default: tri_n(buf, SetTag<TriPair<3>>{}); break;
+                }
+            } else if (tri_nr == 1) {
+                switch (tri_s) {
+                    case 0: tri_n(buf, SetTag<TriSingle<0>>{}); break;
+                    case 1: tri_n(buf, SetTag<TriSingle<1>>{}); break;
+                    case 2: tri_n(buf, SetTag<TriSingle<2>>{}); break;
+                    default: tri_n(buf, SetTag<TriSingle<3>>{}); break;
+                }
             }
         };
 
@@ -1941,7 +1987,7 @@ __global__ void __launch_bounds__(512, 1) k_herk_blk3(FusedArgs a) {
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
                         const int A = R * kST + 16 * (sq_r0 + i) + 4 * lk + e, Bc = C * kST + 16 * (sq_c0 + j) + l16;
-                        if (A < a.n_ant && Bc < a.n_ant)
+                        if (i < sq_nr && A < a.n_ant && Bc < a.n_ant)
                             P[(int64_t)A * ld + Bc] = make_float2(acc_re[i * kTI + j][e], acc_im[i * kTI + j][e]);
                     }
         } else {
