@@ -240,3 +240,26 @@ def test_each_product_path_matches_oracle(orc, case):
     # hundred visible sources, so the per-element split error averages down less
     tol = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 3e-5}[prec]
     assert ef <= tol and ec <= tol
+
+
+@pytest.mark.parametrize("path,n_ant", [("sources", 276), ("sources", 316), ("sources", 356),
+                                        ("fused_blocks", 276), ("fused_blocks", 336), ("fused_blocks", 356)])
+def test_short_last_block(orc, path, n_ant):
+    """A short last antenna block of each size class on the two kernels that cut it: the
+    block-pair kernel splits its row tiles between the row halves (1 + 1, 2 + 2 and 4 + 3 for
+    20, 60 and 100 antennas), and the three-block scalar kernel skips its padding rows and cuts
+    its triangle row sets to the rows that hold antennas (one-row sets, or none, at 2, 5 and 7
+    tile rows)."""
+    wl = synth.workload(2 if path == "sources" else 1, n_ant=n_ant, n_src=400, n_time=1, n_freq=2)
+    say(f"short last block: {path}, {n_ant} antennas ({n_ant - 256} in the last block)")
+    d = mv.device_inputs(wl, "bf16x3")
+    with mv.Context(mv.config_for(wl, "bf16x3")) as ctx:
+        assert ctx.product_path == path
+        V = ctx.simulate(**d).cpu().numpy().astype(np.complex128)
+        ctx.finish()
+    V = V.reshape((-1,) + V.shape[2:])
+    ref = orc.simulate(wl.antpos, wl.freqs, wl.lsts, wl.ra, wl.dec, wl.flux, grid_as_used(wl, "bf16x3"), wl.latitude,
+                       wl.dza, wl.daz, wl.interp)
+    ef, ec = errors(V, ref)
+    say(f"  err_F={ef:.3e} err_CS={ec:.3e}")
+    assert ef <= 3e-5 and ec <= 3e-5
